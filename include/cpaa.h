@@ -1,0 +1,197 @@
+/*
+ * cpaa.h - C ABI of the MI355X (gfx950) implementation of the Chebyshev
+ * Polynomial Approximation Algorithm (CPAA) for PageRank on undirected graphs
+ * (Zhang, Tang, Yao, Zhang, "A Parallel PageRank Algorithm For Undirected
+ * Graph", arXiv 2112.01743).
+ *
+ * What is computed (Sec. 2.1, Sec. 3 eq. 3.1, Sec. 4.1 Alg. 1):
+ *   P = A D^{-1} is the random-walk matrix of an undirected graph (A the 0/1
+ *   symmetric adjacency pattern, D the degrees), c in (0,1) the damping
+ *   factor, p a personalization vector.  PageRank is
+ *       pi = (1 - c) (I - cP)^{-1} p.
+ *   CPAA approximates (I - cP)^{-1} b, b = (1-c) p, by the truncated Chebyshev
+ *   series of f(x) = 1/(1 - cx):
+ *       x_M = (c_0/2) b + sum_{k=1..M} c_k T_k(P) b,    c_k = 2 beta^k / sqrt(1-c^2),
+ *   with T_{k+1}(P)b = 2 P T_k(P)b - T_{k-1}(P)b (Sec. 2.2 property (3)) and
+ *   beta = (1 - sqrt(1-c^2))/c (eq. 4.1).
+ *
+ * Precision: the recurrence runs in FP32; the weighted accumulation of the
+ * series, the residual r = b - (I - cP)x and the returned vector are FP64.
+ * Every solve ends with an FP64 residual; ||r||_1/(1-c) bounds ||x - pi||_1
+ * (||(I-cP)^{-1}||_1 = 1/(1-c) for column-stochastic P).  If that bound is
+ * above the requested tolerance the library runs correction series on r
+ * (x += x_M(r)), at most cpaa_opts.max_refine times.
+ *
+ * Conventions for every entry point:
+ *   - The caller owns every buffer it passes; the library never frees or
+ *     keeps caller pointers beyond the call.  A plan owns device copies of the
+ *     graph and its own workspace.
+ *   - Functions return a cpaa_status and never throw or abort across the ABI.
+ *     On an error other than CPAA_ENOCONV the outputs are left untouched and
+ *     cpaa_last_error() describes the failure (thread-local string).
+ *   - "device pointer" means memory from hipMalloc (or a torch HIP tensor) on
+ *     the device that was current when the plan was made.
+ *   - Work is enqueued on the HIP stream passed as `stream` (NULL = default
+ *     stream); solve calls return after the results are in `x`.
+ *   - Calls that share one plan must not overlap (the plan's workspace is
+ *     reused); different plans are independent.
+ */
+#ifndef CPAA_H
+#define CPAA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CPAA_API __attribute__((visibility("default")))
+
+typedef struct cpaa_plan_s* cpaa_plan_t;
+
+typedef enum {
+  CPAA_OK = 0,
+  CPAA_EINVAL = 1,      /* bad argument: null pointer, c not in (0,1), tol <= 0, bad sizes,
+                           non-finite or negative p, p not summing to 1 */
+  CPAA_ENOTSYM = 2,     /* adjacency pattern is not symmetric (graph not undirected) */
+  CPAA_EISOLATED = 3,   /* a vertex of degree 0: P = A D^{-1} is undefined there (Sec. 2.1) */
+  CPAA_ESELFLOOP = 4,   /* a self loop */
+  CPAA_EPATTERN = 5,    /* row_ptr not monotone, column out of range, unsorted or duplicate */
+  CPAA_ENOMEM = 6,      /* device or host allocation failed */
+  CPAA_EDEVICE = 7,     /* HIP runtime error */
+  CPAA_ENOCONV = 8      /* tolerance not certified within the term / refinement caps;
+                           the best-effort x and its report are still written */
+} cpaa_status;
+
+/* Graph input: the symmetric 0/1 pattern in CSR form, int32 indices.
+ * Each undirected edge {u,v} is stored twice (u->v and v->u); columns sorted
+ * within each row; no self loops, no duplicates, no isolated vertices.
+ * Only the pattern is read: Alg. 1 uses N(u) and deg(v) (Sec. 4.1), no
+ * per-edge values. */
+typedef struct {
+  int32_t n;                 /* vertices */
+  int64_t nnz;               /* stored entries = 2|E| (the paper's m), < 2^31 */
+  const int32_t* row_ptr;    /* [n+1], row_ptr[0] = 0, row_ptr[n] = nnz */
+  const int32_t* col_idx;    /* [nnz] */
+  int32_t num_graphs;        /* 0 or 1: one graph.  > 1: block-diagonal batch of independent
+                                graphs, solved with cpaa_solve_graphs */
+  const int32_t* graph_ptr;  /* [num_graphs+1] first vertex of each graph (num_graphs > 1) */
+  int32_t on_device;         /* 1: row_ptr/col_idx/graph_ptr are device pointers, 0: host */
+} cpaa_csr;
+
+typedef struct {
+  int32_t k_max;          /* cap on terms of one series; 0 = from the a-priori bound (<= 512) */
+  int32_t max_refine;     /* FP64-residual correction series allowed (default 2) */
+  int32_t normalize;      /* 1: divide each result by its sum (Alg. 1's last step);
+                             plain solves only, changes what tol certifies (see cpaa_solve) */
+  int32_t nnz_per_thread; /* 0 auto; 4, 8 or 16: stored entries per thread of a single-vector
+                             work item (a workgroup of 256 threads takes 256*this entries and the
+                             rows they cover, so rows per wavefront = this*64/degree) */
+  int32_t tile_w;         /* 0 auto; 8, 16, 32 or 64: right-hand sides per tile in batched solves */
+  int32_t validate;       /* 1 (default): check the pattern (symmetry, loops, order) on the host */
+  int32_t io_device;      /* 1 (default): p / x0 / x of solve calls are device pointers; 0: host */
+  int32_t time_kernels;   /* 1: time every term kernel with HIP events (report.ms_terms) */
+  int32_t xcd_remap;      /* -1 auto, 0/1: map workgroups to contiguous row ranges per XCD */
+} cpaa_opts;
+
+/* Per-solve report (one per right-hand side in batched calls, one per graph in
+ * cpaa_solve_graphs). */
+typedef struct {
+  int32_t terms;          /* Chebyshev terms M of the main series */
+  int32_t refine_terms;   /* terms summed over all correction series */
+  int32_t refinements;    /* correction series run */
+  int32_t certified;      /* 1 if cert_bound <= tol */
+  int32_t fallback_used;  /* warm start rejected and a plain solve done instead */
+  int32_t pad_;
+  double cert_bound;      /* ||r||_1/(1-c) in FP64: upper bound on ||x - pi||_1 (before normalize) */
+  double resid_l1;        /* ||r||_1, r = b - (I - cP)x */
+  double resid_max;       /* ||r||_inf */
+  double mass;            /* sum_i x_i */
+  double series_cert;     /* in-loop bound of the last series (from its last two terms) */
+  double ms_total;        /* device time of the whole call (events on `stream`) */
+  double ms_terms;        /* device time inside term kernels (time_kernels = 1), whole call */
+  int64_t term_launches;  /* term kernels timed in ms_terms */
+  int64_t edges;          /* nnz x terms (main + correction) processed for this right-hand side */
+} cpaa_report;
+
+/* Plan facts, for diagnostics and benchmarks. */
+typedef struct {
+  int32_t n;
+  int64_t nnz;
+  int32_t num_graphs;
+  int32_t reordered;        /* 1 if vertices were relabelled by degree */
+  int32_t max_degree;
+  int32_t split_rows;       /* rows split across workgroups */
+  int32_t nnz_per_thread;   /* single-vector work item size / 256 */
+  int32_t work_items;       /* single-vector workgroups per term */
+  int32_t tile_w;           /* batched tile width in use */
+  int32_t k_cap_global;     /* a-priori term cap for uniform p at tol 1e-6 */
+  double c;
+  double beta;
+  double vol;               /* sum of degrees */
+} cpaa_plan_info;
+
+/* Fill *o with defaults.  Never fails. */
+CPAA_API void cpaa_default_opts(cpaa_opts* o);
+
+/* Build a plan for graph g and damping c (Sec. 2.1).  Validates the pattern
+ * (if opts->validate), computes degrees, the degree bins / workgroup map,
+ * the coefficient table c_k (Prop. 1: c_k = c_0 beta^k), and uploads the
+ * pattern to the current device.  opts may be NULL (defaults).
+ * Errors: CPAA_EINVAL, CPAA_ENOTSYM, CPAA_EISOLATED, CPAA_ESELFLOOP,
+ * CPAA_EPATTERN, CPAA_ENOMEM, CPAA_EDEVICE.  On success *out owns the plan. */
+CPAA_API cpaa_status cpaa_plan(const cpaa_csr* g, double c, const cpaa_opts* opts, cpaa_plan_t* out);
+
+/* Release every device and host resource of the plan.  NULL is ignored. */
+CPAA_API void cpaa_plan_destroy(cpaa_plan_t plan);
+
+/* Copy the plan's facts into *info. */
+CPAA_API cpaa_status cpaa_plan_info_get(cpaa_plan_t plan, cpaa_plan_info* info);
+
+/* One solve (single-graph plan).
+ *   p   : [n] FP64 personalization, p >= 0, sum p = 1 (Sec. 2.1: an
+ *         n-dimensional probability distribution).
+ *   tol : target for ||x - pi||_1, certified by the FP64 residual (> 0).
+ *   x0  : NULL for a plain solve (b = (1-c)p).  Otherwise a starting guess
+ *         [n]: the library forms r0 = (1-c)p - (I-cP)x0 in FP64 and runs CPAA
+ *         on b = r0 (x = x0 + x_M(r0)); if x0 is not finite or not better than
+ *         zero (||r0||_1 >= (1-c)||p||_1) it falls back to the plain solve and
+ *         sets report.fallback_used.
+ *   x   : [n] FP64 output, in the caller's vertex order.
+ *   rep : may be NULL.
+ * Pointers are device pointers if opts.io_device = 1, host pointers otherwise.
+ * With opts.normalize = 1 the result is divided by its sum after
+ * certification; the bound in the report refers to the unnormalized x.
+ * Returns CPAA_OK when certified, CPAA_ENOCONV when not (x still written). */
+CPAA_API cpaa_status cpaa_solve(cpaa_plan_t plan, const double* p, double tol, const double* x0,
+                       double* x, cpaa_report* rep, void* stream);
+
+/* B solves at once (single-graph plan): column j of P is P[j*ldp + i], i < n,
+ * likewise X0 (may be NULL) and X.  The right-hand sides are processed in
+ * tiles of opts.tile_w columns by one SpMM kernel per term; each tile stops
+ * when all its columns are certified (per-column in-loop certificate), and
+ * each column gets its own FP64 residual and report.
+ * reps: [B] or NULL.  ldp, ldx0, ldx >= n.  Other rules as cpaa_solve. */
+CPAA_API cpaa_status cpaa_solve_batched(cpaa_plan_t plan, int32_t B, const double* P, int64_t ldp,
+                               double tol, const double* X0, int64_t ldx0, double* X,
+                               int64_t ldx, cpaa_report* reps, void* stream);
+
+/* Block-diagonal plan (num_graphs > 1): solve every graph for its own
+ * personalization in one persistent kernel launch (one workgroup per graph at
+ * a time, vectors resident in LDS, terms per graph chosen by its own in-loop
+ * certificate), followed by the FP64 residual of every graph.
+ *   p   : [n] concatenated personalizations; the block of graph g sums to 1.
+ *   x   : [n] concatenated results.
+ *   reps: [num_graphs] or NULL.
+ * Returns CPAA_OK if every graph is certified, CPAA_ENOCONV otherwise. */
+CPAA_API cpaa_status cpaa_solve_graphs(cpaa_plan_t plan, const double* p, double tol, double* x,
+                              cpaa_report* reps, void* stream);
+
+/* Thread-local description of the last error ("" if none). */
+CPAA_API const char* cpaa_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CPAA_H */

@@ -1,0 +1,406 @@
+// Plan construction, validation and the small C entry points.
+//
+// The plan is the host-side "graph builder": it checks that the input is the
+// symmetric pattern of an undirected graph with every degree positive (the
+// setting of Sec. 2.1, where P = A D^{-1} and I - cP is invertible), computes
+// degrees and vol, cuts the CSR into workgroup work items, tabulates the
+// Chebyshev coefficients c_k = 2 beta^k / sqrt(1-c^2) (Prop. 1) and uploads
+// the pattern to the device.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace cpaa {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+namespace {
+
+template <typename T>
+cpaa_status dev_alloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T));
+  if (e != hipSuccess) {
+    *p = nullptr;
+    set_error(std::string("device allocation of ") + std::to_string(count * sizeof(T)) +
+              " bytes failed: " + hipGetErrorString(e));
+    (void)hipGetLastError();
+    return CPAA_ENOMEM;
+  }
+  return CPAA_OK;
+}
+
+template <typename T>
+cpaa_status dev_upload(T** p, const T* src, size_t count) {
+  cpaa_status s = dev_alloc(p, count);
+  if (s != CPAA_OK) return s;
+  if (count) CPAA_HIP(hipMemcpy(*p, src, count * sizeof(T), hipMemcpyHostToDevice));
+  return CPAA_OK;
+}
+
+cpaa_status validate_pattern(int32_t n, int64_t nnz, const int32_t* rp, const int32_t* ci,
+                             bool check_symmetry) {
+  if (rp[0] != 0 || static_cast<int64_t>(rp[n]) != nnz) {
+    set_error("row_ptr[0] must be 0 and row_ptr[n] must equal nnz");
+    return CPAA_EPATTERN;
+  }
+  for (int32_t u = 0; u < n; ++u) {
+    const int32_t a = rp[u], e = rp[u + 1];
+    if (e < a) {
+      set_error("row_ptr is not monotone at row " + std::to_string(u));
+      return CPAA_EPATTERN;
+    }
+    if (e == a) {
+      set_error("vertex " + std::to_string(u) + " is isolated (degree 0)");
+      return CPAA_EISOLATED;
+    }
+    int32_t last = -1;
+    for (int32_t j = a; j < e; ++j) {
+      const int32_t v = ci[j];
+      if (v < 0 || v >= n) {
+        set_error("column index out of range in row " + std::to_string(u));
+        return CPAA_EPATTERN;
+      }
+      if (v == u) {
+        set_error("self loop at vertex " + std::to_string(u));
+        return CPAA_ESELFLOOP;
+      }
+      if (v <= last) {
+        set_error("columns of row " + std::to_string(u) + " are unsorted or duplicated");
+        return CPAA_EPATTERN;
+      }
+      last = v;
+    }
+  }
+  if (!check_symmetry) return CPAA_OK;
+  // The transpose built by a counting pass over rows in increasing order has
+  // sorted rows; a symmetric pattern equals its transpose entry for entry.
+  std::vector<int64_t> cursor(rp, rp + n);
+  std::vector<int32_t> tcol(static_cast<size_t>(nnz));
+  for (int32_t u = 0; u < n; ++u) {
+    for (int32_t j = rp[u]; j < rp[u + 1]; ++j) {
+      const int32_t v = ci[j];
+      const int64_t pos = cursor[v]++;
+      if (pos >= rp[v + 1]) {
+        set_error("adjacency pattern is not symmetric (row " + std::to_string(v) +
+                  " receives more entries than it stores)");
+        return CPAA_ENOTSYM;
+      }
+      tcol[pos] = u;
+    }
+  }
+  for (int64_t j = 0; j < nnz; ++j) {
+    if (tcol[j] != ci[j]) {
+      set_error("adjacency pattern is not symmetric");
+      return CPAA_ENOTSYM;
+    }
+  }
+  return CPAA_OK;
+}
+
+// Work items of the single-vector kernels (see WorkItem).
+void build_items(int32_t n, const int32_t* rp, int npt, std::vector<WorkItem>& items,
+                 std::vector<int>& split_nchunks) {
+  const int cap = kWG * npt;
+  items.clear();
+  split_nchunks.clear();
+  int32_t r = 0;
+  while (r < n) {
+    const int d = rp[r + 1] - rp[r];
+    if (d > cap) {
+      const int slot = static_cast<int>(split_nchunks.size());
+      const int nch = (d + cap - 1) / cap;
+      for (int c = 0; c < nch; ++c) {
+        const int a = rp[r] + c * cap;
+        items.push_back({r, -(slot + 1), a, std::min(a + cap, rp[r + 1])});
+      }
+      split_nchunks.push_back(nch);
+      ++r;
+      continue;
+    }
+    const bool is_long = d > kLongRow;
+    const int32_t r0 = r;
+    int tot = 0;
+    while (r < n && (r - r0) < kWG * 4) {
+      const int dr = rp[r + 1] - rp[r];
+      if (dr > cap || (dr > kLongRow) != is_long || tot + dr > cap) break;
+      tot += dr;
+      ++r;
+    }
+    items.push_back({r0, r, rp[r0], rp[r]});
+  }
+}
+
+// Work items of the tiled kernels, one per wavefront: groups of short rows with
+// at most kTileShortNnz entries, or chunks of kTileChunkNnz entries of a row
+// longer than kTileLongDeg.
+void build_tile_items(int32_t n, const int32_t* rp, std::vector<WorkItem>& items,
+                      std::vector<int>& split_nchunks) {
+  items.clear();
+  split_nchunks.clear();
+  int32_t r = 0;
+  while (r < n) {
+    const int d = rp[r + 1] - rp[r];
+    if (d > kTileLongDeg) {
+      const int slot = static_cast<int>(split_nchunks.size());
+      const int nch = (d + kTileChunkNnz - 1) / kTileChunkNnz;
+      for (int c = 0; c < nch; ++c) {
+        const int a = rp[r] + c * kTileChunkNnz;
+        items.push_back({r, -(slot + 1), a, std::min(a + kTileChunkNnz, rp[r + 1])});
+      }
+      split_nchunks.push_back(nch);
+      ++r;
+      continue;
+    }
+    const int32_t r0 = r;
+    int tot = 0;
+    while (r < n && (r - r0) < 64) {
+      const int dr = rp[r + 1] - rp[r];
+      if (dr > kTileLongDeg || (r > r0 && tot + dr > kTileShortNnz)) break;
+      tot += dr;
+      ++r;
+    }
+    items.push_back({r0, r, rp[r0], rp[r]});
+  }
+}
+
+}  // namespace
+}  // namespace cpaa
+
+using namespace cpaa;
+
+extern "C" {
+
+const char* cpaa_last_error(void) { return g_last_error.c_str(); }
+
+void cpaa_default_opts(cpaa_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->k_max = 0;
+  o->max_refine = 2;
+  o->normalize = 0;
+  o->nnz_per_thread = 0;
+  o->tile_w = 0;
+  o->validate = 1;
+  o->io_device = 1;
+  o->time_kernels = 0;
+  o->xcd_remap = -1;
+}
+
+void cpaa_plan_destroy(cpaa_plan_t pl) {
+  if (!pl) return;
+  free_workspace(pl->ws1);
+  free_workspace(pl->wst);
+  free_workspace(pl->wsg);
+  void* ptrs[] = {pl->d_row_ptr, pl->d_col_idx, pl->d_items, pl->d_split_nchunks,
+                  pl->d_titems, pl->d_tsplit_nchunks, pl->d_graph_ptr, pl->d_graph_order,
+                  pl->d_queue};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  if (pl->ev_begin) (void)hipEventDestroy(pl->ev_begin);
+  if (pl->ev_end) (void)hipEventDestroy(pl->ev_end);
+  for (hipEvent_t e : pl->ev_terms) (void)hipEventDestroy(e);
+  delete pl;
+}
+
+cpaa_status cpaa_plan(const cpaa_csr* g, double c, const cpaa_opts* opts, cpaa_plan_t* out) {
+  set_error("");
+  if (!g || !out) {
+    set_error("cpaa_plan: null argument");
+    return CPAA_EINVAL;
+  }
+  *out = nullptr;
+  if (!(c > 0.0 && c < 1.0)) {
+    set_error("damping factor c must lie in (0, 1)");
+    return CPAA_EINVAL;
+  }
+  if (g->n <= 0 || g->nnz < 0 || g->nnz >= (int64_t(1) << 31) || !g->row_ptr ||
+      (g->nnz > 0 && !g->col_idx)) {
+    set_error("bad CSR sizes or null CSR arrays");
+    return CPAA_EINVAL;
+  }
+  cpaa_opts o;
+  cpaa_default_opts(&o);
+  if (opts) o = *opts;
+  if (o.nnz_per_thread != 0 && o.nnz_per_thread != 4 && o.nnz_per_thread != 8 &&
+      o.nnz_per_thread != 16) {
+    set_error("nnz_per_thread must be 0, 4, 8 or 16");
+    return CPAA_EINVAL;
+  }
+  if (o.tile_w != 0 && o.tile_w != 8 && o.tile_w != 16 && o.tile_w != 32 && o.tile_w != 64) {
+    set_error("tile_w must be 0, 8, 16, 32 or 64");
+    return CPAA_EINVAL;
+  }
+  if (o.k_max < 0 || o.max_refine < 0) {
+    set_error("k_max and max_refine must be >= 0");
+    return CPAA_EINVAL;
+  }
+
+  const int32_t n = g->n;
+  const int64_t nnz = g->nnz;
+  std::vector<int32_t> h_rp, h_ci, h_gp;
+  const int32_t* rp = g->row_ptr;
+  const int32_t* ci = g->col_idx;
+  const int num_graphs = g->num_graphs > 1 ? g->num_graphs : 1;
+  const int32_t* gp = g->graph_ptr;
+  if (num_graphs > 1 && !gp) {
+    set_error("num_graphs > 1 needs graph_ptr");
+    return CPAA_EINVAL;
+  }
+  if (g->on_device) {
+    h_rp.resize(n + 1);
+    h_ci.resize(static_cast<size_t>(nnz));
+    CPAA_HIP(hipMemcpy(h_rp.data(), g->row_ptr, (n + 1) * sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (nnz)
+      CPAA_HIP(hipMemcpy(h_ci.data(), g->col_idx, nnz * sizeof(int32_t), hipMemcpyDeviceToHost));
+    rp = h_rp.data();
+    ci = h_ci.data();
+    if (num_graphs > 1) {
+      h_gp.resize(num_graphs + 1);
+      CPAA_HIP(hipMemcpy(h_gp.data(), g->graph_ptr, (num_graphs + 1) * sizeof(int32_t),
+                         hipMemcpyDeviceToHost));
+      gp = h_gp.data();
+    }
+  }
+  if (o.validate) {
+    cpaa_status s = validate_pattern(n, nnz, rp, ci, true);
+    if (s != CPAA_OK) return s;
+  } else if (rp[0] != 0 || rp[n] != nnz) {
+    set_error("row_ptr[0] must be 0 and row_ptr[n] must equal nnz");
+    return CPAA_EPATTERN;
+  }
+  if (num_graphs > 1) {
+    if (gp[0] != 0 || gp[num_graphs] != n) {
+      set_error("graph_ptr must start at 0 and end at n");
+      return CPAA_EINVAL;
+    }
+    for (int gi = 0; gi < num_graphs; ++gi) {
+      if (gp[gi + 1] <= gp[gi]) {
+        set_error("graph_ptr must be strictly increasing");
+        return CPAA_EINVAL;
+      }
+      if (o.validate) {
+        for (int32_t u = gp[gi]; u < gp[gi + 1]; ++u)
+          for (int32_t j = rp[u]; j < rp[u + 1]; ++j)
+            if (ci[j] < gp[gi] || ci[j] >= gp[gi + 1]) {
+              set_error("an edge crosses the boundary of graph " + std::to_string(gi));
+              return CPAA_EINVAL;
+            }
+      }
+    }
+  }
+
+  cpaa_plan_s* pl = new (std::nothrow) cpaa_plan_s();
+  if (!pl) {
+    set_error("host allocation failed");
+    return CPAA_ENOMEM;
+  }
+  pl->opts = o;
+  pl->n = n;
+  pl->nnz = nnz;
+  pl->c = c;
+  pl->s = std::sqrt(1.0 - c * c);
+  pl->beta = (1.0 - pl->s) / c;
+  pl->num_graphs = num_graphs;
+  (void)hipGetDevice(&pl->device);
+  int maxd = 0, mind = INT32_MAX;
+  double vol = 0.0;
+  for (int32_t u = 0; u < n; ++u) {
+    const int d = rp[u + 1] - rp[u];
+    maxd = std::max(maxd, d);
+    mind = std::min(mind, d);
+    vol += d;
+  }
+  if (mind <= 0) {
+    cpaa_plan_destroy(pl);
+    set_error("isolated vertex (degree 0)");
+    return CPAA_EISOLATED;
+  }
+  pl->max_deg = maxd;
+  pl->min_deg = mind;
+  pl->vol = vol;
+  pl->ck.resize(kMaxTerms + 2);
+  for (int k = 0; k < kMaxTerms + 2; ++k) pl->ck[k] = 2.0 / pl->s * std::pow(pl->beta, k);
+
+  pl->npt = o.nnz_per_thread ? o.nnz_per_thread : 8;
+  pl->xcd_remap = o.xcd_remap < 0 ? 1 : (o.xcd_remap ? 1 : 0);
+  std::vector<WorkItem> items;
+  std::vector<int> nch;
+  build_items(n, rp, pl->npt, items, nch);
+  pl->n_items = static_cast<int>(items.size());
+  pl->n_split_rows = static_cast<int>(nch.size());
+  std::vector<WorkItem> titems;
+  std::vector<int> tnch;
+  build_tile_items(n, rp, titems, tnch);
+  pl->n_titems = static_cast<int>(titems.size());
+  pl->n_tsplit_rows = static_cast<int>(tnch.size());
+  pl->tile_w = o.tile_w ? o.tile_w : 64;
+
+  cpaa_status s = CPAA_OK;
+  if (s == CPAA_OK) s = dev_upload(&pl->d_row_ptr, rp, n + 1);
+  if (s == CPAA_OK) s = dev_upload(&pl->d_col_idx, ci, static_cast<size_t>(nnz));
+  if (s == CPAA_OK) s = dev_upload(&pl->d_items, items.data(), items.size());
+  if (s == CPAA_OK) s = dev_upload(&pl->d_split_nchunks, nch.data(), nch.size());
+  if (s == CPAA_OK) s = dev_upload(&pl->d_titems, titems.data(), titems.size());
+  if (s == CPAA_OK) s = dev_upload(&pl->d_tsplit_nchunks, tnch.data(), tnch.size());
+  if (s == CPAA_OK && num_graphs > 1) {
+    pl->h_graph_ptr.assign(gp, gp + num_graphs + 1);
+    std::vector<int64_t> gnnz(num_graphs);
+    for (int gi = 0; gi < num_graphs; ++gi) {
+      gnnz[gi] = static_cast<int64_t>(rp[gp[gi + 1]]) - rp[gp[gi]];
+      pl->max_graph_n = std::max(pl->max_graph_n, gp[gi + 1] - gp[gi]);
+      pl->max_graph_nnz = std::max(pl->max_graph_nnz, gnnz[gi]);
+    }
+    std::vector<int32_t> order(num_graphs);
+    for (int gi = 0; gi < num_graphs; ++gi) order[gi] = gi;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t a, int32_t b) { return gnnz[a] > gnnz[b]; });
+    s = dev_upload(&pl->d_graph_ptr, gp, num_graphs + 1);
+    if (s == CPAA_OK) s = dev_upload(&pl->d_graph_order, order.data(), order.size());
+    if (s == CPAA_OK) s = dev_alloc(&pl->d_queue, 1);
+  }
+  if (s == CPAA_OK) {
+    if (hipEventCreate(&pl->ev_begin) != hipSuccess || hipEventCreate(&pl->ev_end) != hipSuccess) {
+      set_error("hipEventCreate failed");
+      s = CPAA_EDEVICE;
+    }
+  }
+  if (s != CPAA_OK) {
+    cpaa_plan_destroy(pl);
+    return s;
+  }
+  *out = pl;
+  return CPAA_OK;
+}
+
+cpaa_status cpaa_plan_info_get(cpaa_plan_t pl, cpaa_plan_info* info) {
+  if (!pl || !info) {
+    set_error("cpaa_plan_info_get: null argument");
+    return CPAA_EINVAL;
+  }
+  std::memset(info, 0, sizeof(*info));
+  info->n = pl->n;
+  info->nnz = pl->nnz;
+  info->num_graphs = pl->num_graphs;
+  info->reordered = 0;
+  info->max_degree = pl->max_deg;
+  info->split_rows = pl->n_split_rows;
+  info->nnz_per_thread = pl->npt;
+  info->work_items = pl->n_items;
+  info->tile_w = pl->tile_w;
+  info->c = pl->c;
+  info->beta = pl->beta;
+  info->vol = pl->vol;
+  info->k_cap_global = mass_rule_terms(pl, 1e-6);
+  return CPAA_OK;
+}
+
+}  // extern "C"

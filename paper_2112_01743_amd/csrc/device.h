@@ -1,0 +1,68 @@
+// Device helpers shared by the CPAA kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace cpaa {
+
+// MI355X dispatches consecutive workgroups round-robin over its 8 XCDs, each
+// with a private L2.  With remapping, the workgroups that land on one XCD take
+// one contiguous range of logical work items, so neighbouring rows (and the
+// vector entries they gather) stay in one L2.  Bijective for any total.
+__device__ __forceinline__ int xcd_logical(int b, int total, int remap) {
+  if (!remap) return b;
+  const int x = b & 7, i = b >> 3;
+  const int q = total >> 3, r = total & 7;
+  return x * q + (x < r ? x : r) + i;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  return v;
+}
+
+// Sum over a 256-thread workgroup; the result is valid in thread 0.
+// Every thread of the block must call it (it contains barriers).
+__device__ __forceinline__ double block_sum256(double v) {
+  __shared__ double red[4];
+  v = wave_sum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return (threadIdx.x == 0) ? (red[0] + red[1]) + (red[2] + red[3]) : 0.0;
+}
+
+__device__ __forceinline__ double block_max256(double v) {
+  __shared__ double red[4];
+  v = wave_max(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return (threadIdx.x == 0) ? fmax(fmax(red[0], red[1]), fmax(red[2], red[3])) : 0.0;
+}
+
+// max of non-negative doubles through the integer ordering of their bits
+__device__ __forceinline__ void atomic_max_nonneg(double* addr, double v) {
+  atomicMax(reinterpret_cast<unsigned long long*>(addr),
+            static_cast<unsigned long long>(__double_as_longlong(v)));
+}
+
+__device__ __forceinline__ void atomic_add(double* addr, double v) { unsafeAtomicAdd(addr, v); }
+__device__ __forceinline__ void atomic_add(float* addr, float v) { unsafeAtomicAdd(addr, v); }
+
+__device__ __forceinline__ int prev_pow2(int v) {
+  return v <= 1 ? 1 : (1 << (31 - __clz(v)));
+}
+
+}  // namespace cpaa

@@ -1,0 +1,179 @@
+// Internal declarations of the CPAA library (gfx950 / HIP).
+//
+// Data layout in HBM (single-graph plan):
+//   row_ptr[n+1], col_idx[nnz]      int32 CSR pattern (caller's vertex order)
+//   z[3][n]                          FP32 Chebyshev vectors in z-space, z_k = D^{-1} T_k(P) b
+//   acc[n]                           FP64 running sum D^{-1} x_M
+//   b[n], r[n]                       FP64 right-hand side and residual
+// Batched solves use tiles of W right-hand sides: z[3][tiles][n][W] (FP32),
+// acc/b/r[tiles][n][W] (FP64), so the W values of one vertex are contiguous and
+// a neighbour gather is one coalesced W*4-byte access.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/cpaa.h"
+
+namespace cpaa {
+
+constexpr int kWG = 256;           // threads per workgroup
+constexpr int kSlots = 64;         // atomic reduction slots (spread contention)
+constexpr int kMaxTerms = 512;     // hard cap on terms of one series
+constexpr int kStat = 6;           // reduction fields per column (see kernels.hip)
+constexpr int kLongRow = 128;      // W = 1: rows longer than this never share a block with short rows
+constexpr int kTileLongDeg = 512;  // tiled: rows above this degree are split across wavefronts
+constexpr int kTileChunkNnz = 256; // tiled: nnz per wavefront chunk of a split row
+constexpr int kTileShortNnz = 128; // tiled: nnz budget of a wavefront's group of short rows
+
+void set_error(const std::string& msg);
+
+#define CPAA_HIP(call)                                                            \
+  do {                                                                            \
+    hipError_t e_ = (call);                                                       \
+    if (e_ != hipSuccess) {                                                       \
+      ::cpaa::set_error(std::string("HIP error: ") + hipGetErrorString(e_) +      \
+                        " at " + __FILE__ + ":" + std::to_string(__LINE__));      \
+      return CPAA_EDEVICE;                                                        \
+    }                                                                             \
+  } while (0)
+
+// Work unit of the single-vector SpMV kernels: a window of at most
+// kWG * npt stored entries.
+//   row1 >= 0: rows [row0, row1), all of whose entries lie in [nnz0, nnz1).
+//   row1 <  0: one chunk [nnz0, nnz1) of the split row row0; its partial sum
+//              goes to slot -(row1 + 1).
+struct WorkItem {
+  int row0;
+  int row1;
+  int nnz0;
+  int nnz1;
+};
+
+struct Workspace {
+  int W = 0;              // tile width (1 = single vector path)
+  int tiles = 0;
+  int64_t cols = 0;       // tiles * W
+  size_t vec_elems = 0;   // n * cols
+  float* z[3] = {nullptr, nullptr, nullptr};
+  double* acc = nullptr;
+  double* b = nullptr;
+  double* r = nullptr;
+  double* slots = nullptr;       // [kMaxTerms+2][kSlots][cols] certificate partials
+  double* stat_slots = nullptr;  // [kSlots][cols][kStat]
+  double* stat = nullptr;        // [cols][kStat] collapsed
+  int* done = nullptr;           // [tiles]
+  int* terms = nullptr;          // [tiles]
+  double* series_cert = nullptr; // [cols]
+  float* split_f = nullptr;      // [split slots * W] FP32 partial sums
+  double* split_d = nullptr;     // [split slots * W] FP64 partial sums (residual)
+  int* split_count = nullptr;    // [split slots] arrivals
+  int* active = nullptr;         // [tiles] device copy of the tile mask of a correction pass
+  int* plain = nullptr;          // [cols] columns restarted as plain solves
+  double* col_scale = nullptr;   // [cols] output scale per column
+  double* host = nullptr;        // pinned host mirror
+  size_t host_bytes = 0;
+};
+
+}  // namespace cpaa
+
+struct cpaa_plan_s {
+  int device = 0;
+  int32_t n = 0;
+  int64_t nnz = 0;
+  double c = 0.85;
+  double beta = 0.0;
+  double s = 0.0;     // sqrt(1-c^2)
+  double vol = 0.0;
+  int max_deg = 0;
+  int min_deg = 0;
+  cpaa_opts opts{};
+  int num_graphs = 1;
+
+  int32_t* d_row_ptr = nullptr;
+  int32_t* d_col_idx = nullptr;
+
+  // single-vector work map
+  int npt = 8;                       // nnz per thread of a work item
+  cpaa::WorkItem* d_items = nullptr;
+  int n_items = 0;
+  int n_split_rows = 0;
+  int* d_split_nchunks = nullptr;    // [n_split_rows]
+  int xcd_remap = 0;
+
+  // tiled work map (per wavefront)
+  cpaa::WorkItem* d_titems = nullptr;
+  int n_titems = 0;
+  int n_tsplit_rows = 0;
+  int* d_tsplit_nchunks = nullptr;
+  int tile_w = 64;
+
+  // multi-graph batch
+  int32_t* d_graph_ptr = nullptr;
+  int32_t* d_graph_order = nullptr;  // graphs by nnz, largest first
+  int* d_queue = nullptr;
+  int max_graph_n = 0;
+  int64_t max_graph_nnz = 0;
+  std::vector<int32_t> h_graph_ptr;
+  std::vector<int32_t> h_row_ptr_graph_nnz;  // nnz per graph
+
+  std::vector<double> ck;            // c_k, k = 0..kMaxTerms+1
+
+  cpaa::Workspace ws1;               // W = 1
+  cpaa::Workspace wst;               // tiled
+  cpaa::Workspace wsg;               // multi-graph
+
+  hipEvent_t ev_begin = nullptr, ev_end = nullptr;
+  std::vector<hipEvent_t> ev_terms;  // pairs around term launches
+};
+
+namespace cpaa {
+
+hipError_t fill_f64(double* p, double v, size_t count, hipStream_t st);
+hipError_t fill_i32(int* p, int v, size_t count, hipStream_t st);
+hipError_t collapse_stats(Workspace& ws, hipStream_t st);
+
+// ---- single-vector path (W = 1) ----
+// src: caller vector (p or x0) or the plan's own residual; b = scale * src.
+hipError_t init_w1(const cpaa_plan_s* pl, Workspace& ws, const double* src, double scale,
+                   bool add, bool store_b, bool series, hipStream_t st);
+hipError_t load_x0_w1(const cpaa_plan_s* pl, Workspace& ws, const double* x0, hipStream_t st);
+hipError_t term_w1(const cpaa_plan_s* pl, Workspace& ws, int cur, int prev, int next,
+                   bool first, double a_next, double* cert_slot, const int* done,
+                   hipStream_t st);
+hipError_t check_series(const cpaa_plan_s* pl, Workspace& ws, const double* cert_slot,
+                        double scale, double target, int term_index, hipStream_t st);
+hipError_t residual_w1(const cpaa_plan_s* pl, Workspace& ws, hipStream_t st);
+hipError_t finalize_w1(const cpaa_plan_s* pl, Workspace& ws, double* x, double scale,
+                       hipStream_t st);
+
+// ---- tiled path (W right-hand sides per tile) ----
+hipError_t init_tile(const cpaa_plan_s* pl, Workspace& ws, const double* P, int64_t ldp, int B,
+                     double scale, bool add, bool store_b, bool series, hipStream_t st);
+hipError_t init_tile_from_r(const cpaa_plan_s* pl, Workspace& ws, const int* active,
+                            const int* plain, hipStream_t st);
+hipError_t load_x0_tile(const cpaa_plan_s* pl, Workspace& ws, const double* X0, int64_t ldx0,
+                        int B, hipStream_t st);
+hipError_t term_tile(const cpaa_plan_s* pl, Workspace& ws, int cur, int prev, int next,
+                     bool first, double a_next, double* cert_slot, const int* done,
+                     hipStream_t st);
+hipError_t residual_tile(const cpaa_plan_s* pl, Workspace& ws, const int* active, hipStream_t st);
+hipError_t finalize_tile(const cpaa_plan_s* pl, Workspace& ws, double* X, int64_t ldx, int B,
+                         const double* col_scale, hipStream_t st);
+hipError_t init_done(Workspace& ws, const int* active, hipStream_t st);
+
+// ---- multi-graph path (graphs.hip) ----
+cpaa_status solve_graphs_impl(cpaa_plan_s* pl, const double* p, double tol, double* x,
+                              cpaa_report* reps, hipStream_t st);
+
+// ---- host helpers (solve.hip) ----
+cpaa_status ensure_workspace(cpaa_plan_s* pl, Workspace& ws, int W, int tiles);
+void free_workspace(Workspace& ws);
+double series_tail(const cpaa_plan_s* pl, int M);
+int apriori_terms(const cpaa_plan_s* pl, double norm_dinv_half_b, double target);
+int mass_rule_terms(const cpaa_plan_s* pl, double target);
+
+}  // namespace cpaa

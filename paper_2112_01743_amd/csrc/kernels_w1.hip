@@ -1,0 +1,389 @@
+// Single-vector CPAA kernels (one right-hand side), gfx950.
+//
+// Hot loop (Alg. 1, Sec. 4.1, in z-space z_k = D^{-1} T_k(P) b):
+//     z_{k+1}(u) = 2 * (sum_{v in N(u)} z_k(v)) / d_u - z_{k-1}(u)
+//     acc(u)    += c_{k+1} * z_{k+1}(u)                     (FP64)
+// so the SpMV runs on the 0/1 pattern A and the D^{-1} scaling, the
+// three-term update, the weighted accumulation and the certificate partial
+// d_u |z_{k+1}(u) - beta z_k(u)| all sit in the epilogue of one kernel.
+//
+// Work decomposition: the plan cuts the CSR into work items of at most
+// 256*npt stored entries.  A workgroup loads its item's column indices with
+// fully coalesced loads (npt independent loads per thread) and issues npt
+// independent gathers per thread, stages the gathered values in LDS, and then
+// reduces every row with an adaptive number of lanes per row.  Rows longer
+// than one item (hubs of power-law graphs) are cut into chunks over several
+// workgroups; chunk sums meet in an FP32 atomic slot and the last arriving
+// workgroup runs the row's epilogue.
+#include "device.h"
+#include "internal.h"
+
+namespace cpaa {
+namespace {
+
+// Sum of x over N(u) for the rows of one work item; calls
+// epi.row(u, d_u, sum, sum_of_magnitudes) exactly once per row, from one thread.
+// With ABS the sum of |x| over N(u) is formed too (split partials then use
+// two slots per row: [2*slot] sum, [2*slot+1] sum of magnitudes).
+template <typename V, int NPT, bool ABS, typename Epi>
+__device__ __forceinline__ void spmv_item(const WorkItem it, const int* __restrict__ rp,
+                                          const int* __restrict__ ci, const V* __restrict__ x,
+                                          V* __restrict__ split_part, int* __restrict__ split_count,
+                                          const int* __restrict__ split_nchunks, Epi& epi) {
+  constexpr int CAP = kWG * NPT;
+  __shared__ V vals[CAP];
+  __shared__ int lrp[kWG * 4 + 1];
+  __shared__ V wsum[4];
+  __shared__ V wabs[4];
+  const int t = threadIdx.x;
+  const int nb = it.nnz0, ne = it.nnz1;
+
+  int col[NPT];
+#pragma unroll
+  for (int i = 0; i < NPT; ++i) {
+    const int j = nb + t + i * kWG;
+    col[i] = (j < ne) ? __builtin_nontemporal_load(ci + j) : -1;
+  }
+  V v[NPT];
+#pragma unroll
+  for (int i = 0; i < NPT; ++i) v[i] = (col[i] >= 0) ? x[col[i]] : V(0);
+
+  if (it.row1 < 0) {
+    // one chunk of a split row
+    V s = V(0), sa = V(0);
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+      s += v[i];
+      if (ABS) sa += fabs(v[i]);
+    }
+    s = wave_sum(s);
+    if (ABS) sa = wave_sum(sa);
+    if ((t & 63) == 0) {
+      wsum[t >> 6] = s;
+      wabs[t >> 6] = sa;
+    }
+    __syncthreads();
+    if (t == 0) {
+      const int slot = -(it.row1 + 1);
+      const int ps = ABS ? 2 * slot : slot;
+      atomic_add(&split_part[ps], (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]));
+      if (ABS) atomic_add(&split_part[ps + 1], (wabs[0] + wabs[1]) + (wabs[2] + wabs[3]));
+      __threadfence();
+      const int prev = atomicAdd(&split_count[slot], 1);
+      if (prev == split_nchunks[slot] - 1) {
+        __threadfence();
+        const V full = __hip_atomic_exchange(&split_part[ps], V(0), __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+        V full_abs = V(0);
+        if (ABS)
+          full_abs = __hip_atomic_exchange(&split_part[ps + 1], V(0), __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_exchange(&split_count[slot], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        epi.row(it.row0, rp[it.row0 + 1] - rp[it.row0], full, full_abs);
+      }
+    }
+    return;
+  }
+
+#pragma unroll
+  for (int i = 0; i < NPT; ++i) {
+    const int k = t + i * kWG;
+    if (nb + k < ne) vals[k] = v[i];
+  }
+  const int nrows = it.row1 - it.row0;
+  for (int r = t; r <= nrows; r += kWG) lrp[r] = rp[it.row0 + r] - nb;
+  __syncthreads();
+
+  const int lpr = nrows >= kWG ? 1 : min(64, prev_pow2(kWG / nrows));
+  if (lpr == 1) {
+    for (int r = t; r < nrows; r += kWG) {
+      const int a = lrp[r], e = lrp[r + 1];
+      V s = V(0), sa = V(0);
+      int k = a;
+      for (; k + 4 <= e; k += 4) {
+        s += (vals[k] + vals[k + 1]) + (vals[k + 2] + vals[k + 3]);
+        if (ABS) sa += (fabs(vals[k]) + fabs(vals[k + 1])) + (fabs(vals[k + 2]) + fabs(vals[k + 3]));
+      }
+      for (; k < e; ++k) {
+        s += vals[k];
+        if (ABS) sa += fabs(vals[k]);
+      }
+      epi.row(it.row0 + r, e - a, s, sa);
+    }
+  } else {
+    const int sh = __ffs(lpr) - 1;
+    const int g = t >> sh, l = t & (lpr - 1);
+    V s = V(0), sa = V(0);
+    int a = 0, e = 0;
+    if (g < nrows) {
+      a = lrp[g];
+      e = lrp[g + 1];
+      for (int k = a + l; k < e; k += lpr) {
+        s += vals[k];
+        if (ABS) sa += fabs(vals[k]);
+      }
+    }
+    for (int off = lpr >> 1; off > 0; off >>= 1) {
+      s += __shfl_xor(s, off);
+      if (ABS) sa += __shfl_xor(sa, off);
+    }
+    if (g < nrows && l == 0) epi.row(it.row0 + g, e - a, s, sa);
+  }
+}
+
+struct TermEpi {
+  const float* __restrict__ zc;
+  const float* __restrict__ zp;
+  float* __restrict__ zn;
+  double* __restrict__ acc;
+  float alpha, gamma;
+  double a_next, beta;
+  int want_cert;
+  double cert;
+  __device__ __forceinline__ void row(int r, int d, float s, float) {
+    float y = alpha * (s / static_cast<float>(d));
+    if (gamma != 0.f) y -= gamma * zp[r];
+    zn[r] = y;
+    acc[r] += a_next * static_cast<double>(y);
+    if (want_cert)
+      cert += static_cast<double>(d) *
+              fabs(static_cast<double>(y) - beta * static_cast<double>(zc[r]));
+  }
+};
+
+struct TermArgs {
+  const int* rp;
+  const int* ci;
+  const WorkItem* items;
+  const float* zc;
+  const float* zp;
+  float* zn;
+  double* acc;
+  float alpha, gamma;
+  double a_next, beta;
+  double* cert;          // [kSlots] or null
+  const int* done;       // stop flag or null
+  float* split_part;
+  int* split_count;
+  const int* split_nchunks;
+  int xcd;
+};
+
+template <int NPT>
+__global__ __launch_bounds__(kWG) void k_term_w1(TermArgs a) {
+  if (a.done != nullptr && *a.done) return;
+  const int lb = xcd_logical(blockIdx.x, gridDim.x, a.xcd);
+  TermEpi epi{a.zc, a.zp, a.zn, a.acc, a.alpha, a.gamma, a.a_next, a.beta,
+              a.cert != nullptr, 0.0};
+  spmv_item<float, NPT, false>(a.items[lb], a.rp, a.ci, a.zc, a.split_part, a.split_count,
+                        a.split_nchunks, epi);
+  if (a.cert != nullptr) {
+    const double s = block_sum256(epi.cert);
+    if (threadIdx.x == 0 && s != 0.0) atomic_add(&a.cert[lb % kSlots], s);
+  }
+}
+
+struct ResidEpi {
+  const double* __restrict__ acc;
+  const double* __restrict__ b;
+  double* __restrict__ r_out;
+  double c;
+  double f_abs, f_max, f_q, f_mass, f_round, f_bad;
+  // r = b - d a + c s.  Besides |r| the row adds an upper bound on the FP64
+  // rounding error of that evaluation (any summation order):
+  // (d + 3) u (|b| + d |a| + c sum|a_v|), u = 2^-53, which keeps
+  // ||r||_1 / (1-c) a rigorous bound for the x actually returned.
+  __device__ __forceinline__ void row(int r, int d, double s, double sa) {
+    const double a = acc[r];
+    const double dd = static_cast<double>(d);
+    const double bb = b[r];
+    const double res = bb - dd * a + c * s;
+    r_out[r] = res;
+    const double ar = fabs(res);
+    if (!isfinite(res)) f_bad += 1.0;
+    f_abs += ar;
+    f_max = fmax(f_max, ar);
+    f_q += res * res / dd;
+    f_mass += dd * a;
+    f_round += (dd + 3.0) * 0x1p-53 * (fabs(bb) + dd * fabs(a) + c * sa);
+  }
+};
+
+struct ResidArgs {
+  const int* rp;
+  const int* ci;
+  const WorkItem* items;
+  const double* acc;
+  const double* b;
+  double* r;
+  double c;
+  double* stat_slots;   // [kSlots][1][kStat]
+  double* split_part;
+  int* split_count;
+  const int* split_nchunks;
+  int xcd;
+};
+
+template <int NPT>
+__global__ __launch_bounds__(kWG) void k_resid_w1(ResidArgs a) {
+  const int lb = xcd_logical(blockIdx.x, gridDim.x, a.xcd);
+  ResidEpi epi{a.acc, a.b, a.r, a.c, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  spmv_item<double, NPT, true>(a.items[lb], a.rp, a.ci, a.acc, a.split_part, a.split_count,
+                         a.split_nchunks, epi);
+  const double s_abs = block_sum256(epi.f_abs);
+  const double s_max = block_max256(epi.f_max);
+  const double s_q = block_sum256(epi.f_q);
+  const double s_mass = block_sum256(epi.f_mass);
+  const double s_round = block_sum256(epi.f_round);
+  const double s_bad = block_sum256(epi.f_bad);
+  if (threadIdx.x == 0) {
+    double* o = a.stat_slots + (size_t)(lb % kSlots) * kStat;
+    atomic_add(&o[0], s_abs);
+    atomic_max_nonneg(&o[1], s_max);
+    atomic_add(&o[2], s_q);
+    atomic_add(&o[3], s_mass);
+    atomic_add(&o[4], s_round);
+    if (s_bad != 0.0) atomic_add(&o[5], s_bad);
+  }
+}
+
+// z_0 = b / d (FP32), acc (+)= (c_0/2) b / d (FP64), b = scale * src.
+// Statistics: [0] sum src, [2] sum b^2/d, [4] #negative src, [5] #non-finite src.
+__global__ __launch_bounds__(kWG) void k_init_w1(int n, const int* __restrict__ rp,
+                                                 const double* __restrict__ src, double scale,
+                                                 int add, int store_b, int series, double c0h,
+                                                 double* __restrict__ b, float* __restrict__ z0,
+                                                 double* __restrict__ acc,
+                                                 double* __restrict__ stat_slots) {
+  double f_sum = 0, f_q = 0, f_neg = 0, f_bad = 0;
+  for (int u = blockIdx.x * kWG + threadIdx.x; u < n; u += gridDim.x * kWG) {
+    const double p = src[u];
+    const double bu = scale * p;
+    const double d = static_cast<double>(rp[u + 1] - rp[u]);
+    const double y = bu / d;
+    if (store_b) b[u] = bu;
+    if (series) {
+      z0[u] = static_cast<float>(y);
+      acc[u] = add ? acc[u] + c0h * y : c0h * y;
+    }
+    f_sum += p;
+    f_q += bu * y;
+    f_neg += (p < 0.0) ? 1.0 : 0.0;
+    f_bad += isfinite(p) ? 0.0 : 1.0;
+  }
+  const double s0 = block_sum256(f_sum), s2 = block_sum256(f_q);
+  const double s4 = block_sum256(f_neg), s5 = block_sum256(f_bad);
+  if (threadIdx.x == 0) {
+    double* o = stat_slots + (size_t)(blockIdx.x % kSlots) * kStat;
+    atomic_add(&o[0], s0);
+    atomic_add(&o[2], s2);
+    if (s4 != 0.0) atomic_add(&o[4], s4);
+    if (s5 != 0.0) atomic_add(&o[5], s5);
+  }
+}
+
+// acc = x0 / d; statistic [1] counts non-finite x0 entries.
+__global__ __launch_bounds__(kWG) void k_load_x0_w1(int n, const int* __restrict__ rp,
+                                                    const double* __restrict__ x0,
+                                                    double* __restrict__ acc,
+                                                    double* __restrict__ stat_slots) {
+  double f_bad = 0;
+  for (int u = blockIdx.x * kWG + threadIdx.x; u < n; u += gridDim.x * kWG) {
+    const double v = x0[u];
+    f_bad += isfinite(v) ? 0.0 : 1.0;
+    acc[u] = v / static_cast<double>(rp[u + 1] - rp[u]);
+  }
+  const double s5 = block_sum256(f_bad);
+  if (threadIdx.x == 0 && s5 != 0.0)
+    atomic_add(&stat_slots[(size_t)(blockIdx.x % kSlots) * kStat + 1], s5);
+}
+
+// x = scale * D acc
+__global__ __launch_bounds__(kWG) void k_finalize_w1(int n, const int* __restrict__ rp,
+                                                     const double* __restrict__ acc, double scale,
+                                                     double* __restrict__ x) {
+  for (int u = blockIdx.x * kWG + threadIdx.x; u < n; u += gridDim.x * kWG)
+    x[u] = scale * static_cast<double>(rp[u + 1] - rp[u]) * acc[u];
+}
+
+int elem_grid(int64_t n) {
+  const int64_t g = (n + kWG - 1) / kWG;
+  return static_cast<int>(g < 8192 ? (g < 1 ? 1 : g) : 8192);
+}
+
+}  // namespace
+
+hipError_t init_w1(const cpaa_plan_s* pl, Workspace& ws, const double* src, double scale,
+                   bool add, bool store_b, bool series, hipStream_t st) {
+  hipLaunchKernelGGL(k_init_w1, dim3(elem_grid(pl->n)), dim3(kWG), 0, st, pl->n, pl->d_row_ptr,
+                     src, scale, add ? 1 : 0, store_b ? 1 : 0, series ? 1 : 0, pl->ck[0] / 2.0,
+                     ws.b, ws.z[0], ws.acc, ws.stat_slots);
+  return hipGetLastError();
+}
+
+hipError_t load_x0_w1(const cpaa_plan_s* pl, Workspace& ws, const double* x0, hipStream_t st) {
+  hipLaunchKernelGGL(k_load_x0_w1, dim3(elem_grid(pl->n)), dim3(kWG), 0, st, pl->n,
+                     pl->d_row_ptr, x0, ws.acc, ws.stat_slots);
+  return hipGetLastError();
+}
+
+hipError_t term_w1(const cpaa_plan_s* pl, Workspace& ws, int cur, int prev, int next, bool first,
+                   double a_next, double* cert_slot, const int* done, hipStream_t st) {
+  TermArgs a;
+  a.rp = pl->d_row_ptr;
+  a.ci = pl->d_col_idx;
+  a.items = pl->d_items;
+  a.zc = ws.z[cur];
+  a.zp = first ? nullptr : ws.z[prev];
+  a.zn = ws.z[next];
+  a.acc = ws.acc;
+  a.alpha = first ? 1.f : 2.f;
+  a.gamma = first ? 0.f : 1.f;
+  a.a_next = a_next;
+  a.beta = pl->beta;
+  a.cert = cert_slot;
+  a.done = done;
+  a.split_part = ws.split_f;
+  a.split_count = ws.split_count;
+  a.split_nchunks = pl->d_split_nchunks;
+  a.xcd = pl->xcd_remap;
+  const dim3 grid(pl->n_items);
+  switch (pl->npt) {
+    case 4: hipLaunchKernelGGL(k_term_w1<4>, grid, dim3(kWG), 0, st, a); break;
+    case 16: hipLaunchKernelGGL(k_term_w1<16>, grid, dim3(kWG), 0, st, a); break;
+    default: hipLaunchKernelGGL(k_term_w1<8>, grid, dim3(kWG), 0, st, a); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t residual_w1(const cpaa_plan_s* pl, Workspace& ws, hipStream_t st) {
+  ResidArgs a;
+  a.rp = pl->d_row_ptr;
+  a.ci = pl->d_col_idx;
+  a.items = pl->d_items;
+  a.acc = ws.acc;
+  a.b = ws.b;
+  a.r = ws.r;
+  a.c = pl->c;
+  a.stat_slots = ws.stat_slots + (size_t)kSlots * ws.cols * kStat;   // residual phase
+  a.split_part = ws.split_d;
+  a.split_count = ws.split_count;
+  a.split_nchunks = pl->d_split_nchunks;
+  a.xcd = pl->xcd_remap;
+  const dim3 grid(pl->n_items);
+  switch (pl->npt) {
+    case 4: hipLaunchKernelGGL(k_resid_w1<4>, grid, dim3(kWG), 0, st, a); break;
+    case 16: hipLaunchKernelGGL(k_resid_w1<16>, grid, dim3(kWG), 0, st, a); break;
+    default: hipLaunchKernelGGL(k_resid_w1<8>, grid, dim3(kWG), 0, st, a); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t finalize_w1(const cpaa_plan_s* pl, Workspace& ws, double* x, double scale,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_finalize_w1, dim3(elem_grid(pl->n)), dim3(kWG), 0, st, pl->n,
+                     pl->d_row_ptr, ws.acc, scale, x);
+  return hipGetLastError();
+}
+
+}  // namespace cpaa

@@ -1,0 +1,638 @@
+// Solve orchestration: one series of Chebyshev terms, the FP64 residual check,
+// correction series on the residual, warm starts and the report.
+//
+// A series on right-hand side b (Sec. 3 eq. 3.1 applied to b) runs
+//   term 0 (init):  z_0 = D^{-1} b,  acc (+)= (c_0/2) z_0
+//   term 1:         z_1 = D^{-1} A z_0,  acc += c_1 z_1
+//   term k+1:       z_{k+1} = 2 D^{-1} A z_k - z_{k-1},  acc += c_{k+1} z_{k+1}
+// so x = D acc.  Stopping: the identity
+//   b - (I - cP) x_M = ((1+s)/s) beta^{M+1} (T_{M+1}(P) b - beta T_M(P) b)
+// (derived from eq. 3.1 and the three-term recurrence, s = sqrt(1-c^2)) gives
+// an in-loop bound ||x_M - x||_1 <= ||.||_1/(1-c) from the last two vectors;
+// the kernel producing z_{M+1} accumulates sum_u d_u |z_{M+1}(u) - beta z_M(u)|
+// and a one-workgroup check kernel raises a device-side stop flag, so later
+// term kernels exit at once and the host never waits inside a series.  The
+// cap on terms is the a-priori bound sqrt(vol) ||D^{-1/2} b||_2 sum_{k>M} c_k
+// (P = D^{1/2} S D^{-1/2} with S symmetric, spectrum in [-1,1] by Lemma 2),
+// and no check runs before eq. 4.1's mass error ERR_M (a lower bound on the
+// L1 error of a probability right-hand side) is below the target.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "internal.h"
+
+namespace cpaa {
+
+void free_workspace(Workspace& ws) {
+  void* ptrs[] = {ws.z[0], ws.z[1], ws.z[2], ws.acc, ws.b, ws.r, ws.slots, ws.stat_slots,
+                  ws.stat, ws.done, ws.terms, ws.series_cert, ws.split_f, ws.split_d,
+                  ws.split_count, ws.active, ws.plain, ws.col_scale};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  if (ws.host) (void)hipHostFree(ws.host);
+  ws = Workspace();
+}
+
+// Host mirror layout (pinned): stat[2][cols][kStat] | series_cert[cols] | col_scale[cols] |
+// done[tiles] | terms[tiles] | active[tiles] | plain[cols]
+static size_t host_mirror_bytes(int64_t cols, int tiles) {
+  return (size_t)(2 * kStat + 2) * cols * sizeof(double) + (size_t)(3 * tiles + cols) * sizeof(int) +
+         64;
+}
+
+cpaa_status ensure_workspace(cpaa_plan_s* pl, Workspace& ws, int W, int tiles) {
+  if (ws.W == W && ws.tiles == tiles && ws.z[0]) return CPAA_OK;
+  free_workspace(ws);
+  ws.W = W;
+  ws.tiles = tiles;
+  ws.cols = static_cast<int64_t>(tiles) * W;
+  ws.vec_elems = static_cast<size_t>(pl->n) * ws.cols;
+  // split-row partial sums: one set per tile (tiles run concurrently)
+  const size_t nsplit = (size_t)std::max(W == 1 ? pl->n_split_rows : pl->n_tsplit_rows, 1);
+  const size_t split_sets = (size_t)tiles;
+  auto alloc = [&](void** p, size_t bytes) -> bool {
+    if (bytes == 0) bytes = 8;
+    if (hipMalloc(p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      *p = nullptr;
+      return false;
+    }
+    return true;
+  };
+  bool ok = true;
+  for (int i = 0; i < 3; ++i) ok = ok && alloc((void**)&ws.z[i], ws.vec_elems * sizeof(float));
+  ok = ok && alloc((void**)&ws.acc, ws.vec_elems * sizeof(double));
+  ok = ok && alloc((void**)&ws.b, ws.vec_elems * sizeof(double));
+  ok = ok && alloc((void**)&ws.r, ws.vec_elems * sizeof(double));
+  ok = ok && alloc((void**)&ws.slots, (size_t)(kMaxTerms + 2) * kSlots * ws.cols * sizeof(double));
+  ok = ok && alloc((void**)&ws.stat_slots, (size_t)2 * kSlots * ws.cols * kStat * sizeof(double));
+  ok = ok && alloc((void**)&ws.stat, (size_t)2 * ws.cols * kStat * sizeof(double));
+  ok = ok && alloc((void**)&ws.done, (size_t)tiles * sizeof(int));
+  ok = ok && alloc((void**)&ws.terms, (size_t)tiles * sizeof(int));
+  ok = ok && alloc((void**)&ws.series_cert, (size_t)ws.cols * sizeof(double));
+  ok = ok && alloc((void**)&ws.split_f, split_sets * nsplit * W * sizeof(float));
+  ok = ok && alloc((void**)&ws.split_d, split_sets * nsplit * 2 * W * sizeof(double));
+  ok = ok && alloc((void**)&ws.split_count, split_sets * nsplit * sizeof(int));
+  ok = ok && alloc((void**)&ws.active, (size_t)tiles * sizeof(int));
+  ok = ok && alloc((void**)&ws.plain, (size_t)ws.cols * sizeof(int));
+  ok = ok && alloc((void**)&ws.col_scale, (size_t)ws.cols * sizeof(double));
+  ws.host_bytes = host_mirror_bytes(ws.cols, tiles);
+  if (ok && hipHostMalloc((void**)&ws.host, ws.host_bytes, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    ws.host = nullptr;
+    ok = false;
+  }
+  if (ok) {
+    ok = hipMemset(ws.split_f, 0, split_sets * nsplit * W * sizeof(float)) == hipSuccess &&
+         hipMemset(ws.split_d, 0, split_sets * nsplit * 2 * W * sizeof(double)) == hipSuccess &&
+         hipMemset(ws.split_count, 0, split_sets * nsplit * sizeof(int)) == hipSuccess &&
+         hipDeviceSynchronize() == hipSuccess;
+  }
+  if (!ok) {
+    free_workspace(ws);
+    set_error("workspace allocation failed (n = " + std::to_string(pl->n) +
+              ", columns = " + std::to_string(static_cast<long long>(tiles) * W) + ")");
+    return CPAA_ENOMEM;
+  }
+  return CPAA_OK;
+}
+
+double series_tail(const cpaa_plan_s* pl, int M) {
+  // sum_{k>M} c_k = (2/s) beta^{M+1} / (1 - beta)
+  return 2.0 / pl->s * std::pow(pl->beta, M + 1) / (1.0 - pl->beta);
+}
+
+int apriori_terms(const cpaa_plan_s* pl, double q, double target) {
+  // q = sum_u b_u^2 / d_u = ||D^{-1/2} b||_2^2
+  const int cap = pl->opts.k_max > 0 ? std::min(pl->opts.k_max, kMaxTerms) : kMaxTerms;
+  const double scale = std::sqrt(pl->vol) * std::sqrt(std::max(q, 0.0));
+  if (!(scale > 0.0)) return 0;
+  for (int M = 0; M <= cap; ++M)
+    if (scale * series_tail(pl, M) <= target) return M;
+  return cap;
+}
+
+int mass_rule_terms(const cpaa_plan_s* pl, double target) {
+  // eq. 4.1: ERR_M = 2 beta^{M+1} / (1 + beta)
+  for (int M = 0; M < kMaxTerms; ++M)
+    if (2.0 * std::pow(pl->beta, M + 1) / (1.0 + pl->beta) <= target) return M;
+  return kMaxTerms;
+}
+
+namespace {
+
+struct TermTimer {
+  cpaa_plan_s* pl;
+  bool on;
+  struct Rec {
+    int ev;          // index of the first event of the pair
+    int series;
+    int term;        // index of the term this launch produces
+  };
+  std::vector<Rec> recs;
+  int used = 0;
+  hipError_t before(int series, int term, hipStream_t st) {
+    if (!on) return hipSuccess;
+    while ((int)pl->ev_terms.size() < used + 2) {
+      hipEvent_t e;
+      hipError_t err = hipEventCreate(&e);
+      if (err != hipSuccess) return err;
+      pl->ev_terms.push_back(e);
+    }
+    recs.push_back({used, series, term});
+    hipError_t err = hipEventRecord(pl->ev_terms[used], st);
+    used += 2;
+    return err;
+  }
+  hipError_t after(hipStream_t st) {
+    if (!on) return hipSuccess;
+    return hipEventRecord(pl->ev_terms[recs.back().ev + 1], st);
+  }
+  // sum of durations of the launches that did work (term <= terms run by their series)
+  void total(const std::vector<int>& series_terms, double* ms, int64_t* launches) {
+    *ms = 0.0;
+    *launches = 0;
+    for (const Rec& r : recs) {
+      if (r.term > series_terms[r.series]) continue;
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, pl->ev_terms[r.ev], pl->ev_terms[r.ev + 1]) == hipSuccess) {
+        *ms += t;
+        ++*launches;
+      }
+    }
+  }
+};
+
+using TermFn = hipError_t (*)(const cpaa_plan_s*, Workspace&, int, int, int, bool, double,
+                              double*, const int*, hipStream_t);
+
+// Launch terms 1..k_cap of a series whose init already ran.  Returns after
+// enqueueing; the stop flag / term count live in ws.done / ws.terms.  With
+// `active` (device [tiles]) only the active tiles run.
+cpaa_status run_series(cpaa_plan_s* pl, Workspace& ws, TermFn term, int series_id, int k_cap,
+                       int k_min, double target, TermTimer& timer, hipStream_t st,
+                       const int* active = nullptr) {
+  const int64_t cols = ws.cols;
+  CPAA_HIP(fill_f64(ws.slots, 0.0, (size_t)(k_cap + 1) * kSlots * cols, st));
+  CPAA_HIP(init_done(ws, active, st));
+  CPAA_HIP(fill_i32(ws.terms, k_cap, ws.tiles, st));
+  CPAA_HIP(fill_f64(ws.series_cert, -1.0, cols, st));
+  for (int k = 0; k < k_cap; ++k) {
+    // this launch produces z_{k+1}; its certificate is that of x_k
+    double* cert = (k >= k_min) ? ws.slots + (size_t)k * kSlots * cols : nullptr;
+    const int* done = (active != nullptr || (k >= 1 && k - 1 >= k_min)) ? ws.done : nullptr;
+    CPAA_HIP(timer.before(series_id, k + 1, st));
+    CPAA_HIP(term(pl, ws, k % 3, (k + 2) % 3, (k + 1) % 3, k == 0, pl->ck[k + 1], cert, done, st));
+    CPAA_HIP(timer.after(st));
+    if (cert) {
+      const double scale = (1.0 + pl->s) / pl->s * std::pow(pl->beta, k + 1) / (1.0 - pl->c);
+      CPAA_HIP(check_series(pl, ws, cert, scale, target, k + 1, st));
+    }
+  }
+  return CPAA_OK;
+}
+
+struct HostView {
+  double* stat;
+  double* series_cert;
+  double* col_scale;
+  int* done;
+  int* terms;
+  int* active;
+  int* plain;
+};
+
+HostView host_view(Workspace& ws) {
+  HostView v;
+  v.stat = ws.host;
+  v.series_cert = v.stat + 2 * ws.cols * kStat;
+  v.col_scale = v.series_cert + ws.cols;
+  v.done = reinterpret_cast<int*>(v.col_scale + ws.cols);
+  v.terms = v.done + ws.tiles;
+  v.active = v.terms + ws.tiles;
+  v.plain = v.active + ws.tiles;
+  return v;
+}
+
+cpaa_status read_back(Workspace& ws, hipStream_t st) {
+  HostView v = host_view(ws);
+  CPAA_HIP(collapse_stats(ws, st));
+  CPAA_HIP(hipMemcpyAsync(v.stat, ws.stat, 2 * ws.cols * kStat * sizeof(double),
+                          hipMemcpyDeviceToHost, st));
+  CPAA_HIP(hipMemcpyAsync(v.series_cert, ws.series_cert, ws.cols * sizeof(double),
+                          hipMemcpyDeviceToHost, st));
+  CPAA_HIP(hipMemcpyAsync(v.done, ws.done, ws.tiles * sizeof(int), hipMemcpyDeviceToHost, st));
+  CPAA_HIP(hipMemcpyAsync(v.terms, ws.terms, ws.tiles * sizeof(int), hipMemcpyDeviceToHost, st));
+  CPAA_HIP(hipStreamSynchronize(st));
+  return CPAA_OK;
+}
+
+inline double stat_at(Workspace& ws, int phase, int64_t col, int f) {
+  return host_view(ws).stat[(phase * ws.cols + col) * kStat + f];
+}
+
+cpaa_status check_p_stats(Workspace& ws, int64_t col) {
+  const double sum = stat_at(ws, 0, col, 0);
+  const double neg = stat_at(ws, 0, col, 4);
+  const double bad = stat_at(ws, 0, col, 5);
+  if (bad != 0.0 || !std::isfinite(sum)) {
+    set_error("personalization vector has non-finite entries");
+    return CPAA_EINVAL;
+  }
+  if (neg != 0.0) {
+    set_error("personalization vector has negative entries");
+    return CPAA_EINVAL;
+  }
+  if (std::fabs(sum - 1.0) > 1e-9) {
+    set_error("personalization vector must sum to 1 (sum = " + std::to_string(sum) + ")");
+    return CPAA_EINVAL;
+  }
+  return CPAA_OK;
+}
+
+// ||x - (I-cP)^{-1} b||_1 <= ||r||_1 / (1-c) for column-stochastic P.  The
+// computed ||r||_1 is inflated by the kernels' bound on the rounding of r
+// (round), by the rounding of x = D acc (u * mass) and by the rounding of the
+// n-term sum itself, so the reported figure bounds the error of the x returned.
+double rigorous_bound(const cpaa_plan_s* pl, double resid_l1, double round, double mass) {
+  const double u = 0x1p-53;
+  const double sum_err = 1.0 + 2.0 * u * static_cast<double>(pl->n);
+  return (resid_l1 * sum_err + round) / (1.0 - pl->c) + u * std::fabs(mass);
+}
+
+// RAII device buffers for host-pointer I/O
+struct TempDev {
+  void* p = nullptr;
+  ~TempDev() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+}  // namespace
+}  // namespace cpaa
+
+using namespace cpaa;
+
+extern "C" cpaa_status cpaa_solve(cpaa_plan_t pl, const double* p, double tol, const double* x0,
+                                  double* x, cpaa_report* rep, void* stream) {
+  set_error("");
+  if (!pl || !p || !x) {
+    set_error("cpaa_solve: null argument");
+    return CPAA_EINVAL;
+  }
+  if (!(tol > 0.0) || !std::isfinite(tol)) {
+    set_error("tol must be positive and finite");
+    return CPAA_EINVAL;
+  }
+  if (pl->num_graphs > 1) {
+    set_error("block-diagonal plans are solved with cpaa_solve_graphs");
+    return CPAA_EINVAL;
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  cpaa_status s = ensure_workspace(pl, pl->ws1, 1, 1);
+  if (s != CPAA_OK) return s;
+  Workspace& ws = pl->ws1;
+  const int n = pl->n;
+  const double c = pl->c;
+
+  TempDev tp, tx0, tx;
+  const double* dp = p;
+  const double* dx0 = x0;
+  double* dx = x;
+  if (!pl->opts.io_device) {
+    if (hipMalloc(&tp.p, n * sizeof(double)) != hipSuccess ||
+        hipMalloc(&tx.p, n * sizeof(double)) != hipSuccess ||
+        (x0 && hipMalloc(&tx0.p, n * sizeof(double)) != hipSuccess)) {
+      (void)hipGetLastError();
+      set_error("device allocation for host I/O failed");
+      return CPAA_ENOMEM;
+    }
+    CPAA_HIP(hipMemcpyAsync(tp.p, p, n * sizeof(double), hipMemcpyHostToDevice, st));
+    if (x0) CPAA_HIP(hipMemcpyAsync(tx0.p, x0, n * sizeof(double), hipMemcpyHostToDevice, st));
+    dp = static_cast<const double*>(tp.p);
+    dx0 = x0 ? static_cast<const double*>(tx0.p) : nullptr;
+    dx = static_cast<double*>(tx.p);
+  }
+
+  TermTimer timer{pl, pl->opts.time_kernels != 0};
+  std::vector<int> series_terms;
+  cpaa_report R;
+  std::memset(&R, 0, sizeof(R));
+  CPAA_HIP(hipEventRecord(pl->ev_begin, st));
+  CPAA_HIP(fill_f64(ws.stat_slots, 0.0, (size_t)2 * kSlots * ws.cols * kStat, st));
+
+  bool warm = dx0 != nullptr;
+  bool p_checked = false;
+  double q0 = 0.0;  // ||D^{-1/2} b'||^2 of the first series' right-hand side
+  bool skip_series = false;
+  if (warm) {
+    CPAA_HIP(load_x0_w1(pl, ws, dx0, st));
+    // b = (1-c) p only (no series start), then r0 = b - (I - cP) x0
+    CPAA_HIP(init_w1(pl, ws, dp, 1.0 - c, false, true, false, st));
+    CPAA_HIP(residual_w1(pl, ws, st));
+    if ((s = read_back(ws, st)) != CPAA_OK) return s;
+    if ((s = check_p_stats(ws, 0)) != CPAA_OK) return s;
+    p_checked = true;
+    const double r0 = stat_at(ws, 1, 0, 0);
+    const double bnorm = (1.0 - c) * stat_at(ws, 0, 0, 0);
+    const bool finite = stat_at(ws, 0, 0, 1) == 0.0 && stat_at(ws, 1, 0, 5) == 0.0 &&
+                        std::isfinite(r0);
+    if (!finite || !(r0 < bnorm)) {
+      warm = false;
+      R.fallback_used = 1;
+    } else if (r0 / (1.0 - c) <= tol) {
+      skip_series = true;
+    } else {
+      q0 = stat_at(ws, 1, 0, 2);
+      // series on b' = r0, added to acc = D^{-1} x0
+      CPAA_HIP(init_w1(pl, ws, ws.r, 1.0, true, false, true, st));
+    }
+  }
+  if (!warm) {
+    CPAA_HIP(fill_f64(ws.stat_slots, 0.0, (size_t)kSlots * ws.cols * kStat, st));
+    CPAA_HIP(init_w1(pl, ws, dp, 1.0 - c, false, true, true, st));
+    if ((s = read_back(ws, st)) != CPAA_OK) return s;
+    if (!p_checked && (s = check_p_stats(ws, 0)) != CPAA_OK) return s;
+    q0 = stat_at(ws, 0, 0, 2);
+  }
+
+  const double target_main = 0.5 * tol;
+  int k_cap = 0;
+  if (!skip_series) {
+    k_cap = apriori_terms(pl, q0, target_main);
+    const int k_min = warm ? 1 : std::min(mass_rule_terms(pl, target_main), k_cap);
+    if ((s = run_series(pl, ws, term_w1, 0, k_cap, k_min, target_main, timer, st)) != CPAA_OK)
+      return s;
+  }
+  series_terms.push_back(k_cap);
+
+  double bound = 0.0;
+  for (;;) {
+    CPAA_HIP(fill_f64(ws.stat_slots + (size_t)kSlots * ws.cols * kStat, 0.0,
+                      (size_t)kSlots * ws.cols * kStat, st));
+    CPAA_HIP(residual_w1(pl, ws, st));
+    if ((s = read_back(ws, st)) != CPAA_OK) return s;
+    HostView hv = host_view(ws);
+    const int ran = hv.done[0] ? hv.terms[0] : series_terms.back();
+    series_terms.back() = skip_series && series_terms.size() == 1 ? 0 : ran;
+    if (series_terms.size() == 1) {
+      R.terms = series_terms[0];
+    } else {
+      R.refine_terms += series_terms.back();
+    }
+    R.series_cert = hv.series_cert[0];
+    R.resid_l1 = stat_at(ws, 1, 0, 0);
+    R.resid_max = stat_at(ws, 1, 0, 1);
+    R.mass = stat_at(ws, 1, 0, 3);
+    bound = rigorous_bound(pl, R.resid_l1, stat_at(ws, 1, 0, 4), R.mass);
+    if (bound <= tol || !std::isfinite(bound) || R.refinements >= pl->opts.max_refine) break;
+    // correction series on b' = r: x += x_M(r)
+    const double target_ref = 0.25 * tol;
+    const int kr = apriori_terms(pl, stat_at(ws, 1, 0, 2), target_ref);
+    CPAA_HIP(init_w1(pl, ws, ws.r, 1.0, true, false, true, st));
+    R.refinements++;
+    series_terms.push_back(kr);
+    if ((s = run_series(pl, ws, term_w1, (int)series_terms.size() - 1, kr, 1, target_ref, timer,
+                        st)) != CPAA_OK)
+      return s;
+  }
+  R.cert_bound = bound;
+  R.certified = (bound <= tol) ? 1 : 0;
+  const double scale = pl->opts.normalize ? 1.0 / R.mass : 1.0;
+  CPAA_HIP(finalize_w1(pl, ws, dx, scale, st));
+  CPAA_HIP(hipEventRecord(pl->ev_end, st));
+  if (!pl->opts.io_device) CPAA_HIP(hipMemcpyAsync(x, dx, n * sizeof(double), hipMemcpyDeviceToHost, st));
+  CPAA_HIP(hipStreamSynchronize(st));
+  float ms = 0.f;
+  CPAA_HIP(hipEventElapsedTime(&ms, pl->ev_begin, pl->ev_end));
+  R.ms_total = ms;
+  timer.total(series_terms, &R.ms_terms, &R.term_launches);
+  if (pl->opts.normalize) R.mass = 1.0;
+  R.edges = pl->nnz * static_cast<int64_t>(R.terms + R.refine_terms);
+  if (rep) *rep = R;
+  if (!R.certified) {
+    set_error("tolerance not certified: bound " + std::to_string(bound));
+    return CPAA_ENOCONV;
+  }
+  return CPAA_OK;
+}
+
+// ----------------------------------------------------------------------------
+// Batched solves: tiles of W right-hand sides, one SpMM kernel per term.
+// ----------------------------------------------------------------------------
+extern "C" cpaa_status cpaa_solve_batched(cpaa_plan_t pl, int32_t B, const double* P, int64_t ldp,
+                                          double tol, const double* X0, int64_t ldx0, double* X,
+                                          int64_t ldx, cpaa_report* reps, void* stream) {
+  set_error("");
+  if (!pl || !P || !X || B <= 0) {
+    set_error("cpaa_solve_batched: null argument or B <= 0");
+    return CPAA_EINVAL;
+  }
+  if (!(tol > 0.0) || !std::isfinite(tol)) {
+    set_error("tol must be positive and finite");
+    return CPAA_EINVAL;
+  }
+  if (pl->num_graphs > 1) {
+    set_error("block-diagonal plans are solved with cpaa_solve_graphs");
+    return CPAA_EINVAL;
+  }
+  const int64_t n = pl->n;
+  if (ldp < n || ldx < n || (X0 && ldx0 < n)) {
+    set_error("leading dimensions must be >= n");
+    return CPAA_EINVAL;
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  int W = pl->tile_w;
+  while (W > 8 && W / 2 >= B) W /= 2;
+  const int T = (B + W - 1) / W;
+  cpaa_status s = ensure_workspace(pl, pl->wst, W, T);
+  if (s != CPAA_OK) return s;
+  Workspace& ws = pl->wst;
+  const double c = pl->c;
+  const int64_t cols = ws.cols;
+
+  TempDev tP, tX0, tX;
+  const double* dP = P;
+  const double* dX0 = X0;
+  double* dX = X;
+  int64_t lp = ldp, lx0 = ldx0, lx = ldx;
+  if (!pl->opts.io_device) {
+    const size_t bytes = (size_t)B * n * sizeof(double);
+    if (hipMalloc(&tP.p, bytes) != hipSuccess || hipMalloc(&tX.p, bytes) != hipSuccess ||
+        (X0 && hipMalloc(&tX0.p, bytes) != hipSuccess)) {
+      (void)hipGetLastError();
+      set_error("device allocation for host I/O failed");
+      return CPAA_ENOMEM;
+    }
+    CPAA_HIP(hipMemcpy2DAsync(tP.p, n * sizeof(double), P, ldp * sizeof(double),
+                              n * sizeof(double), B, hipMemcpyHostToDevice, st));
+    if (X0)
+      CPAA_HIP(hipMemcpy2DAsync(tX0.p, n * sizeof(double), X0, ldx0 * sizeof(double),
+                                n * sizeof(double), B, hipMemcpyHostToDevice, st));
+    dP = static_cast<const double*>(tP.p);
+    dX0 = X0 ? static_cast<const double*>(tX0.p) : nullptr;
+    dX = static_cast<double*>(tX.p);
+    lp = lx0 = lx = n;
+  }
+
+  TermTimer timer{pl, pl->opts.time_kernels != 0};
+  std::vector<int> series_terms;
+  std::vector<int> terms_main(T, 0), refine_terms(T, 0), refinements(T, 0);
+  std::vector<int> fallback(cols, 0);
+  std::vector<double> bound(cols, 0.0), r_l1(cols, 0.0), r_max(cols, 0.0), mass(cols, 0.0),
+      q_r(cols, 0.0), scert(cols, -1.0);
+  HostView hv = host_view(ws);
+
+  CPAA_HIP(hipEventRecord(pl->ev_begin, st));
+  CPAA_HIP(fill_f64(ws.stat_slots, 0.0, (size_t)2 * kSlots * cols * kStat, st));
+  auto validate_cols = [&]() -> cpaa_status {
+    for (int j = 0; j < B; ++j) {
+      cpaa_status e = check_p_stats(ws, j);
+      if (e != CPAA_OK) {
+        set_error(std::string("column ") + std::to_string(j) + ": " + cpaa_last_error());
+        return e;
+      }
+    }
+    return CPAA_OK;
+  };
+
+  const double target_main = 0.5 * tol;
+  int k_min;
+  std::vector<double> q(cols, 0.0);
+  if (dX0) {
+    CPAA_HIP(load_x0_tile(pl, ws, dX0, lx0, B, st));
+    CPAA_HIP(init_tile(pl, ws, dP, lp, B, 1.0 - c, false, true, false, st));
+    CPAA_HIP(residual_tile(pl, ws, nullptr, st));
+    if ((s = read_back(ws, st)) != CPAA_OK) return s;
+    if ((s = validate_cols()) != CPAA_OK) return s;
+    for (int64_t j = 0; j < cols; ++j) {
+      const double r0 = stat_at(ws, 1, j, 0);
+      const double bnorm = (1.0 - c) * stat_at(ws, 0, j, 0);
+      const bool finite = stat_at(ws, 0, j, 1) == 0.0 && stat_at(ws, 1, j, 5) == 0.0 &&
+                          std::isfinite(r0);
+      const bool use_warm = j < B && finite && r0 < bnorm;
+      hv.plain[j] = use_warm ? 0 : 1;
+      fallback[j] = (j < B && !use_warm) ? 1 : 0;
+      q[j] = use_warm ? stat_at(ws, 1, j, 2) : stat_at(ws, 0, j, 2);
+    }
+    CPAA_HIP(hipMemcpyAsync(ws.plain, hv.plain, cols * sizeof(int), hipMemcpyHostToDevice, st));
+    CPAA_HIP(init_tile_from_r(pl, ws, nullptr, ws.plain, st));
+    k_min = 1;
+  } else {
+    CPAA_HIP(init_tile(pl, ws, dP, lp, B, 1.0 - c, false, true, true, st));
+    if ((s = read_back(ws, st)) != CPAA_OK) return s;
+    if ((s = validate_cols()) != CPAA_OK) return s;
+    for (int64_t j = 0; j < cols; ++j) q[j] = stat_at(ws, 0, j, 2);
+    k_min = mass_rule_terms(pl, target_main);
+  }
+  int k_cap = 0;
+  for (int64_t j = 0; j < cols; ++j) k_cap = std::max(k_cap, apriori_terms(pl, q[j], target_main));
+  k_min = std::min(k_min, k_cap);
+  if ((s = run_series(pl, ws, term_tile, 0, k_cap, k_min, target_main, timer, st)) != CPAA_OK)
+    return s;
+  series_terms.push_back(k_cap);
+
+  std::vector<int> active(T, 1);
+  bool first = true;
+  bool masked = false;
+  for (int round = 0;; ++round) {
+    CPAA_HIP(fill_f64(ws.stat_slots + (size_t)kSlots * cols * kStat, 0.0,
+                      (size_t)kSlots * cols * kStat, st));
+    CPAA_HIP(residual_tile(pl, ws, masked ? ws.active : nullptr, st));
+    if ((s = read_back(ws, st)) != CPAA_OK) return s;
+    int ran_max = 0;
+    for (int t = 0; t < T; ++t) {
+      if (!active[t]) continue;
+      const int ran = hv.terms[t];
+      ran_max = std::max(ran_max, ran);
+      if (first) terms_main[t] = ran;
+      else refine_terms[t] += ran;
+      for (int jj = 0; jj < W; ++jj) {
+        const int64_t j = (int64_t)t * W + jj;
+        r_l1[j] = stat_at(ws, 1, j, 0);
+        r_max[j] = stat_at(ws, 1, j, 1);
+        q_r[j] = stat_at(ws, 1, j, 2);
+        mass[j] = stat_at(ws, 1, j, 3);
+        scert[j] = hv.series_cert[j];
+        bound[j] = rigorous_bound(pl, r_l1[j], stat_at(ws, 1, j, 4), mass[j]);
+      }
+    }
+    series_terms.back() = ran_max;
+    first = false;
+    bool any = false;
+    int k_ref = 0;
+    const double target_ref = 0.25 * tol;
+    for (int t = 0; t < T; ++t) {
+      bool need = false;
+      for (int jj = 0; jj < W; ++jj) {
+        const int64_t j = (int64_t)t * W + jj;
+        if (j < B && (bound[j] > tol) && std::isfinite(bound[j])) need = true;
+      }
+      active[t] = (need && refinements[t] < pl->opts.max_refine) ? 1 : 0;
+      if (active[t]) {
+        any = true;
+        for (int jj = 0; jj < W; ++jj)
+          k_ref = std::max(k_ref, apriori_terms(pl, q_r[(int64_t)t * W + jj], target_ref));
+      }
+    }
+    if (!any) break;
+    for (int t = 0; t < T; ++t) {
+      hv.active[t] = active[t];
+      refinements[t] += active[t];
+    }
+    CPAA_HIP(hipMemcpyAsync(ws.active, hv.active, T * sizeof(int), hipMemcpyHostToDevice, st));
+    masked = true;
+    CPAA_HIP(init_tile_from_r(pl, ws, ws.active, nullptr, st));
+    series_terms.push_back(k_ref);
+    if ((s = run_series(pl, ws, term_tile, (int)series_terms.size() - 1, k_ref, 1, target_ref,
+                        timer, st, ws.active)) != CPAA_OK)
+      return s;
+  }
+  const double* col_scale = nullptr;
+  if (pl->opts.normalize) {
+    for (int64_t j = 0; j < cols; ++j) hv.col_scale[j] = mass[j] != 0.0 ? 1.0 / mass[j] : 1.0;
+    CPAA_HIP(hipMemcpyAsync(ws.col_scale, hv.col_scale, cols * sizeof(double),
+                            hipMemcpyHostToDevice, st));
+    col_scale = ws.col_scale;
+  }
+  CPAA_HIP(finalize_tile(pl, ws, dX, lx, B, col_scale, st));
+  CPAA_HIP(hipEventRecord(pl->ev_end, st));
+  if (!pl->opts.io_device)
+    CPAA_HIP(hipMemcpy2DAsync(X, ldx * sizeof(double), dX, n * sizeof(double), n * sizeof(double),
+                              B, hipMemcpyDeviceToHost, st));
+  CPAA_HIP(hipStreamSynchronize(st));
+  float ms = 0.f;
+  CPAA_HIP(hipEventElapsedTime(&ms, pl->ev_begin, pl->ev_end));
+  double ms_terms = 0.0;
+  int64_t launches = 0;
+  timer.total(series_terms, &ms_terms, &launches);
+  bool all_ok = true;
+  for (int j = 0; j < B; ++j) {
+    const int t = j / W;
+    cpaa_report R;
+    std::memset(&R, 0, sizeof(R));
+    R.terms = terms_main[t];
+    R.refine_terms = refine_terms[t];
+    R.refinements = refinements[t];
+    R.cert_bound = bound[j];
+    R.certified = bound[j] <= tol ? 1 : 0;
+    R.fallback_used = fallback[j];
+    R.resid_l1 = r_l1[j];
+    R.resid_max = r_max[j];
+    R.mass = pl->opts.normalize ? 1.0 : mass[j];
+    R.series_cert = scert[j];
+    R.ms_total = ms;
+    R.ms_terms = ms_terms;
+    R.term_launches = launches;
+    R.edges = pl->nnz * static_cast<int64_t>(R.terms + R.refine_terms);
+    all_ok = all_ok && R.certified;
+    if (reps) reps[j] = R;
+  }
+  if (!all_ok) {
+    set_error("tolerance not certified for every column");
+    return CPAA_ENOCONV;
+  }
+  return CPAA_OK;
+}

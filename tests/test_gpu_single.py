@@ -1,0 +1,246 @@
+"""GPU parity of the single-vector CPAA path (cpaa_solve) against the FP64 oracle.
+
+Bar: ||x - pi||_1 <= tol (1e-6 unless stated), and the library's own FP64
+certificate must bound the true error.  pi comes from the oracle's dense solve
+(small graphs) or its power method certified to 1e-13.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+
+pytestmark = pytest.mark.gpu
+C = 0.85
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2112_01743_amd import binding
+    binding.lib()      # raises if the HIP library is missing
+    return torch
+
+
+def _dev(torch, a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _truth(g, p):
+    if g.n <= 2500:
+        return oracle.pagerank_exact(g, p, C)
+    return oracle.pagerank_power(g, p, C, tol=1e-13)[0]
+
+
+def _note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _solve(torch, g, p, tol=1e-6, x0=None, **opts):
+    from paper_2112_01743_amd import Plan
+    plan = Plan.from_graph(g, C, **opts)
+    x, rep = plan.solve(_dev(torch, p), tol, None if x0 is None else _dev(torch, x0))
+    torch.cuda.synchronize()
+    return x.cpu().numpy(), rep, plan
+
+
+def _assert_parity(g, p, x, rep, tol):
+    pi = _truth(g, p)
+    err = np.abs(x - pi).sum()
+    assert rep["status"] == "CPAA_OK", rep
+    assert rep["certified"] == 1
+    assert err <= tol, (err, rep)
+    # the certificate is rigorous for the returned x; 2e-13 covers the error of the truth
+    assert err <= rep["cert_bound"] * (1 + 1e-9) + 2e-13, (err, rep)
+    return err
+
+
+SMALL = {
+    "cycle7": lambda: gg.cycle(7),
+    "path6": lambda: gg.path(6),
+    "star6": lambda: gg.star(6),
+    "complete5": lambda: gg.complete(5),
+    "edge2": lambda: gg.path(2),
+    "random60": lambda: gg.random_connected(60, 6.0, seed=13),
+    "random777": lambda: gg.random_connected(777, 5.0, seed=14),
+    "er2000": lambda: gg.erdos_renyi(2000, 10, seed=2),
+}
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+@pytest.mark.parametrize("tol", [1e-6, 1e-9])
+def test_small_graphs_uniform_and_source(torch_cuda, name, tol):
+    g = SMALL[name]()
+    _note(f"case {name} n={g.n} nnz={g.nnz} tol={tol}")
+    for p in (gg.uniform_personalization(g.n), gg.source_personalization(g.n, [g.n // 2])[0]):
+        x, rep, _ = _solve(torch_cuda, g, p, tol)
+        _assert_parity(g, p, x, rep, tol)
+
+
+def test_config0_er_10k_tail_1e10(torch_cuda):
+    """Erdos-Renyi n=10,000, average degree 10, p = e/n; terms chosen so the
+    coefficient tail is below 1e-10 and the result certified to 1e-10."""
+    g = gg.erdos_renyi(10000, 10, seed=2112000)
+    _note(f"config0 n={g.n} nnz={g.nnz}")
+    p = gg.uniform_personalization(g.n)
+    x, rep, _ = _solve(torch_cuda, g, p, 1e-10)
+    pi = oracle.pagerank_power(g, p, C, tol=1e-14)[0]
+    err = np.abs(x - pi).sum()
+    assert rep["certified"] == 1 and err <= 1e-10, (err, rep)
+    assert rep["terms"] + rep["refine_terms"] >= oracle.terms_for_mass_error(C, 1e-10) - 5
+
+
+def test_series_term_parity_with_oracle_cpaa(torch_cuda):
+    """With the term count pinned (k_max = M, no refinement) the GPU result is
+    the FP32-recurrence value of x_M; it must match the oracle's FP64 x_M to
+    the FP32 rounding level."""
+    g = gg.chung_lu(5000, 8, 2.5, seed=77)
+    p = gg.source_personalization(g.n, [3])[0]
+    for M in (1, 2, 5, 12, 30):
+        x, rep, _ = _solve(torch_cuda, g, p, 1e-14, k_max=M, max_refine=0)
+        assert rep["terms"] == M and rep["refinements"] == 0
+        ref = oracle.cpaa(g, (1 - C) * p, C, M)
+        err = np.abs(x - ref).sum()
+        _note(f"M={M} term-parity L1={err:.3e}")
+        assert err <= 2e-6 * max(1.0, np.abs(ref).sum()), (M, err)
+
+
+def test_hub_rows_split_across_workgroups(torch_cuda):
+    """A star with 20,000 leaves plus a ring among the leaves: the hub row is
+    longer than one work item and is cut into chunks (atomic fix-up)."""
+    n = 20001
+    leaves = np.arange(1, n)
+    u = np.concatenate([np.zeros(n - 1, dtype=np.int64), leaves])
+    v = np.concatenate([leaves, np.roll(leaves, 1)])
+    g = gg.csr_from_edges(n, u, v)
+    from paper_2112_01743_amd import Plan
+    info = Plan.from_graph(g, C).info()
+    assert info["split_rows"] >= 1
+    for p in (gg.uniform_personalization(n), gg.source_personalization(n, [0])[0],
+              gg.source_personalization(n, [17])[0]):
+        for rep_i in range(2):     # second solve checks the split slots were reset
+            x, rep, _ = _solve(torch_cuda, g, p, 1e-7)
+            _assert_parity(g, p, x, rep, 1e-7)
+
+
+def test_power_law_mid_size(torch_cuda):
+    g = gg.chung_lu(200000, 16, 2.1, seed=2112001, dmax=50000)
+    _note(f"chung-lu n={g.n} nnz={g.nnz} maxdeg={np.diff(g.row_ptr).max()}")
+    for p in (gg.uniform_personalization(g.n), gg.source_personalization(g.n, [0])[0],
+              gg.source_personalization(g.n, [g.n - 1])[0]):
+        x, rep, _ = _solve(torch_cuda, g, p, 1e-6)
+        _assert_parity(g, p, x, rep, 1e-6)
+
+
+@pytest.mark.parametrize("npt", [4, 8, 16])
+def test_work_item_sizes_agree(torch_cuda, npt):
+    g = gg.chung_lu(30000, 12, 2.3, seed=5, dmax=8000)
+    p = gg.uniform_personalization(g.n)
+    x, rep, _ = _solve(torch_cuda, g, p, 1e-8, nnz_per_thread=npt)
+    _assert_parity(g, p, x, rep, 1e-8)
+
+
+@pytest.mark.parametrize("remap", [0, 1])
+def test_xcd_remap_agrees(torch_cuda, remap):
+    g = gg.perturbed_grid(120, 0.05, 0.01, seed=9)
+    p = gg.source_personalization(g.n, [g.n // 3])[0]
+    x, rep, _ = _solve(torch_cuda, g, p, 1e-7, xcd_remap=remap)
+    _assert_parity(g, p, x, rep, 1e-7)
+
+
+def test_warm_start_good_guess_needs_fewer_terms(torch_cuda):
+    g = gg.chung_lu(20000, 10, 2.2, seed=31)
+    p = gg.source_personalization(g.n, [5])[0]
+    pi = _truth(g, p)
+    _, plain, _ = _solve(torch_cuda, g, p, 1e-7)
+    rng = gg.philox(3)
+    x0 = np.abs(pi * (1 + 1e-3 * rng.standard_normal(g.n)))
+    x0 /= x0.sum()
+    x, rep, _ = _solve(torch_cuda, g, p, 1e-7, x0=x0)
+    _assert_parity(g, p, x, rep, 1e-7)
+    assert rep["fallback_used"] == 0
+    assert rep["terms"] < plain["terms"], (rep["terms"], plain["terms"])
+
+
+@pytest.mark.parametrize("kind", ["nan", "zeros", "bad"])
+def test_warm_start_fallback(torch_cuda, kind):
+    g = gg.random_connected(300, 5.0, seed=8)
+    p = gg.source_personalization(g.n, [7])[0]
+    x0 = {"nan": np.full(g.n, np.nan), "zeros": np.zeros(g.n),
+          "bad": np.full(g.n, 50.0)}[kind]
+    x, rep, _ = _solve(torch_cuda, g, p, 1e-8, x0=x0)
+    assert rep["fallback_used"] == 1
+    _assert_parity(g, p, x, rep, 1e-8)
+
+
+def test_normalize_matches_alg1_final_step(torch_cuda):
+    g = gg.random_connected(500, 6.0, seed=4)
+    p = gg.uniform_personalization(g.n)
+    x, rep, _ = _solve(torch_cuda, g, p, 1e-9, normalize=1)
+    assert abs(x.sum() - 1.0) < 1e-12
+    assert np.abs(x - _truth(g, p)).sum() < 1e-9
+
+
+def test_host_pointer_io(torch_cuda):
+    from paper_2112_01743_amd import binding as B
+    g = gg.random_connected(400, 5.0, seed=6)
+    p = np.ascontiguousarray(gg.source_personalization(g.n, [9])[0])
+    x = np.zeros(g.n)
+    plan = B.Plan.from_graph(g, C, io_device=0)
+    st, rep = B.cpaa_solve(plan.handle, p.ctypes.data, 1e-8, None, x.ctypes.data)
+    assert st == B.CPAA_OK, B.cpaa_last_error()
+    assert np.abs(x - _truth(g, p)).sum() <= 1e-8
+
+
+def test_invalid_personalization_rejected(torch_cuda):
+    from paper_2112_01743_amd import binding as B
+    g = gg.cycle(10)
+    from paper_2112_01743_amd import Plan
+    plan = Plan.from_graph(g, C)
+    out = torch_cuda.full((g.n,), 7.0, dtype=torch_cuda.float64, device="cuda")
+    for bad in (np.full(g.n, 0.2), np.r_[-0.1, np.full(g.n - 1, 1.1 / (g.n - 1))],
+                np.r_[np.nan, np.full(g.n - 1, 1.0 / (g.n - 1))]):
+        st, _ = B.cpaa_solve(plan.handle, _dev(torch_cuda, bad).data_ptr(), 1e-6, None,
+                             out.data_ptr())
+        assert st == B.CPAA_EINVAL
+        assert float(out[0]) == 7.0     # outputs untouched on error
+    st, _ = B.cpaa_solve(plan.handle, _dev(torch_cuda, np.full(g.n, 0.1)).data_ptr(), -1.0, None,
+                         out.data_ptr())
+    assert st == B.CPAA_EINVAL
+
+
+def test_term_cap_reports_noconv_with_best_effort(torch_cuda):
+    g = gg.random_connected(300, 5.0, seed=12)
+    p = gg.uniform_personalization(g.n)
+    x, rep, _ = _solve(torch_cuda, g, p, 1e-9, k_max=3, max_refine=0)
+    assert rep["status"] == "CPAA_ENOCONV" and rep["certified"] == 0
+    ref = oracle.cpaa(g, (1 - C) * p, C, 3)
+    assert np.abs(x - ref).sum() < 1e-6
+    err = np.abs(x - _truth(g, p)).sum()
+    assert err <= rep["cert_bound"] * (1 + 1e-9) + 2e-13
+
+
+def test_repeated_solves_reuse_plan(torch_cuda):
+    from paper_2112_01743_amd import Plan
+    g = gg.chung_lu(50000, 16, 2.1, seed=44, dmax=20000)
+    plan = Plan.from_graph(g, C)
+    p = _dev(torch_cuda, gg.uniform_personalization(g.n))
+    outs = [plan.solve(p, 1e-6)[0].cpu().numpy() for _ in range(3)]
+    truth = _truth(g, gg.uniform_personalization(g.n))
+    # split hub rows meet through FP32 atomics, so runs agree to rounding, not bitwise
+    for o in outs:
+        assert np.abs(o - truth).sum() <= 1e-6
+    assert np.abs(outs[0] - outs[1]).sum() < 1e-7 and np.abs(outs[1] - outs[2]).sum() < 1e-7
+
+
+def test_kernel_timing_report(torch_cuda):
+    g = gg.chung_lu(100000, 16, 2.1, seed=45, dmax=30000)
+    x, rep, _ = _solve(torch_cuda, g, gg.uniform_personalization(g.n), 1e-6, time_kernels=1)
+    assert rep["term_launches"] == rep["terms"] + rep["refine_terms"]
+    assert rep["ms_terms"] > 0 and rep["ms_total"] >= rep["ms_terms"]
+    assert rep["edges"] == g.nnz * (rep["terms"] + rep["refine_terms"])

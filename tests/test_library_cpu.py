@@ -1,0 +1,88 @@
+"""Host-side checks of the C-ABI library: it loads, exports every function
+include/cpaa.h declares, and rejects bad graphs before touching a GPU."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+from paper_2112_01743_amd import binding as B
+
+
+def test_library_exports_every_declared_function():
+    names = B.header_functions()
+    assert {"cpaa_plan", "cpaa_solve", "cpaa_solve_batched", "cpaa_solve_graphs",
+            "cpaa_plan_destroy", "cpaa_last_error", "cpaa_default_opts",
+            "cpaa_plan_info_get"} <= set(names)
+    L = B.lib()
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_library_exports_nothing_else():
+    import subprocess
+    out = subprocess.run(["nm", "-D", "--defined-only", B.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = sorted(l.split()[-1] for l in out.splitlines() if " T " in l)
+    assert exported == B.header_functions()
+
+
+def test_struct_sizes_match_header_layout():
+    assert ctypes.sizeof(B.cpaa_opts) == 9 * 4
+    assert ctypes.sizeof(B.cpaa_report) == 6 * 4 + 7 * 8 + 2 * 8
+    assert ctypes.sizeof(B.cpaa_csr) == 56
+
+
+def test_default_opts():
+    o = B.cpaa_default_opts()
+    assert o.max_refine == 2 and o.validate == 1 and o.io_device == 1 and o.xcd_remap == -1
+
+
+def _plan_status(rp, ci, c=0.85, **kw):
+    rp = np.asarray(rp, dtype=np.int32)
+    ci = np.asarray(ci, dtype=np.int32)
+    csr = B.cpaa_csr(n=len(rp) - 1, nnz=len(ci), row_ptr=rp.ctypes.data, col_idx=ci.ctypes.data,
+                     num_graphs=0, graph_ptr=None, on_device=0)
+    o = B.cpaa_default_opts()
+    for k, v in kw.items():
+        setattr(o, k, v)
+    h = ctypes.c_void_p()
+    st = B.lib().cpaa_plan(ctypes.byref(csr), c, ctypes.byref(o), ctypes.byref(h))
+    if st == 0:
+        B.lib().cpaa_plan_destroy(h)
+    return st
+
+
+@pytest.mark.parametrize("case,rp,ci,status", [
+    ("asymmetric", [0, 1, 2, 2], [1, 2], B.CPAA_EISOLATED),
+    ("asymmetric2", [0, 1, 3, 4], [1, 0, 2, 0], B.CPAA_ENOTSYM),
+    ("selfloop", [0, 2, 3], [0, 1, 0], B.CPAA_ESELFLOOP),
+    ("isolated", [0, 1, 2, 2], [1, 0], B.CPAA_EISOLATED),
+    ("unsorted", [0, 2, 3, 4], [2, 1, 0, 0], B.CPAA_EPATTERN),
+    ("duplicate", [0, 2, 3], [1, 1, 0], B.CPAA_EPATTERN),
+    ("out_of_range", [0, 1, 2], [5, 0], B.CPAA_EPATTERN),
+    ("bad_rowptr", [0, 2, 1], [1, 0], B.CPAA_EPATTERN),
+])
+def test_plan_rejects_bad_patterns(case, rp, ci, status):
+    assert _plan_status(rp, ci) == status, (case, B.cpaa_last_error())
+
+
+def test_plan_rejects_bad_damping_and_options():
+    g = gg.cycle(5)
+    assert _plan_status(g.row_ptr, g.col_idx, c=1.0) == B.CPAA_EINVAL
+    assert _plan_status(g.row_ptr, g.col_idx, c=0.0) == B.CPAA_EINVAL
+    assert _plan_status(g.row_ptr, g.col_idx, nnz_per_thread=3) == B.CPAA_EINVAL
+    assert _plan_status(g.row_ptr, g.col_idx, tile_w=7) == B.CPAA_EINVAL
+    assert "tile_w" in B.cpaa_last_error()
+
+
+def test_plan_rejects_edge_across_graph_boundary():
+    # two graphs {0,1} and {2,3} but edge 1-2 crosses
+    rp = np.array([0, 1, 3, 5, 6], dtype=np.int32)
+    ci = np.array([1, 0, 2, 1, 3, 2], dtype=np.int32)
+    gp = np.array([0, 2, 4], dtype=np.int32)
+    csr = B.cpaa_csr(n=4, nnz=6, row_ptr=rp.ctypes.data, col_idx=ci.ctypes.data, num_graphs=2,
+                     graph_ptr=gp.ctypes.data, on_device=0)
+    h = ctypes.c_void_p()
+    st = B.lib().cpaa_plan(ctypes.byref(csr), 0.85, None, ctypes.byref(h))
+    assert st == B.CPAA_EINVAL and "crosses" in B.cpaa_last_error()
