@@ -84,14 +84,15 @@ typedef struct {
   int32_t max_refine;     /* FP64-residual correction series allowed (default 2) */
   int32_t normalize;      /* 1: divide each result by its sum (Alg. 1's last step);
                              plain solves only, changes what tol certifies (see cpaa_solve) */
-  int32_t nnz_per_thread; /* 0 auto; 4, 8 or 16: stored entries per thread of a single-vector
+  int32_t nnz_per_thread; /* 0 auto; 4, 8, 16 or 32: stored entries per thread of a single-vector
                              work item (a workgroup of 256 threads takes 256*this entries and the
                              rows they cover, so rows per wavefront = this*64/degree) */
   int32_t tile_w;         /* 0 auto; 8, 16, 32 or 64: right-hand sides per tile in batched solves */
   int32_t validate;       /* 1 (default): check the pattern (symmetry, loops, order) on the host */
   int32_t io_device;      /* 1 (default): p / x0 / x of solve calls are device pointers; 0: host */
   int32_t time_kernels;   /* 1: time every term kernel with HIP events (report.ms_terms) */
-  int32_t xcd_remap;      /* -1 auto, 0/1: map workgroups to contiguous row ranges per XCD */
+  int32_t xcd_remap;      /* -1 auto (off for single-vector kernels, on for tiled kernels),
+                             0/1: map workgroups to contiguous row ranges per XCD */
 } cpaa_opts;
 
 /* Per-solve report (one per right-hand side in batched calls, one per graph in

@@ -231,8 +231,8 @@ cpaa_status cpaa_plan(const cpaa_csr* g, double c, const cpaa_opts* opts, cpaa_p
   cpaa_default_opts(&o);
   if (opts) o = *opts;
   if (o.nnz_per_thread != 0 && o.nnz_per_thread != 4 && o.nnz_per_thread != 8 &&
-      o.nnz_per_thread != 16) {
-    set_error("nnz_per_thread must be 0, 4, 8 or 16");
+      o.nnz_per_thread != 16 && o.nnz_per_thread != 32) {
+    set_error("nnz_per_thread must be 0, 4, 8, 16 or 32");
     return CPAA_EINVAL;
   }
   if (o.tile_w != 0 && o.tile_w != 8 && o.tile_w != 16 && o.tile_w != 32 && o.tile_w != 64) {
@@ -330,8 +330,14 @@ cpaa_status cpaa_plan(const cpaa_csr* g, double c, const cpaa_opts* opts, cpaa_p
   pl->ck.resize(kMaxTerms + 2);
   for (int k = 0; k < kMaxTerms + 2; ++k) pl->ck[k] = 2.0 / pl->s * std::pow(pl->beta, k);
 
-  pl->npt = o.nnz_per_thread ? o.nnz_per_thread : 8;
-  pl->xcd_remap = o.xcd_remap < 0 ? 1 : (o.xcd_remap ? 1 : 0);
+  // Random gathers into a vector larger than one XCD's L2 are latency bound:
+  // large graphs get 32 independent gathers in flight per thread.
+  pl->npt = o.nnz_per_thread ? o.nnz_per_thread : (n >= (1 << 20) ? 32 : 16);
+  // XCD-contiguous row ranges help lattice-like graphs in the tiled kernel but
+  // concentrate the hub rows of power-law graphs on one XCD in the
+  // single-vector kernel, so "auto" enables it for tiles only.
+  pl->xcd_remap = o.xcd_remap < 0 ? 0 : (o.xcd_remap ? 1 : 0);
+  pl->xcd_remap_tile = o.xcd_remap < 0 ? 1 : (o.xcd_remap ? 1 : 0);
   std::vector<WorkItem> items;
   std::vector<int> nch;
   build_items(n, rp, pl->npt, items, nch);

@@ -102,7 +102,8 @@ struct cpaa_plan_s {
   int n_items = 0;
   int n_split_rows = 0;
   int* d_split_nchunks = nullptr;    // [n_split_rows]
-  int xcd_remap = 0;
+  int xcd_remap = 0;                 // single-vector kernels
+  int xcd_remap_tile = 1;            // tiled kernels
 
   // tiled work map (per wavefront)
   cpaa::WorkItem* d_titems = nullptr;

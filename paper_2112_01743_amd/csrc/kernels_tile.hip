@@ -436,7 +436,7 @@ hipError_t term_tile(const cpaa_plan_s* pl, Workspace& ws, int cur, int prev, in
   a.split_count = ws.split_count;
   a.split_nchunks = pl->d_tsplit_nchunks;
   a.n_split = pl->n_tsplit_rows;
-  a.xcd = pl->xcd_remap;
+  a.xcd = pl->xcd_remap_tile;
   const int blocks = (pl->n_titems + kWaves - 1) / kWaves;
   CPAA_LAUNCH_W(k_term_tile, ws.W, dim3(blocks, ws.tiles), st, a);
   return hipGetLastError();
@@ -460,7 +460,7 @@ hipError_t residual_tile(const cpaa_plan_s* pl, Workspace& ws, const int* active
   a.split_count = ws.split_count;
   a.split_nchunks = pl->d_tsplit_nchunks;
   a.n_split = pl->n_tsplit_rows;
-  a.xcd = pl->xcd_remap;
+  a.xcd = pl->xcd_remap_tile;
   const int blocks = (pl->n_titems + kWaves - 1) / kWaves;
   CPAA_LAUNCH_W(k_resid_tile, ws.W, dim3(blocks, ws.tiles), st, a);
   return hipGetLastError();

@@ -351,6 +351,7 @@ hipError_t term_w1(const cpaa_plan_s* pl, Workspace& ws, int cur, int prev, int 
   switch (pl->npt) {
     case 4: hipLaunchKernelGGL(k_term_w1<4>, grid, dim3(kWG), 0, st, a); break;
     case 16: hipLaunchKernelGGL(k_term_w1<16>, grid, dim3(kWG), 0, st, a); break;
+    case 32: hipLaunchKernelGGL(k_term_w1<32>, grid, dim3(kWG), 0, st, a); break;
     default: hipLaunchKernelGGL(k_term_w1<8>, grid, dim3(kWG), 0, st, a); break;
   }
   return hipGetLastError();
@@ -374,6 +375,7 @@ hipError_t residual_w1(const cpaa_plan_s* pl, Workspace& ws, hipStream_t st) {
   switch (pl->npt) {
     case 4: hipLaunchKernelGGL(k_resid_w1<4>, grid, dim3(kWG), 0, st, a); break;
     case 16: hipLaunchKernelGGL(k_resid_w1<16>, grid, dim3(kWG), 0, st, a); break;
+    case 32: hipLaunchKernelGGL(k_resid_w1<32>, grid, dim3(kWG), 0, st, a); break;
     default: hipLaunchKernelGGL(k_resid_w1<8>, grid, dim3(kWG), 0, st, a); break;
   }
   return hipGetLastError();
