@@ -25,7 +25,7 @@ __all__ = [
     "CSR", "philox", "csr_from_edges", "drop_isolated", "erdos_renyi", "chung_lu",
     "perturbed_grid", "uneven_batch", "cycle", "complete", "star", "path",
     "random_connected", "random_sources", "uniform_personalization",
-    "source_personalization", "degrees",
+    "source_personalization", "degrees", "batch_sources", "subgraph", "mpnn_init",
 ]
 
 
@@ -363,6 +363,47 @@ def random_sources(n: int, count: int, seed, replace: bool = False) -> np.ndarra
 def uniform_personalization(n: int) -> np.ndarray:
     """p = e/n (global PageRank)."""
     return np.full(n, 1.0 / n)
+
+
+def batch_sources(g: CSR, seed) -> tuple[np.ndarray, np.ndarray]:
+    """One uniformly random source per graph of a block-diagonal batch.
+
+    Returns (sources as global vertex ids, concatenated personalization vector
+    whose block for graph k is the indicator of its source)."""
+    rng = philox(seed)
+    gp = g.graph_ptr.astype(np.int64)
+    sizes = np.diff(gp)
+    src = gp[:-1] + np.floor(rng.random(sizes.shape[0]) * sizes).astype(np.int64)
+    p = np.zeros(g.n)
+    p[src] = 1.0
+    return src, p
+
+
+def subgraph(g: CSR, k: int) -> CSR:
+    """Graph k of a block-diagonal batch, relabelled from 0."""
+    v0, v1 = int(g.graph_ptr[k]), int(g.graph_ptr[k + 1])
+    e0, e1 = int(g.row_ptr[v0]), int(g.row_ptr[v1])
+    return CSR(n=v1 - v0, row_ptr=(g.row_ptr[v0:v1 + 1] - e0).astype(np.int32),
+               col_idx=(g.col_idx[e0:e1] - v0).astype(np.int32))
+
+
+def mpnn_init(seed, layers: int = 3, hidden: int = 64, in_features: int = 2) -> dict:
+    """Initial parameters of the warm-start network (Glorot-uniform weights,
+    zero biases), FP32.  Keys: w_self{l}, w_nbr{l} (fan_in x hidden), b{l},
+    w_out (hidden), b_out (1)."""
+    rng = philox(seed)
+    params = {}
+    fan_in = in_features
+    for l in range(layers):
+        lim = np.sqrt(6.0 / (fan_in + hidden))
+        params[f"w_self{l}"] = rng.uniform(-lim, lim, (fan_in, hidden)).astype(np.float32)
+        params[f"w_nbr{l}"] = rng.uniform(-lim, lim, (fan_in, hidden)).astype(np.float32)
+        params[f"b{l}"] = np.zeros(hidden, dtype=np.float32)
+        fan_in = hidden
+    lim = np.sqrt(6.0 / (hidden + 1))
+    params["w_out"] = rng.uniform(-lim, lim, hidden).astype(np.float32)
+    params["b_out"] = np.zeros(1, dtype=np.float32)
+    return params
 
 
 def source_personalization(n: int, sources) -> np.ndarray:

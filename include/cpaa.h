@@ -93,6 +93,10 @@ typedef struct {
   int32_t time_kernels;   /* 1: time every term kernel with HIP events (report.ms_terms) */
   int32_t xcd_remap;      /* -1 auto (off for single-vector kernels, on for tiled kernels),
                              0/1: map workgroups to contiguous row ranges per XCD */
+  int32_t autotune;       /* 1: the first cpaa_solve_graphs call times the candidate workgroup
+                             sizes (256, 512, 1024 threads per graph) on its own input and keeps
+                             the fastest; the first cpaa_solve_batched call does the same for
+                             tile_w (16, 32, 64) when tile_w = 0 */
 } cpaa_opts;
 
 /* Per-solve report (one per right-hand side in batched calls, one per graph in

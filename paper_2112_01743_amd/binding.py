@@ -36,7 +36,7 @@ class cpaa_opts(ctypes.Structure):
                 ("normalize", ctypes.c_int32), ("nnz_per_thread", ctypes.c_int32),
                 ("tile_w", ctypes.c_int32), ("validate", ctypes.c_int32),
                 ("io_device", ctypes.c_int32), ("time_kernels", ctypes.c_int32),
-                ("xcd_remap", ctypes.c_int32)]
+                ("xcd_remap", ctypes.c_int32), ("autotune", ctypes.c_int32)]
 
 
 class cpaa_report(ctypes.Structure):

@@ -193,6 +193,7 @@ void cpaa_default_opts(cpaa_opts* o) {
   o->io_device = 1;
   o->time_kernels = 0;
   o->xcd_remap = -1;
+  o->autotune = 0;
 }
 
 void cpaa_plan_destroy(cpaa_plan_t pl) {
@@ -200,6 +201,7 @@ void cpaa_plan_destroy(cpaa_plan_t pl) {
   free_workspace(pl->ws1);
   free_workspace(pl->wst);
   free_workspace(pl->wsg);
+  free_graph_state(pl);
   void* ptrs[] = {pl->d_row_ptr, pl->d_col_idx, pl->d_items, pl->d_split_nchunks,
                   pl->d_titems, pl->d_tsplit_nchunks, pl->d_graph_ptr, pl->d_graph_order,
                   pl->d_queue};
@@ -359,7 +361,8 @@ cpaa_status cpaa_plan(const cpaa_csr* g, double c, const cpaa_opts* opts, cpaa_p
   if (s == CPAA_OK) s = dev_upload(&pl->d_tsplit_nchunks, tnch.data(), tnch.size());
   if (s == CPAA_OK && num_graphs > 1) {
     pl->h_graph_ptr.assign(gp, gp + num_graphs + 1);
-    std::vector<int64_t> gnnz(num_graphs);
+    std::vector<int64_t>& gnnz = pl->h_graph_nnz;
+    gnnz.assign(num_graphs, 0);
     for (int gi = 0; gi < num_graphs; ++gi) {
       gnnz[gi] = static_cast<int64_t>(rp[gp[gi + 1]]) - rp[gp[gi]];
       pl->max_graph_n = std::max(pl->max_graph_n, gp[gi + 1] - gp[gi]);
@@ -372,6 +375,7 @@ cpaa_status cpaa_plan(const cpaa_csr* g, double c, const cpaa_opts* opts, cpaa_p
     s = dev_upload(&pl->d_graph_ptr, gp, num_graphs + 1);
     if (s == CPAA_OK) s = dev_upload(&pl->d_graph_order, order.data(), order.size());
     if (s == CPAA_OK) s = dev_alloc(&pl->d_queue, 1);
+    if (s == CPAA_OK) s = build_graph_state(pl, rp, ci, gp);
   }
   if (s == CPAA_OK) {
     if (hipEventCreate(&pl->ev_begin) != hipSuccess || hipEventCreate(&pl->ev_end) != hipSuccess) {

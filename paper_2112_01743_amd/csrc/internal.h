@@ -119,7 +119,8 @@ struct cpaa_plan_s {
   int max_graph_n = 0;
   int64_t max_graph_nnz = 0;
   std::vector<int32_t> h_graph_ptr;
-  std::vector<int32_t> h_row_ptr_graph_nnz;  // nnz per graph
+  std::vector<int64_t> h_graph_nnz;  // stored entries per graph
+  void* graph_state = nullptr;       // graphs.hip: packed local pairs, records, HIP graph
 
   std::vector<double> ck;            // c_k, k = 0..kMaxTerms+1
 
@@ -167,6 +168,9 @@ hipError_t finalize_tile(const cpaa_plan_s* pl, Workspace& ws, double* X, int64_
 hipError_t init_done(Workspace& ws, const int* active, hipStream_t st);
 
 // ---- multi-graph path (graphs.hip) ----
+cpaa_status build_graph_state(cpaa_plan_s* pl, const int32_t* rp, const int32_t* ci,
+                              const int32_t* gp);
+void free_graph_state(cpaa_plan_s* pl);
 cpaa_status solve_graphs_impl(cpaa_plan_s* pl, const double* p, double tol, double* x,
                               cpaa_report* reps, hipStream_t st);
 

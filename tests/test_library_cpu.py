@@ -28,7 +28,7 @@ def test_library_exports_nothing_else():
 
 
 def test_struct_sizes_match_header_layout():
-    assert ctypes.sizeof(B.cpaa_opts) == 9 * 4
+    assert ctypes.sizeof(B.cpaa_opts) == 10 * 4
     assert ctypes.sizeof(B.cpaa_report) == 6 * 4 + 7 * 8 + 2 * 8
     assert ctypes.sizeof(B.cpaa_csr) == 56
 
