@@ -192,6 +192,54 @@ CPAA_API cpaa_status cpaa_solve_batched(cpaa_plan_t plan, int32_t B, const doubl
 CPAA_API cpaa_status cpaa_solve_graphs(cpaa_plan_t plan, const double* p, double tol, double* x,
                               cpaa_report* reps, void* stream);
 
+/* ---- Learned warm start --------------------------------------------------
+ * A message-passing network of `layers` layers of width 64 over the plan's
+ * graph predicts a personalized PageRank vector x0 from each vertex's log
+ * degree and a one-hot source; pass its output as x0 / X0 to cpaa_solve /
+ * cpaa_solve_batched, which run CPAA on the residual and fall back to the
+ * plain solve when x0 is rejected.  Per layer l: M = A D^{-1} H (the paper's
+ * P, Sec. 2.1), Z = H W_self + M W_nbr + b, H' = relu(Z); head:
+ * x0 = softmax over the vertices of H w_out + b_out (clamped to +-80).  bf16 weights and
+ * activations, FP32 accumulation (MFMA for the width-64 layers), FP32
+ * gradients, Adam on FP32 master weights.
+ * Parameter packing (FP32, host arrays): for l = 0..layers-1: W_self^l
+ * (fan_in x 64 row-major, fan_in = 2 for l = 0 else 64), W_nbr^l (same), b^l
+ * (64); then w_out (64), b_out (1).  cpaa_model_num_params gives the count.
+ * The model keeps a pointer to the plan, which must outlive it. */
+typedef struct cpaa_model_s* cpaa_model_t;
+
+/* Create a model on a single-graph plan with the given initial parameters
+ * (host).  hidden must be 64, layers 1..4.  Errors: CPAA_EINVAL, CPAA_ENOMEM,
+ * CPAA_EDEVICE. */
+CPAA_API cpaa_status cpaa_model_create(cpaa_plan_t plan, int32_t layers, int32_t hidden,
+                                       const float* params, cpaa_model_t* out);
+CPAA_API void cpaa_model_destroy(cpaa_model_t model);
+CPAA_API int32_t cpaa_model_num_params(cpaa_model_t model);
+
+/* Copy out / restore the FP32 master parameters, Adam moments and step count
+ * (host arrays of cpaa_model_num_params floats; NULL skips an array).  Used
+ * for checkpoints and resuming training. */
+CPAA_API cpaa_status cpaa_model_get_state(cpaa_model_t model, float* params, float* adam_m,
+                                          float* adam_v, int64_t* step);
+CPAA_API cpaa_status cpaa_model_set_state(cpaa_model_t model, const float* params,
+                                          const float* adam_m, const float* adam_v,
+                                          int64_t step);
+
+/* x0 for B sources (host int32 array): column j written to X0[j*ldx + i]
+ * (device FP64).  Synchronous on `stream`. */
+CPAA_API cpaa_status cpaa_model_predict(cpaa_model_t model, int32_t B, const int32_t* sources,
+                                        double* X0, int64_t ldx, void* stream);
+
+/* One training step on B sources against targets T (device FP64, column j at
+ * T[j*ldt]; normally plain CPAA results): forward, cross-entropy loss
+ * -sum_u T_u log x0_u, backward, gradient averaged over the sources, then Adam
+ * with learning rate lr if lr > 0.  grads_out (host, may be NULL) receives the
+ * averaged gradient (before the update); loss_out (host, may be NULL) the
+ * mean L1 distance sum_u |x0_u - T_u| of the step's guesses. */
+CPAA_API cpaa_status cpaa_model_train_step(cpaa_model_t model, int32_t B, const int32_t* sources,
+                                           const double* T, int64_t ldt, float lr,
+                                           float* grads_out, double* loss_out, void* stream);
+
 /* Thread-local description of the last error ("" if none). */
 CPAA_API const char* cpaa_last_error(void);
 

@@ -5,15 +5,18 @@ GPU library trains on CPAA outputs (inputs: log-degree and a one-hot source;
 output: a probability vector x0 used as the CPAA starting guess).  Readings
 (not in the paper): aggregation uses the paper's transition matrix
 (M = P H = A D^{-1} H, the same neighbour weighting as Alg. 1's inner loop),
-ReLU activations, a softplus score normalised over the graph, L1 loss.
+ReLU activations, a softmax over the graph's vertices of the score (so a
+score of log d gives the degree-proportional stationary vector exactly).  Training minimises the cross-entropy -sum_u pi_u log x0_u
+(the natural objective of a softmax output; its score gradient is
+x0 sum(pi) - pi); the L1 distance sum_u |x0_u - pi_u| is the reported error.
 
     H^0      = [log d, 1{u = s}]                      (n x 2)
     M^l      = A D^{-1} H^l
     Z^l      = H^l W_self^l + M^l W_nbr^l + b^l      (n x hidden)
     H^{l+1}  = relu(Z^l)
     score    = H^L w_out + b_out
-    x0       = softplus(score) / sum(softplus(score))
-    loss     = sum_u |x0_u - pi_u|
+    x0       = exp(score - max score) / sum(exp(score - max score))
+    loss     = -sum_u pi_u log x0_u          (error measure: sum_u |x0_u - pi_u|)
 
 ``bf16=True`` reproduces the GPU kernels' precision: weights, H and M are
 rounded to bfloat16 (round to nearest even) before every product, products
@@ -29,8 +32,8 @@ import numpy as np
 
 from .cpaa_ref import adjacency
 
-__all__ = ["bf16_round", "mpnn_features", "mpnn_forward", "mpnn_loss", "mpnn_backward",
-           "param_names"]
+__all__ = ["bf16_round", "mpnn_features", "mpnn_forward", "mpnn_loss", "mpnn_l1",
+           "mpnn_backward", "param_names"]
 
 
 def bf16_round(a: np.ndarray) -> np.ndarray:
@@ -60,14 +63,6 @@ def mpnn_features(g, source: int) -> np.ndarray:
     return h0
 
 
-def _softplus(s):
-    return np.logaddexp(0.0, s)
-
-
-def _sigmoid(s):
-    return 0.5 * (1.0 + np.tanh(0.5 * s))
-
-
 def mpnn_forward(g, params: dict, source: int, layers: int = 3, bf16: bool = False):
     """Returns (x0, cache) for one source."""
     A = adjacency(g)
@@ -83,30 +78,34 @@ def mpnn_forward(g, params: dict, source: int, layers: int = 3, bf16: bool = Fal
         cache["Z"].append(Z)
         cache["H"].append(H)
     score = H @ r(params["w_out"]) + params["b_out"][0]
-    y = _softplus(score)
+    y = np.exp(score - score.max())
     x0 = y / y.sum()
     cache.update(score=score, y=y, x0=x0)
     return x0, cache
 
 
 def mpnn_loss(x0: np.ndarray, target: np.ndarray) -> float:
+    """Cross-entropy -sum_u pi_u log x0_u (the training objective)."""
+    return float(-(target * np.log(x0)).sum())
+
+
+def mpnn_l1(x0: np.ndarray, target: np.ndarray) -> float:
+    """L1 distance of the guess to the target (the reported error)."""
     return float(np.abs(x0 - target).sum())
 
 
 def mpnn_backward(params: dict, cache: dict, target: np.ndarray, layers: int = 3,
                   bf16: bool = False) -> dict:
-    """Gradient of the L1 loss with respect to every parameter (FP64).
+    """Gradient of the cross-entropy loss with respect to every parameter (FP64).
 
     Weights enter the forward pass as their (optionally bf16-rounded) values;
     the gradient is taken with respect to those values (straight-through).
     """
     r = bf16_round if bf16 else (lambda a: np.asarray(a, dtype=np.float64))
     A, d = cache["A"], cache["d"]
-    x0, y, score = cache["x0"], cache["y"], cache["score"]
-    S = y.sum()
-    gx = np.sign(x0 - target)
-    gy = (gx - np.dot(gx, x0)) / S
-    gs = gy * _sigmoid(score)
+    x0, score = cache["x0"], cache["score"]
+    # d/ds_u of -sum_v pi_v log softmax(s)_v = x0_u sum(pi) - pi_u
+    gs = x0 * target.sum() - target
     grads = {}
     HL = cache["H"][layers]
     grads["w_out"] = HL.T @ gs

@@ -96,6 +96,22 @@ def lib() -> ctypes.CDLL:
     L.cpaa_solve_graphs.restype = ctypes.c_int
     L.cpaa_last_error.argtypes = []
     L.cpaa_last_error.restype = ctypes.c_char_p
+    fp = ctypes.POINTER(ctypes.c_float)
+    L.cpaa_model_create.argtypes = [vp, i32, i32, fp, ctypes.POINTER(vp)]
+    L.cpaa_model_create.restype = ctypes.c_int
+    L.cpaa_model_destroy.argtypes = [vp]
+    L.cpaa_model_destroy.restype = None
+    L.cpaa_model_num_params.argtypes = [vp]
+    L.cpaa_model_num_params.restype = i32
+    L.cpaa_model_get_state.argtypes = [vp, fp, fp, fp, ctypes.POINTER(i64)]
+    L.cpaa_model_get_state.restype = ctypes.c_int
+    L.cpaa_model_set_state.argtypes = [vp, fp, fp, fp, i64]
+    L.cpaa_model_set_state.restype = ctypes.c_int
+    L.cpaa_model_predict.argtypes = [vp, i32, ctypes.POINTER(i32), vp, i64, vp]
+    L.cpaa_model_predict.restype = ctypes.c_int
+    L.cpaa_model_train_step.argtypes = [vp, i32, ctypes.POINTER(i32), vp, i64, ctypes.c_float,
+                                        fp, ctypes.POINTER(dbl), vp]
+    L.cpaa_model_train_step.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -175,6 +191,11 @@ def cpaa_solve_graphs(plan, p_ptr: int, tol: float, x_ptr: int, num_graphs: int,
 # convenience object over torch HIP tensors
 # ----------------------------------------------------------------------------
 
+def _ld(t, n: int) -> int:
+    """Leading dimension of a (B, n) tensor; a single row may report any stride."""
+    return int(t.stride(0)) if int(t.shape[0]) > 1 else max(int(t.stride(0)), n)
+
+
 def _stream_handle(stream) -> int:
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
@@ -248,10 +269,10 @@ class Plan:
         B = int(P.shape[0])
         if out is None:
             out = torch.empty_like(P)
-        st, reps = cpaa_solve_batched(self.handle, B, P.data_ptr(), int(P.stride(0)), tol,
+        st, reps = cpaa_solve_batched(self.handle, B, P.data_ptr(), _ld(P, self.n), tol,
                                       None if X0 is None else X0.data_ptr(),
-                                      int(X0.stride(0)) if X0 is not None else self.n,
-                                      out.data_ptr(), int(out.stride(0)), _stream_handle(stream))
+                                      _ld(X0, self.n) if X0 is not None else self.n,
+                                      out.data_ptr(), _ld(out, self.n), _stream_handle(stream))
         if check and st not in (CPAA_OK, CPAA_ENOCONV):
             raise CpaaError(st, "cpaa_solve_batched")
         out_reps = []
@@ -275,6 +296,112 @@ class Plan:
     def close(self):
         if getattr(self, "handle", None):
             cpaa_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ----------------------------------------------------------------------------
+# warm-start network
+# ----------------------------------------------------------------------------
+
+def pack_params(params: dict, layers: int) -> np.ndarray:
+    """Flatten a parameter dict into the packing order of include/cpaa.h."""
+    parts = []
+    for l in range(layers):
+        parts += [params[f"w_self{l}"], params[f"w_nbr{l}"], params[f"b{l}"]]
+    parts += [params["w_out"], params["b_out"]]
+    return np.concatenate([np.asarray(a, dtype=np.float32).reshape(-1) for a in parts])
+
+
+def unpack_params(flat: np.ndarray, layers: int, hidden: int = 64, in_features: int = 2) -> dict:
+    out, at, fin = {}, 0, in_features
+    for l in range(layers):
+        for name, shape in ((f"w_self{l}", (fin, hidden)), (f"w_nbr{l}", (fin, hidden)),
+                            (f"b{l}", (hidden,))):
+            size = int(np.prod(shape))
+            out[name] = flat[at:at + size].reshape(shape)
+            at += size
+        fin = hidden
+    out["w_out"] = flat[at:at + hidden]
+    out["b_out"] = flat[at + hidden:at + hidden + 1]
+    return out
+
+
+def _fptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+class Model:
+    """The warm-start network on a Plan's graph (cpaa_model_*)."""
+
+    def __init__(self, plan: "Plan", params: dict, layers: int = 3, hidden: int = 64):
+        self.plan = plan            # the model keeps a pointer to the plan
+        self.layers = layers
+        flat = np.ascontiguousarray(pack_params(params, layers))
+        h = ctypes.c_void_p()
+        st = lib().cpaa_model_create(plan.handle, layers, hidden, _fptr(flat), ctypes.byref(h))
+        if st != CPAA_OK:
+            raise CpaaError(st, "cpaa_model_create")
+        self.handle = h
+        self.num_params = int(lib().cpaa_model_num_params(h))
+
+    def get_state(self):
+        P = self.num_params
+        w, m, v = (np.zeros(P, dtype=np.float32) for _ in range(3))
+        step = ctypes.c_int64()
+        st = lib().cpaa_model_get_state(self.handle, _fptr(w), _fptr(m), _fptr(v),
+                                        ctypes.byref(step))
+        if st != CPAA_OK:
+            raise CpaaError(st, "cpaa_model_get_state")
+        return w, m, v, int(step.value)
+
+    def set_state(self, w, m=None, v=None, step=0):
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        m = None if m is None else np.ascontiguousarray(m, dtype=np.float32)
+        v = None if v is None else np.ascontiguousarray(v, dtype=np.float32)
+        st = lib().cpaa_model_set_state(self.handle, _fptr(w), None if m is None else _fptr(m),
+                                        None if v is None else _fptr(v), int(step))
+        if st != CPAA_OK:
+            raise CpaaError(st, "cpaa_model_set_state")
+
+    def params(self) -> dict:
+        return unpack_params(self.get_state()[0], self.layers)
+
+    def predict(self, sources, out=None, stream=None):
+        """x0 for each source: (B, n) float64 HIP tensor."""
+        import torch
+        src = np.ascontiguousarray(np.asarray(sources, dtype=np.int32))
+        B = int(src.shape[0])
+        if out is None:
+            out = torch.empty((B, self.plan.n), dtype=torch.float64, device="cuda")
+        st = lib().cpaa_model_predict(self.handle, B,
+                                      src.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                      out.data_ptr(), _ld(out, self.plan.n), _stream_handle(stream))
+        if st != CPAA_OK:
+            raise CpaaError(st, "cpaa_model_predict")
+        return out
+
+    def train_step(self, sources, targets, lr: float, want_grads: bool = False, stream=None):
+        """targets: (B, n) float64 HIP tensor.  Returns (mean loss, grads or None)."""
+        src = np.ascontiguousarray(np.asarray(sources, dtype=np.int32))
+        grads = np.zeros(self.num_params, dtype=np.float32) if want_grads else None
+        loss = ctypes.c_double()
+        st = lib().cpaa_model_train_step(
+            self.handle, int(src.shape[0]), src.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+            targets.data_ptr(), _ld(targets, self.plan.n), float(lr),
+            None if grads is None else _fptr(grads), ctypes.byref(loss), _stream_handle(stream))
+        if st != CPAA_OK:
+            raise CpaaError(st, "cpaa_model_train_step")
+        return loss.value, (None if grads is None else unpack_params(grads, self.layers))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().cpaa_model_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

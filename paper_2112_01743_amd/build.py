@@ -22,7 +22,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libcpaa.so")
 
 SOURCES = ["api.hip", "solve.hip", "kernels_common.hip", "kernels_w1.hip", "kernels_tile.hip",
-           "graphs.hip"]
+           "graphs.hip", "mpnn.hip"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 

@@ -13,7 +13,9 @@ def test_library_exports_every_declared_function():
     names = B.header_functions()
     assert {"cpaa_plan", "cpaa_solve", "cpaa_solve_batched", "cpaa_solve_graphs",
             "cpaa_plan_destroy", "cpaa_last_error", "cpaa_default_opts",
-            "cpaa_plan_info_get"} <= set(names)
+            "cpaa_plan_info_get", "cpaa_model_create", "cpaa_model_predict",
+            "cpaa_model_train_step", "cpaa_model_get_state", "cpaa_model_set_state",
+            "cpaa_model_destroy", "cpaa_model_num_params"} <= set(names)
     L = B.lib()
     for name in names:
         assert hasattr(L, name), name
@@ -86,3 +88,13 @@ def test_plan_rejects_edge_across_graph_boundary():
     h = ctypes.c_void_p()
     st = B.lib().cpaa_plan(ctypes.byref(csr), 0.85, None, ctypes.byref(h))
     assert st == B.CPAA_EINVAL and "crosses" in B.cpaa_last_error()
+
+
+def test_param_packing_roundtrip():
+    import graphgen as gg
+    p = gg.mpnn_init(3)
+    flat = B.pack_params(p, 3)
+    assert flat.size == 2 * 2 * 64 + 64 + 2 * (2 * 64 * 64 + 64) + 65
+    back = B.unpack_params(flat, 3)
+    for k, v in p.items():
+        assert np.array_equal(back[k], v)

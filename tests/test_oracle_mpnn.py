@@ -40,8 +40,22 @@ def test_one_layer_closed_form():
     p["w_out"] = np.array([0.0, 1.0], dtype=np.float32)
     p["b_out"] = np.zeros(1, dtype=np.float32)
     x0, _ = om.mpnn_forward(g, p, source=2, layers=1)
-    sp = np.log1p(np.exp([0.0, 0.0, 1.0, 0.0, 0.0]))
-    assert np.allclose(x0, sp / sp.sum(), atol=1e-15)
+    e = np.exp([0.0, 0.0, 1.0, 0.0, 0.0])
+    assert np.allclose(x0, e / e.sum(), atol=1e-15)
+
+
+def test_log_degree_score_gives_stationary_vector():
+    """score = log d reproduces the stationary distribution d / vol exactly."""
+    g = gg.random_connected(40, 5.0, seed=9)
+    p = gg.mpnn_init(0, layers=1, hidden=2)
+    p["w_self0"] = np.eye(2, dtype=np.float32)
+    p["w_nbr0"] = np.zeros((2, 2), dtype=np.float32)
+    p["b0"] = np.zeros(2, dtype=np.float32)
+    p["w_out"] = np.array([1.0, 0.0], dtype=np.float32)
+    p["b_out"] = np.zeros(1, dtype=np.float32)
+    d = np.diff(g.row_ptr).astype(float)
+    x0, _ = om.mpnn_forward(g, p, source=0, layers=1)
+    assert np.allclose(x0, d / d.sum(), atol=1e-15)
 
 
 def test_aggregation_is_transition_matrix():
