@@ -103,48 +103,130 @@ __global__ __launch_bounds__(kWG) void k_features(int n, const int* __restrict__
   }
 }
 
-// M^0 = A D^{-1} H^0 for the two input features (thread per vertex)
-__global__ __launch_bounds__(kWG) void k_agg2(int n, const int* __restrict__ rp,
+// Aggregations walk the plan's wavefront work items (groups of short rows, or
+// chunks of a long row whose partial sums meet in an FP32 slot; the last
+// chunk to arrive finishes the row), so hub rows of power-law graphs are
+// spread over many wavefronts.
+
+// M^0 = A D^{-1} H^0 for the two input features: lanes stride over a row's
+// neighbours and reduce with shuffles.
+__global__ __launch_bounds__(kWG) void k_agg2(const WorkItem* __restrict__ items, int n_items,
+                                              const int* __restrict__ rp,
                                               const int* __restrict__ ci,
                                               const float* __restrict__ invd,
                                               const uint16_t* __restrict__ h,
-                                              uint16_t* __restrict__ m) {
-  for (int u = blockIdx.x * kWG + threadIdx.x; u < n; u += gridDim.x * kWG) {
-    float a0 = 0.f, a1 = 0.f;
-    for (int j = rp[u]; j < rp[u + 1]; ++j) {
+                                              uint16_t* __restrict__ m, float* __restrict__ part,
+                                              int* __restrict__ count,
+                                              const int* __restrict__ nchunks) {
+  const int lane = threadIdx.x & 63;
+  const int item = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (item >= n_items) return;
+  const WorkItem it = items[item];
+  auto row_sum = [&](int beg, int end, float& a0, float& a1) {
+    a0 = a1 = 0.f;
+    for (int j = beg + lane; j < end; j += 64) {
       const int v = ci[j];
       const float w = invd[v];
       a0 += bf2f(h[2 * v]) * w;
       a1 += bf2f(h[2 * v + 1]) * w;
     }
-    m[2 * u] = f2bf(a0);
-    m[2 * u + 1] = f2bf(a1);
+    a0 = wave_sum(a0);
+    a1 = wave_sum(a1);
+  };
+  if (it.row1 >= 0) {
+    for (int r = it.row0; r < it.row1; ++r) {
+      float a0, a1;
+      row_sum(rp[r], rp[r + 1], a0, a1);
+      if (lane == 0) {
+        m[2 * r] = f2bf(a0);
+        m[2 * r + 1] = f2bf(a1);
+      }
+    }
+    return;
+  }
+  const int slot = -(it.row1 + 1);
+  float a0, a1;
+  row_sum(it.nnz0, it.nnz1, a0, a1);
+  int prev = 0;
+  if (lane == 0) {
+    atomicAdd(&part[2 * slot], a0);
+    atomicAdd(&part[2 * slot + 1], a1);
+    __threadfence();
+    prev = atomicAdd(&count[slot], 1);
+    if (prev == nchunks[slot] - 1) {
+      __threadfence();
+      const float f0 = __hip_atomic_exchange(&part[2 * slot], 0.f, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+      const float f1 = __hip_atomic_exchange(&part[2 * slot + 1], 0.f, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_exchange(&count[slot], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      m[2 * it.row0] = f2bf(f0);
+      m[2 * it.row0 + 1] = f2bf(f1);
+    }
   }
 }
 
-// M = A D^{-1} H for 64 features: one wavefront per vertex, lane = feature
-__global__ __launch_bounds__(kWG) void k_agg64(int n, const int* __restrict__ rp,
+// 64-feature aggregation over work items, lane = feature.
+//   forward  (BWD = false): M[u] = bf16( sum_{v in N(u)} invd[v] * H[v] ),  H bf16
+//   backward (BWD = true) : dH[u] += invd[u] * sum_{v in N(u)} dM[v],       dM FP32
+template <bool BWD>
+__global__ __launch_bounds__(kWG) void k_agg64(const WorkItem* __restrict__ items, int n_items,
+                                               const int* __restrict__ rp,
                                                const int* __restrict__ ci,
                                                const float* __restrict__ invd,
-                                               const uint16_t* __restrict__ h,
-                                               uint16_t* __restrict__ m) {
+                                               const void* __restrict__ xin,
+                                               void* __restrict__ out, float* __restrict__ part,
+                                               int* __restrict__ count,
+                                               const int* __restrict__ nchunks) {
   const int lane = threadIdx.x & 63;
-  const int wave = (blockIdx.x * kWG + threadIdx.x) >> 6;
-  const int nwaves = (gridDim.x * kWG) >> 6;
-  for (int u = wave; u < n; u += nwaves) {
-    const int beg = rp[u], end = rp[u + 1];
-    float a0 = 0.f, a1 = 0.f;
-    int j = beg;
-    for (; j + 2 <= end; j += 2) {
-      const int v0 = ci[j], v1 = ci[j + 1];
-      a0 += bf2f(h[(size_t)v0 * kHid + lane]) * invd[v0];
-      a1 += bf2f(h[(size_t)v1 * kHid + lane]) * invd[v1];
+  const int item = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (item >= n_items) return;
+  const WorkItem it = items[item];
+  const uint16_t* hb = static_cast<const uint16_t*>(xin);
+  const float* xf = static_cast<const float*>(xin);
+  auto load = [&](int v) -> float {
+    return BWD ? xf[(size_t)v * kHid + lane] : bf2f(hb[(size_t)v * kHid + lane]) * invd[v];
+  };
+  auto finish = [&](int r, float acc) {
+    if (BWD)
+      static_cast<float*>(out)[(size_t)r * kHid + lane] += invd[r] * acc;
+    else
+      static_cast<uint16_t*>(out)[(size_t)r * kHid + lane] = f2bf(acc);
+  };
+  if (it.row1 >= 0) {
+    for (int r = it.row0; r < it.row1; ++r) {
+      const int beg = rp[r], end = rp[r + 1];
+      float a0 = 0.f, a1 = 0.f;
+      int j = beg;
+      for (; j + 2 <= end; j += 2) {
+        a0 += load(ci[j]);
+        a1 += load(ci[j + 1]);
+      }
+      if (j < end) a0 += load(ci[j]);
+      finish(r, a0 + a1);
     }
-    if (j < end) {
-      const int v0 = ci[j];
-      a0 += bf2f(h[(size_t)v0 * kHid + lane]) * invd[v0];
-    }
-    m[(size_t)u * kHid + lane] = f2bf(a0 + a1);
+    return;
+  }
+  const int slot = -(it.row1 + 1);
+  float a0 = 0.f, a1 = 0.f;
+  int j = it.nnz0;
+  for (; j + 2 <= it.nnz1; j += 2) {
+    a0 += load(ci[j]);
+    a1 += load(ci[j + 1]);
+  }
+  if (j < it.nnz1) a0 += load(ci[j]);
+  atomicAdd(&part[(size_t)slot * kHid + lane], a0 + a1);
+  __threadfence();
+  int prev = 0;
+  if (lane == 0) prev = atomicAdd(&count[slot], 1);
+  prev = __shfl(prev, 0);
+  if (prev == nchunks[slot] - 1) {
+    __threadfence();
+    const float full = __hip_atomic_exchange(&part[(size_t)slot * kHid + lane], 0.f,
+                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    finish(it.row0, full);
+    if (lane == 0)
+      __hip_atomic_exchange(&count[slot], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -451,29 +533,6 @@ __global__ __launch_bounds__(kWG) void k_dh(int n, const float* __restrict__ dz,
   }
 }
 
-// dH = dHd + D^{-1} A dM  (A symmetric, so P^T = D^{-1} A), in place over dHd
-__global__ __launch_bounds__(kWG) void k_agg_bwd(int n, const int* __restrict__ rp,
-                                                 const int* __restrict__ ci,
-                                                 const float* __restrict__ invd,
-                                                 const float* __restrict__ dm,
-                                                 float* __restrict__ dh) {
-  const int lane = threadIdx.x & 63;
-  const int wave = (blockIdx.x * kWG + threadIdx.x) >> 6;
-  const int nwaves = (gridDim.x * kWG) >> 6;
-  for (int v = wave; v < n; v += nwaves) {
-    const int beg = rp[v], end = rp[v + 1];
-    float a0 = 0.f, a1 = 0.f;
-    int j = beg;
-    for (; j + 2 <= end; j += 2) {
-      a0 += dm[(size_t)ci[j] * kHid + lane];
-      a1 += dm[(size_t)ci[j + 1] * kHid + lane];
-    }
-    if (j < end) a0 += dm[(size_t)ci[j] * kHid + lane];
-    const size_t e = (size_t)v * kHid + lane;
-    dh[e] += invd[v] * (a0 + a1);
-  }
-}
-
 __global__ __launch_bounds__(kWG) void k_adam(int total, float* __restrict__ w,
                                               const float* __restrict__ g, float* __restrict__ m,
                                               float* __restrict__ v, float lr, float b1, float b2,
@@ -524,6 +583,8 @@ struct cpaa_model_s {
   double* red = nullptr;     // [3] per source
   double* x0tmp = nullptr;   // [n]
   double* hred = nullptr;    // pinned [3]
+  float* part = nullptr;     // [long-row slots][64] partial sums of split rows
+  int* count = nullptr;      // [long-row slots] chunk arrivals
 };
 
 static void model_free(cpaa_model_s* md) {
@@ -531,7 +592,7 @@ static void model_free(cpaa_model_s* md) {
   void* ptrs[] = {md->params, md->grads, md->adam_m, md->adam_v, md->wr, md->wt[0], md->wt[1],
                   md->wt[2], md->invd, md->h0, md->m0, md->h[0], md->h[1], md->h[2], md->h[3],
                   md->m[0], md->m[1], md->m[2], md->m[3], md->s, md->y, md->gs, md->dz, md->dh,
-                  md->dm, md->red, md->x0tmp};
+                  md->dm, md->red, md->x0tmp, md->part, md->count};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (md->hred) (void)hipHostFree(md->hred);
@@ -551,13 +612,16 @@ static hipError_t forward(cpaa_model_s* md, int source, double* x0, hipStream_t 
   const int gw = grid_rows(n, 4);      // wavefront-per-vertex kernels: 4 vertices per block pass
   const int ge = grid_rows(n, kWG);
   hipLaunchKernelGGL(k_features, dim3(ge), dim3(kWG), 0, st, n, pl->d_row_ptr, source, md->h0);
-  hipLaunchKernelGGL(k_agg2, dim3(ge), dim3(kWG), 0, st, n, pl->d_row_ptr, pl->d_col_idx, md->invd,
-                     md->h0, md->m0);
+  const dim3 gi((pl->n_titems + 3) / 4);
+  hipLaunchKernelGGL(k_agg2, gi, dim3(kWG), 0, st, pl->d_titems, pl->n_titems, pl->d_row_ptr,
+                     pl->d_col_idx, md->invd, md->h0, md->m0, md->part, md->count,
+                     pl->d_tsplit_nchunks);
   hipLaunchKernelGGL(k_dense0, dim3(gw), dim3(kWG), 0, st, n, md->h0, md->m0, md->wr, md->o,
                      md->h[0]);
   for (int l = 1; l < md->layers; ++l) {
-    hipLaunchKernelGGL(k_agg64, dim3(gw), dim3(kWG), 0, st, n, pl->d_row_ptr, pl->d_col_idx,
-                       md->invd, md->h[l - 1], md->m[l - 1]);
+    hipLaunchKernelGGL(k_agg64<false>, gi, dim3(kWG), 0, st, pl->d_titems, pl->n_titems,
+                       pl->d_row_ptr, pl->d_col_idx, md->invd, (const void*)md->h[l - 1],
+                       (void*)md->m[l - 1], md->part, md->count, pl->d_tsplit_nchunks);
     hipLaunchKernelGGL(k_dense_mfma, dim3(grid_rows(n, 64)), dim3(kWG), 0, st, n, md->h[l - 1],
                        md->m[l - 1], md->wt[l - 1], md->params + md->o.b[l], md->h[l]);
   }
@@ -597,8 +661,10 @@ static hipError_t backward(cpaa_model_s* md, const double* x0, const double* pi,
                          md->o.w_nbr[l], md->o.b[l], chunk);
       hipLaunchKernelGGL(k_dh, dim3(gw), dim3(kWG), 0, st, n, md->dz, md->wr, md->o.w_self[l],
                          md->o.w_nbr[l], md->dh, md->dm);
-      hipLaunchKernelGGL(k_agg_bwd, dim3(gw), dim3(kWG), 0, st, n, pl->d_row_ptr, pl->d_col_idx,
-                         md->invd, md->dm, md->dh);
+      hipLaunchKernelGGL(k_agg64<true>, dim3((pl->n_titems + 3) / 4), dim3(kWG), 0, st,
+                         pl->d_titems, pl->n_titems, pl->d_row_ptr, pl->d_col_idx, md->invd,
+                         (const void*)md->dm, (void*)md->dh, md->part, md->count,
+                         pl->d_tsplit_nchunks);
     } else {
       const int chunk = 256;
       hipLaunchKernelGGL(k_wgrad2, dim3(std::max(1, (n + chunk * 4 - 1) / (chunk * 4))),
@@ -660,6 +726,9 @@ cpaa_status cpaa_model_create(cpaa_plan_t pl, int32_t layers, int32_t hidden, co
   A((void**)&md->dm, n * kHid * 4);
   A((void**)&md->red, 4 * 8);
   A((void**)&md->x0tmp, n * 8);
+  const size_t nslots = std::max(pl->n_tsplit_rows, 1);
+  A((void**)&md->part, nslots * kHid * 4);
+  A((void**)&md->count, nslots * 4);
   if (ok && hipHostMalloc((void**)&md->hred, 4 * 8, hipHostMallocDefault) != hipSuccess) {
     (void)hipGetLastError();
     ok = false;
@@ -670,6 +739,8 @@ cpaa_status cpaa_model_create(cpaa_plan_t pl, int32_t layers, int32_t hidden, co
     return CPAA_ENOMEM;
   }
   if (hipMemcpy(md->params, params, P * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(md->part, 0, nslots * kHid * 4) != hipSuccess ||
+      hipMemset(md->count, 0, nslots * 4) != hipSuccess ||
       hipMemset(md->adam_m, 0, P * 4) != hipSuccess || hipMemset(md->adam_v, 0, P * 4) != hipSuccess) {
     model_free(md);
     set_error("upload of the network parameters failed");
