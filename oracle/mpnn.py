@@ -33,7 +33,7 @@ import numpy as np
 from .cpaa_ref import adjacency
 
 __all__ = ["bf16_round", "mpnn_features", "mpnn_forward", "mpnn_loss", "mpnn_l1",
-           "mpnn_backward", "param_names"]
+           "mpnn_backward", "param_names", "adam_step"]
 
 
 def bf16_round(a: np.ndarray) -> np.ndarray:
@@ -122,3 +122,17 @@ def mpnn_backward(params: dict, cache: dict, target: np.ndarray, layers: int = 3
             # M = A D^{-1} H  =>  dH += D^{-1} A^T dM, and A is symmetric
             dH = dZ @ r(params[f"w_self{l}"]).T + (A @ dM) / d[:, None]
     return grads
+
+
+def adam_step(w: np.ndarray, g: np.ndarray, m: np.ndarray, v: np.ndarray, step: int, lr: float,
+              b1: float = 0.9, b2: float = 0.999, eps: float = 1e-8):
+    """One Adam update (Kingma and Ba, 2015, Algorithm 1) in FP64.
+
+    ``step`` counts updates already taken; the bias corrections use step + 1.
+    Returns (w', m', v')."""
+    m = b1 * np.asarray(m, dtype=np.float64) + (1.0 - b1) * g
+    v = b2 * np.asarray(v, dtype=np.float64) + (1.0 - b2) * g * g
+    t = step + 1
+    m_hat = m / (1.0 - b1**t)
+    v_hat = v / (1.0 - b2**t)
+    return np.asarray(w, dtype=np.float64) - lr * m_hat / (np.sqrt(v_hat) + eps), m, v

@@ -175,6 +175,17 @@ void build_tile_items(int32_t n, const int32_t* rp, std::vector<WorkItem>& items
 }  // namespace
 }  // namespace cpaa
 
+namespace cpaa {
+void select_map(cpaa_plan_s* pl, size_t i) {
+  const WorkMap& m = pl->maps[i];
+  pl->npt = m.npt;
+  pl->d_items = m.d_items;
+  pl->n_items = m.n_items;
+  pl->n_split_rows = m.n_split_rows;
+  pl->d_split_nchunks = m.d_split_nchunks;
+}
+}  // namespace cpaa
+
 using namespace cpaa;
 
 extern "C" {
@@ -202,9 +213,12 @@ void cpaa_plan_destroy(cpaa_plan_t pl) {
   free_workspace(pl->wst);
   free_workspace(pl->wsg);
   free_graph_state(pl);
-  void* ptrs[] = {pl->d_row_ptr, pl->d_col_idx, pl->d_items, pl->d_split_nchunks,
-                  pl->d_titems, pl->d_tsplit_nchunks, pl->d_graph_ptr, pl->d_graph_order,
-                  pl->d_queue};
+  for (WorkMap& m : pl->maps) {
+    if (m.d_items) (void)hipFree(m.d_items);
+    if (m.d_split_nchunks) (void)hipFree(m.d_split_nchunks);
+  }
+  void* ptrs[] = {pl->d_row_ptr, pl->d_col_idx, pl->d_titems, pl->d_tsplit_nchunks,
+                  pl->d_graph_ptr, pl->d_graph_order, pl->d_queue};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (pl->ev_begin) (void)hipEventDestroy(pl->ev_begin);
@@ -340,11 +354,14 @@ cpaa_status cpaa_plan(const cpaa_csr* g, double c, const cpaa_opts* opts, cpaa_p
   // single-vector kernel, so "auto" enables it for tiles only.
   pl->xcd_remap = o.xcd_remap < 0 ? 0 : (o.xcd_remap ? 1 : 0);
   pl->xcd_remap_tile = o.xcd_remap < 0 ? 1 : (o.xcd_remap ? 1 : 0);
-  std::vector<WorkItem> items;
-  std::vector<int> nch;
-  build_items(n, rp, pl->npt, items, nch);
-  pl->n_items = static_cast<int>(items.size());
-  pl->n_split_rows = static_cast<int>(nch.size());
+  // candidate work maps: the chosen npt, plus the other sizes when autotuning
+  std::vector<int> npts = {pl->npt};
+  if (o.autotune && o.nnz_per_thread == 0 && num_graphs == 1)
+    for (int c : {8, 16, 32})
+      if (c != pl->npt) npts.push_back(c);
+  std::vector<std::vector<WorkItem>> item_sets(npts.size());
+  std::vector<std::vector<int>> nch_sets(npts.size());
+  for (size_t i = 0; i < npts.size(); ++i) build_items(n, rp, npts[i], item_sets[i], nch_sets[i]);
   std::vector<WorkItem> titems;
   std::vector<int> tnch;
   build_tile_items(n, rp, titems, tnch);
@@ -355,8 +372,17 @@ cpaa_status cpaa_plan(const cpaa_csr* g, double c, const cpaa_opts* opts, cpaa_p
   cpaa_status s = CPAA_OK;
   if (s == CPAA_OK) s = dev_upload(&pl->d_row_ptr, rp, n + 1);
   if (s == CPAA_OK) s = dev_upload(&pl->d_col_idx, ci, static_cast<size_t>(nnz));
-  if (s == CPAA_OK) s = dev_upload(&pl->d_items, items.data(), items.size());
-  if (s == CPAA_OK) s = dev_upload(&pl->d_split_nchunks, nch.data(), nch.size());
+  pl->maps.resize(npts.size());
+  for (size_t i = 0; i < npts.size() && s == CPAA_OK; ++i) {
+    WorkMap& m = pl->maps[i];
+    m.npt = npts[i];
+    m.n_items = static_cast<int>(item_sets[i].size());
+    m.n_split_rows = static_cast<int>(nch_sets[i].size());
+    pl->max_split_rows = std::max(pl->max_split_rows, m.n_split_rows);
+    s = dev_upload(&m.d_items, item_sets[i].data(), item_sets[i].size());
+    if (s == CPAA_OK) s = dev_upload(&m.d_split_nchunks, nch_sets[i].data(), nch_sets[i].size());
+  }
+  if (s == CPAA_OK) select_map(pl, 0);
   if (s == CPAA_OK) s = dev_upload(&pl->d_titems, titems.data(), titems.size());
   if (s == CPAA_OK) s = dev_upload(&pl->d_tsplit_nchunks, tnch.data(), tnch.size());
   if (s == CPAA_OK && num_graphs > 1) {

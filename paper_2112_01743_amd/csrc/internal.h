@@ -53,6 +53,15 @@ struct WorkItem {
   int nnz1;
 };
 
+// One decomposition of the CSR into single-vector work items (for one npt).
+struct WorkMap {
+  int npt = 0;
+  WorkItem* d_items = nullptr;
+  int n_items = 0;
+  int n_split_rows = 0;
+  int* d_split_nchunks = nullptr;
+};
+
 struct Workspace {
   int W = 0;              // tile width (1 = single vector path)
   int tiles = 0;
@@ -96,12 +105,16 @@ struct cpaa_plan_s {
   int32_t* d_row_ptr = nullptr;
   int32_t* d_col_idx = nullptr;
 
-  // single-vector work map
+  // single-vector work map in use (one of `maps`)
   int npt = 8;                       // nnz per thread of a work item
   cpaa::WorkItem* d_items = nullptr;
   int n_items = 0;
   int n_split_rows = 0;
   int* d_split_nchunks = nullptr;    // [n_split_rows]
+  std::vector<cpaa::WorkMap> maps;   // candidates (several when autotuning)
+  int max_split_rows = 0;            // over all candidates (workspace sizing)
+  bool tuned_w1 = false;
+  bool tuned_tile = false;
   int xcd_remap = 0;                 // single-vector kernels
   int xcd_remap_tile = 1;            // tiled kernels
 
@@ -176,6 +189,7 @@ cpaa_status solve_graphs_impl(cpaa_plan_s* pl, const double* p, double tol, doub
 
 // ---- host helpers (solve.hip) ----
 cpaa_status ensure_workspace(cpaa_plan_s* pl, Workspace& ws, int W, int tiles);
+void select_map(cpaa_plan_s* pl, size_t i);
 void free_workspace(Workspace& ws);
 double series_tail(const cpaa_plan_s* pl, int M);
 int apriori_terms(const cpaa_plan_s* pl, double norm_dinv_half_b, double target);

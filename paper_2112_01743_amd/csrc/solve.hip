@@ -50,7 +50,7 @@ cpaa_status ensure_workspace(cpaa_plan_s* pl, Workspace& ws, int W, int tiles) {
   ws.cols = static_cast<int64_t>(tiles) * W;
   ws.vec_elems = static_cast<size_t>(pl->n) * ws.cols;
   // split-row partial sums: one set per tile (tiles run concurrently)
-  const size_t nsplit = (size_t)std::max(W == 1 ? pl->n_split_rows : pl->n_tsplit_rows, 1);
+  const size_t nsplit = (size_t)std::max(W == 1 ? pl->max_split_rows : pl->n_tsplit_rows, 1);
   const size_t split_sets = (size_t)tiles;
   auto alloc = [&](void** p, size_t bytes) -> bool {
     if (bytes == 0) bytes = 8;
@@ -192,6 +192,21 @@ cpaa_status run_series(cpaa_plan_s* pl, Workspace& ws, TermFn term, int series_i
     }
   }
   return CPAA_OK;
+}
+
+// Time `reps` term launches (first term included) of the current work map on
+// the workspace's current z_0; returns milliseconds per launch.  The probes
+// write z and acc, so callers restart the series afterwards.
+float time_terms(cpaa_plan_s* pl, Workspace& ws, TermFn term, int reps, hipStream_t st,
+                 hipError_t* err) {
+  *err = hipEventRecord(pl->ev_begin, st);
+  for (int k = 0; k < reps && *err == hipSuccess; ++k)
+    *err = term(pl, ws, k % 3, (k + 2) % 3, (k + 1) % 3, k == 0, 0.0, nullptr, nullptr, st);
+  if (*err == hipSuccess) *err = hipEventRecord(pl->ev_end, st);
+  if (*err == hipSuccess) *err = hipEventSynchronize(pl->ev_end);
+  float ms = 0.f;
+  if (*err == hipSuccess) *err = hipEventElapsedTime(&ms, pl->ev_begin, pl->ev_end);
+  return ms / reps;
 }
 
 struct HostView {
@@ -356,6 +371,26 @@ extern "C" cpaa_status cpaa_solve(cpaa_plan_t pl, const double* p, double tol, c
     if ((s = read_back(ws, st)) != CPAA_OK) return s;
     if (!p_checked && (s = check_p_stats(ws, 0)) != CPAA_OK) return s;
     q0 = stat_at(ws, 0, 0, 2);
+    if (pl->opts.autotune && !pl->tuned_w1 && pl->maps.size() > 1) {
+      // autotune the work-item size on this input: time a few terms per candidate
+      size_t best = 0;
+      float best_ms = 1e30f;
+      for (size_t i = 0; i < pl->maps.size(); ++i) {
+        select_map(pl, i);
+        hipError_t e = hipSuccess;
+        time_terms(pl, ws, term_w1, 2, st, &e);            // warm-up
+        const float ms = time_terms(pl, ws, term_w1, 4, st, &e);
+        CPAA_HIP(e);
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = i;
+        }
+      }
+      select_map(pl, best);
+      pl->tuned_w1 = true;
+      // restart the series (the probes overwrote z and acc)
+      CPAA_HIP(init_w1(pl, ws, dp, 1.0 - c, false, true, true, st));
+    }
   }
 
   const double target_main = 0.5 * tol;
@@ -444,10 +479,33 @@ extern "C" cpaa_status cpaa_solve_batched(cpaa_plan_t pl, int32_t B, const doubl
     return CPAA_EINVAL;
   }
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  cpaa_status s;
+  if (pl->opts.autotune && pl->opts.tile_w == 0 && !pl->tuned_tile && pl->opts.io_device) {
+    // autotune the tile width on this input: time a few terms per candidate
+    int best_w = pl->tile_w;
+    float best_ms = 1e30f;
+    for (int Wc : {16, 32, 64}) {
+      if (Wc > 16 && Wc / 2 >= B) break;
+      const int Tc = (B + Wc - 1) / Wc;
+      if ((s = ensure_workspace(pl, pl->wst, Wc, Tc)) != CPAA_OK) return s;
+      CPAA_HIP(fill_f64(pl->wst.stat_slots, 0.0, (size_t)2 * kSlots * pl->wst.cols * kStat, st));
+      CPAA_HIP(init_tile(pl, pl->wst, P, ldp, B, 1.0 - pl->c, false, false, true, st));
+      hipError_t e = hipSuccess;
+      time_terms(pl, pl->wst, term_tile, 2, st, &e);
+      const float ms = time_terms(pl, pl->wst, term_tile, 4, st, &e) / (float)(Tc * Wc);
+      CPAA_HIP(e);
+      if (ms < best_ms) {
+        best_ms = ms;
+        best_w = Wc;
+      }
+    }
+    pl->tile_w = best_w;
+    pl->tuned_tile = true;
+  }
   int W = pl->tile_w;
   while (W > 8 && W / 2 >= B) W /= 2;
   const int T = (B + W - 1) / W;
-  cpaa_status s = ensure_workspace(pl, pl->wst, W, T);
+  s = ensure_workspace(pl, pl->wst, W, T);
   if (s != CPAA_OK) return s;
   Workspace& ws = pl->wst;
   const double c = pl->c;

@@ -78,6 +78,23 @@ def test_tile_widths_agree_on_power_law(torch_cuda, W):
     _check(g, P, X, reps, 1e-7)
 
 
+@pytest.mark.parametrize("B", [5, 40, 100])
+def test_autotuned_tile_width(torch_cuda, B):
+    from paper_2112_01743_amd import Plan
+    g = gg.chung_lu(20000, 12, 2.1, seed=3, dmax=5000)
+    src = gg.random_sources(g.n, B, seed=8)
+    P = gg.source_personalization(g.n, src)
+    plan = Plan.from_graph(g, C, autotune=1)
+    X, reps = plan.solve_batched(_dev(torch_cuda, P), 1e-7)
+    W = plan.info()["tile_w"]
+    _note(f"B={B}: autotuned tile_w={W}")
+    assert W in (16, 32, 64)
+    _check(g, P, X.cpu().numpy(), reps, 1e-7)
+    X2, reps2 = plan.solve_batched(_dev(torch_cuda, P[:3]), 1e-7)
+    assert plan.info()["tile_w"] == W
+    _check(g, P[:3], X2.cpu().numpy(), reps2, 1e-7)
+
+
 def test_mixed_personalizations_and_strides(torch_cuda):
     from paper_2112_01743_amd import Plan
     torch = torch_cuda

@@ -1,0 +1,115 @@
+"""Parity at the full workload sizes, in the launch configuration bench.py times.
+
+At these sizes the oracle checks the GPU result through properties that hold at
+any size: its own FP64 residual r = b - (I - cP) x (one sparse product on the
+CPU) gives ||x - pi||_1 <= ||r||_1 / (1 - c), which must be <= tol; sampled
+columns are also compared with the oracle's power method.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+
+pytestmark = pytest.mark.gpu
+C = 0.85
+TOL = 1e-6
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2112_01743_amd import binding
+    binding.lib()
+    return torch
+
+
+def _note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _oracle_bound(g, B, X):
+    """Oracle's FP64 residual bound for each column; B, X: (cols, n)."""
+    r = oracle.residual(g, B.T, X.T, C)
+    return np.abs(r).sum(axis=0) / (1 - C)
+
+
+@pytest.mark.timeout(600)
+def test_chung_lu_4m_global(torch_cuda):
+    from paper_2112_01743_amd import Plan
+    torch = torch_cuda
+    g = gg.chung_lu(4_000_000, 16, 2.1, seed=2112001, dmin=1.0, dmax=50000.0)
+    _note(f"chung-lu n={g.n} nnz={g.nnz}")
+    plan = Plan.from_graph(g, C, time_kernels=1)     # the bench's plan options
+    p = np.full(g.n, 1.0 / g.n)
+    x, rep = plan.solve(torch.as_tensor(p, device="cuda"), TOL)
+    x = x.cpu().numpy()
+    bound = _oracle_bound(g, ((1 - C) * p)[None, :], x[None, :])[0]
+    _note(f"gpu bound {rep['cert_bound']:.3e} oracle bound {bound:.3e} terms {rep['terms']}")
+    assert rep["certified"] == 1 and bound <= TOL
+    assert abs(bound - rep["cert_bound"]) <= 1e-3 * bound + 1e-12
+    # sampled entries against the power method (certified to 1e-9)
+    pi, _ = oracle.pagerank_power(g, p, C, tol=1e-9)
+    idx = gg.philox(5).choice(g.n, 2000, replace=False)
+    idx = np.concatenate([idx, np.arange(50)])       # and the 50 largest-degree vertices
+    assert np.max(np.abs(x[idx] - pi[idx])) <= TOL + 1e-9
+    assert abs(x.sum() - 1.0) <= TOL
+
+
+@pytest.mark.timeout(600)
+def test_grid_256_sources(torch_cuda):
+    from paper_2112_01743_amd import Plan
+    torch = torch_cuda
+    g = gg.perturbed_grid(1000, 0.05, 0.01, seed=2112002)
+    src = gg.random_sources(g.n, 256, seed=2112002)
+    _note(f"grid n={g.n} nnz={g.nnz}")
+    plan = Plan.from_graph(g, C, time_kernels=1)
+    P = torch.zeros((256, g.n), dtype=torch.float64, device="cuda")
+    P[torch.arange(256), torch.as_tensor(src, device="cuda")] = 1.0
+    X, reps = plan.solve_batched(P, TOL)
+    X = X.cpu().numpy()
+    assert all(r["certified"] for r in reps)
+    Pn = np.zeros((256, g.n))
+    Pn[np.arange(256), src] = 1.0
+    bounds = _oracle_bound(g, (1 - C) * Pn, X)
+    _note(f"oracle bounds max {bounds.max():.3e}")
+    assert bounds.max() <= TOL
+    # reversibility d_s pi_s(t) = d_t pi_t(s) among the sources, within the bounds
+    d = np.diff(g.row_ptr).astype(float)
+    M = X[:, src]
+    lhs = d[src][:, None] * M
+    tolm = d[src][:, None] * bounds[None, :] + d[src][None, :] * bounds[:, None]
+    assert np.all(np.abs(lhs - lhs.T) <= tolm + 1e-15)
+    # two sampled columns against the power method
+    for j in (0, 255):
+        pi, _ = oracle.pagerank_power(g, Pn[j], C, tol=1e-10)
+        assert np.abs(X[j] - pi).sum() <= TOL
+
+
+@pytest.mark.timeout(600)
+def test_uneven_batch_10k_graphs(torch_cuda):
+    from paper_2112_01743_amd import Plan
+    torch = torch_cuda
+    g = gg.uneven_batch(10_000, seed=2112003)
+    _, p = gg.batch_sources(g, seed=2112003)
+    _note(f"batch n={g.n} nnz={g.nnz}")
+    plan = Plan.from_graph(g, C, autotune=1)          # the bench's plan options
+    x, reps = plan.solve_graphs(torch.as_tensor(p, device="cuda"), TOL)
+    x = x.cpu().numpy()
+    assert all(r["certified"] for r in reps)
+    # the block-diagonal residual separates by graph
+    r = oracle.residual(g, (1 - C) * p, x, C)
+    gp = g.graph_ptr.astype(np.int64)
+    per_graph = np.add.reduceat(np.abs(r), gp[:-1]) / (1 - C)
+    _note(f"oracle per-graph bounds max {per_graph.max():.3e}")
+    assert per_graph.max() <= TOL
+    for k in gg.philox(3).choice(g.num_graphs, 6, replace=False):
+        sub = gg.subgraph(g, k)
+        v0, v1 = gp[k], gp[k + 1]
+        pi = oracle.pagerank_exact(sub, p[v0:v1], C)
+        assert np.abs(x[v0:v1] - pi).sum() <= TOL

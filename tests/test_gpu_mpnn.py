@@ -77,7 +77,49 @@ def test_gradients_match_oracle(torch_cuda):
         assert diff <= 5e-2 * np.linalg.norm(r) + 1e-6, (k, diff)
 
 
+def test_training_steps_match_oracle_along_trajectory(torch_cuda):
+    """Each GPU train step: its loss and gradient equal the oracle's at the
+    GPU's current parameters, and the Adam update equals the FP64 Adam
+    reference applied to the GPU's gradient."""
+    from paper_2112_01743_amd import Plan
+    from paper_2112_01743_amd.binding import Model, pack_params, unpack_params
+    torch = torch_cuda
+    g = gg.chung_lu(3000, 8, 2.3, seed=11)
+    plan = Plan.from_graph(g, C)
+    model = Model(plan, gg.mpnn_init(2))
+    src = gg.random_sources(g.n, 16, seed=3)
+    T, _ = plan.solve_batched(_dev(torch, gg.source_personalization(g.n, src)), 1e-9)
+    Tn = T.cpu().numpy()
+    for step in range(4):
+        idx = np.arange(4) + 4 * step
+        w, m, v, k = model.get_state()
+        params = {n: a.astype(np.float64) for n, a in unpack_params(w, 3).items()}
+        ref, loss_ref = None, 0.0
+        for j in idx:
+            x0, cache = om.mpnn_forward(g, params, src[j], bf16=True)
+            loss_ref += om.mpnn_l1(x0, Tn[j]) / len(idx)
+            gj = om.mpnn_backward(params, cache, Tn[j], bf16=True)
+            ref = gj if ref is None else {n: ref[n] + gj[n] for n in ref}
+        ref = {n: a / len(idx) for n, a in ref.items()}
+        loss, grads = model.train_step(src[idx], T[idx], lr=3e-2, want_grads=True)
+        assert abs(loss - loss_ref) <= 1e-5 * loss_ref, (step, loss, loss_ref)
+        for n in ref:
+            if n == "b_out":      # exactly zero in exact arithmetic
+                assert abs(grads[n][0]) <= 1e-6
+                continue
+            rel = np.linalg.norm(grads[n] - ref[n]) / np.linalg.norm(ref[n])
+            assert rel <= 1e-4, (step, n, rel)
+        w2 = model.get_state()[0]
+        w_ref, _, _ = om.adam_step(w, pack_params(grads, 3).astype(np.float64), m, v, k, 3e-2)
+        err = np.abs(w2 - w_ref).max()
+        _note(f"step {step}: loss {loss:.6f} (oracle {loss_ref:.6f}), Adam max diff {err:.1e}")
+        assert err <= 1e-6
+
+
 def test_training_on_cpaa_outputs_reduces_loss(torch_cuda):
+    """Learning-rate decay from 3e-2 to 3e-3: at a constant 3e-2 Adam
+    amplifies the FP32 rounding noise of near-zero gradient components and
+    the trajectory stalls near the stationary-vector error."""
     from paper_2112_01743_amd import Plan
     from paper_2112_01743_amd.binding import Model
     torch = torch_cuda
@@ -88,15 +130,20 @@ def test_training_on_cpaa_outputs_reduces_loss(torch_cuda):
     T, reps = plan.solve_batched(_dev(torch, gg.source_personalization(g.n, src)), 1e-6)
     assert all(r["certified"] for r in reps)
     losses = []
-    for step in range(60):
+    steps = 160
+    for step in range(steps):
         idx = np.arange(8) + 8 * (step % 8)
-        loss, _ = model.train_step(src[idx], T[idx], lr=3e-2)
+        lr = 3e-2 * 0.1 ** (step / (steps - 1))
+        loss, _ = model.train_step(src[idx], T[idx], lr=lr)
         losses.append(loss)
-    _note(f"L1 first {np.mean(losses[:8]):.4f} last {np.mean(losses[-8:]):.4f}")
-    assert np.mean(losses[-8:]) < 0.6 * np.mean(losses[:8])
+    X0 = model.predict(src).cpu().numpy()
+    Tn = T.cpu().numpy()
+    final = np.abs(X0 - Tn).sum(axis=1).mean()
     d = np.diff(g.row_ptr).astype(float)
-    stationary = np.mean([np.abs(d / d.sum() - T[j].cpu().numpy()).sum() for j in range(8)])
-    assert np.mean(losses[-8:]) < stationary
+    stationary = np.abs(d / d.sum() - Tn).sum(axis=1).mean()
+    _note(f"L1 first {np.mean(losses[:8]):.4f} final {final:.4f} stationary {stationary:.4f}")
+    assert final < 0.5 * np.mean(losses[:8])
+    assert final < 0.8 * stationary
 
 
 def test_warm_started_solves_judged_by_plain_cpaa(torch_cuda):

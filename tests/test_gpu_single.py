@@ -145,6 +145,22 @@ def test_work_item_sizes_agree(torch_cuda, npt):
     _assert_parity(g, p, x, rep, 1e-8)
 
 
+def test_autotuned_work_items(torch_cuda):
+    """The autotuner times candidate work-item sizes on the first plain solve,
+    keeps the fastest, and every later solve uses it."""
+    g = gg.chung_lu(60000, 12, 2.2, seed=17, dmax=10000)
+    p = gg.uniform_personalization(g.n)
+    x, rep, plan = _solve(torch_cuda, g, p, 1e-8, autotune=1)
+    npt = plan.info()["nnz_per_thread"]
+    _note(f"autotuned nnz_per_thread={npt}")
+    assert npt in (8, 16, 32)
+    _assert_parity(g, p, x, rep, 1e-8)
+    q = gg.source_personalization(g.n, [11])[0]
+    x2, rep2 = plan.solve(_dev(torch_cuda, q), 1e-8)
+    assert plan.info()["nnz_per_thread"] == npt
+    _assert_parity(g, q, x2.cpu().numpy(), rep2, 1e-8)
+
+
 @pytest.mark.parametrize("remap", [0, 1])
 def test_xcd_remap_agrees(torch_cuda, remap):
     g = gg.perturbed_grid(120, 0.05, 0.01, seed=9)

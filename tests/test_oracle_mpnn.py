@@ -108,3 +108,21 @@ def test_mutation_wrong_aggregation_transpose_is_caught(monkeypatch):
     monkeypatch.setattr(om, "mpnn_forward", wrong)
     _, cache = om.mpnn_forward(g, gg.mpnn_init(1, layers=1, hidden=4), 0, layers=1)
     assert not np.allclose(cache["M"][0], P @ cache["H"][0], atol=1e-10)
+
+
+def test_adam_first_step_is_signed_learning_rate():
+    # with zero moments, the bias-corrected first update is lr * g / (|g| + eps)
+    g = np.array([3.0, -2e-3, 0.0, 5e-9])
+    w, m, v = om.adam_step(np.ones(4), g, np.zeros(4), np.zeros(4), 0, 0.1)
+    assert np.allclose(w, 1.0 - 0.1 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-15)
+    assert abs(w[0] - 0.9) < 1e-9 and abs(w[1] - 1.1) < 1e-6 and w[2] == 1.0
+    assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
+
+
+def test_adam_constant_gradient_moves_lr_per_step():
+    # bias correction makes m_hat = g and v_hat = g^2 exactly for a constant gradient
+    w, m, v = np.zeros(3), np.zeros(3), np.zeros(3)
+    g = np.array([0.5, -4.0, 1e-3])
+    for t in range(25):
+        w, m, v = om.adam_step(w, g, m, v, t, 0.01)
+    assert np.allclose(w, -25 * 0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=0)
