@@ -93,10 +93,22 @@ typedef struct {
   int32_t time_kernels;   /* 1: time every term kernel with HIP events (report.ms_terms) */
   int32_t xcd_remap;      /* -1 auto (off for single-vector kernels, on for tiled kernels),
                              0/1: map workgroups to contiguous row ranges per XCD */
-  int32_t autotune;       /* 1: the first cpaa_solve_graphs call times the candidate workgroup
-                             sizes (256, 512, 1024 threads per graph) on its own input and keeps
-                             the fastest; the first cpaa_solve_batched call does the same for
-                             tile_w (16, 32, 64) when tile_w = 0 */
+  int32_t autotune;       /* 1: the first call of each solve path times its candidate launch
+                             shapes on its own input and keeps the fastest for the plan:
+                             cpaa_solve (plain solve): work maps of 8/16/32 entries per thread
+                             (when nnz_per_thread = 0); cpaa_solve_batched: tile_w 16/32/64
+                             (when tile_w = 0); cpaa_solve_graphs: 256/512/1024 threads per
+                             graph */
+  int32_t column_slices;  /* single-vector path: 0 auto, 1 off, 8 on.  On: vertices are relabelled
+                             by degree rank dealt round-robin into 8 contiguous slices (equal
+                             size and near-equal degree sum); each term's SpMV then runs per
+                             column slice, slice s on the workgroups the hardware places on XCD
+                             s, so every XCD gathers from one eighth of the vector, which stays
+                             in its L2, and a combine pass adds the 8 partial row sums and
+                             applies the term update.  Auto: on for one graph with n >= 2^20
+                             and max degree >= 16 x average degree.  Needs one graph and
+                             n < 8 (2^21 - 1) (else CPAA_EINVAL).  Inputs and outputs keep the caller's
+                             labels. */
 } cpaa_opts;
 
 /* Per-solve report (one per right-hand side in batched calls, one per graph in
@@ -124,7 +136,7 @@ typedef struct {
   int32_t n;
   int64_t nnz;
   int32_t num_graphs;
-  int32_t reordered;        /* 1 if vertices were relabelled by degree */
+  int32_t reordered;        /* 1 if the single-vector path relabelled the vertices */
   int32_t max_degree;
   int32_t split_rows;       /* rows split across workgroups */
   int32_t nnz_per_thread;   /* single-vector work item size / 256 */
@@ -134,6 +146,7 @@ typedef struct {
   double c;
   double beta;
   double vol;               /* sum of degrees */
+  int32_t column_slices;    /* single-vector term: 1 (row order) or 8 (column-sliced) */
 } cpaa_plan_info;
 
 /* Fill *o with defaults.  Never fails. */

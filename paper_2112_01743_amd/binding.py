@@ -36,7 +36,8 @@ class cpaa_opts(ctypes.Structure):
                 ("normalize", ctypes.c_int32), ("nnz_per_thread", ctypes.c_int32),
                 ("tile_w", ctypes.c_int32), ("validate", ctypes.c_int32),
                 ("io_device", ctypes.c_int32), ("time_kernels", ctypes.c_int32),
-                ("xcd_remap", ctypes.c_int32), ("autotune", ctypes.c_int32)]
+                ("xcd_remap", ctypes.c_int32), ("autotune", ctypes.c_int32),
+                ("column_slices", ctypes.c_int32)]
 
 
 class cpaa_report(ctypes.Structure):
@@ -59,7 +60,8 @@ class cpaa_plan_info(ctypes.Structure):
                 ("split_rows", ctypes.c_int32), ("nnz_per_thread", ctypes.c_int32),
                 ("work_items", ctypes.c_int32), ("tile_w", ctypes.c_int32),
                 ("k_cap_global", ctypes.c_int32), ("c", ctypes.c_double),
-                ("beta", ctypes.c_double), ("vol", ctypes.c_double)]
+                ("beta", ctypes.c_double), ("vol", ctypes.c_double),
+                ("column_slices", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

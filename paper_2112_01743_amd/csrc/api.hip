@@ -7,6 +7,7 @@
 // Chebyshev coefficients c_k = 2 beta^k / sqrt(1-c^2) (Prop. 1) and uploads
 // the pattern to the device.
 #include <algorithm>
+#include <thread>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -172,6 +173,143 @@ void build_tile_items(int32_t n, const int32_t* rp, std::vector<WorkItem>& items
   }
 }
 
+// Run body(i) for i in [0, count) on up to 16 host threads.
+template <typename F>
+void parallel_for(int64_t count, F body) {
+  const int64_t nt = std::max<int64_t>(
+      1, std::min<int64_t>({16, (int64_t)std::thread::hardware_concurrency(), count}));
+  std::vector<std::thread> pool;
+  auto run = [&](int64_t t) {
+    for (int64_t i = t * count / nt; i < (t + 1) * count / nt; ++i) body(i);
+  };
+  for (int64_t t = 1; t < nt; ++t) pool.emplace_back(run, t);
+  run(0);
+  for (std::thread& th : pool) th.join();
+}
+
+// Labelling of the column-sliced path: vertices ranked by degree (descending,
+// ties by label) and dealt round-robin into kSlices slices, slice s taking the
+// contiguous labels [slice_off[s], slice_off[s+1]).  Every slice gets n/8
+// vertices and about vol/8 stored entries as columns.  Returns the relabelled
+// CSR (rows and columns in new labels, columns sorted) and perm[new] = old.
+void slice_relabel(int32_t n, const int32_t* rp, const int32_t* ci, std::vector<int32_t>& rp2,
+                   std::vector<int32_t>& ci2, std::vector<int32_t>& perm,
+                   int slice_off[kSlices + 1]) {
+  std::vector<int32_t> order(n);
+  for (int32_t v = 0; v < n; ++v) order[v] = v;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+    return rp[a + 1] - rp[a] > rp[b + 1] - rp[b];
+  });
+  slice_off[0] = 0;
+  for (int sl = 0; sl < kSlices; ++sl)
+    slice_off[sl + 1] = slice_off[sl] + (n > sl ? (n - sl + kSlices - 1) / kSlices : 0);
+  std::vector<int32_t> new_of(n);
+  perm.assign(n, 0);
+  for (int32_t r = 0; r < n; ++r) {
+    const int32_t u = slice_off[r % kSlices] + r / kSlices;
+    new_of[order[r]] = u;
+    perm[u] = order[r];
+  }
+  rp2.assign(static_cast<size_t>(n) + 1, 0);
+  for (int32_t u = 0; u < n; ++u) rp2[u + 1] = rp2[u] + (rp[perm[u] + 1] - rp[perm[u]]);
+  ci2.resize(static_cast<size_t>(rp2[n]));
+  parallel_for(n, [&](int64_t u) {
+    const int32_t v = perm[u];
+    int32_t* dst = ci2.data() + rp2[u];
+    for (int32_t j = rp[v]; j < rp[v + 1]; ++j) *dst++ = new_of[ci[j]];
+    std::sort(ci2.data() + rp2[u], dst);
+  });
+}
+
+// Work items and packed entries of the column-sliced term (relabelled CSR).
+// Per slice the items cover every row (rows without entries in the slice
+// still get their zero partial written): consecutive rows with at most
+// kWG * kSliceNpt entries and kSliceRows rows per item; a row with more entries
+// in one slice than an item holds is cut into split chunks (plain local
+// columns, nnz1 = physical end).  Multi-row items store their entries in the
+// transposed per-wavefront layout described below; nnz0 is the physical start
+// and nnz1 - nnz0 the number of entries (the layout pads each wavefront's
+// share to a multiple of 64 with kSliceNone).
+void build_sliced(int32_t n, const std::vector<int32_t>& rp2, const std::vector<int32_t>& ci2,
+                  const int slice_off[kSlices + 1], std::vector<uint32_t>& entries,
+                  std::vector<WorkItem>& items, std::vector<int>& split_nchunks,
+                  int item_off[kSlices + 1]) {
+  const int cap = kWG * kSliceNpt;
+  std::vector<std::vector<uint32_t>> ent(kSlices);
+  std::vector<std::vector<WorkItem>> its(kSlices);
+  std::vector<std::vector<int>> nch(kSlices);
+  parallel_for(kSlices, [&](int64_t sl) {
+    const int32_t lo = slice_off[sl], hi = slice_off[sl + 1];
+    std::vector<int32_t> beg(n), len(n);
+    for (int32_t u = 0; u < n; ++u) {
+      const int32_t* a = ci2.data() + rp2[u];
+      const int32_t* b = ci2.data() + rp2[u + 1];
+      const int32_t* x = std::lower_bound(a, b, lo);
+      const int32_t* y = std::lower_bound(x, b, hi);
+      beg[u] = static_cast<int32_t>(x - ci2.data());
+      len[u] = static_cast<int32_t>(y - x);
+    }
+    std::vector<uint32_t>& E = ent[sl];
+    std::vector<WorkItem>& I = its[sl];
+    std::vector<uint32_t> logical;
+    int32_t r = 0;
+    while (r < n) {
+      if (len[r] > cap) {
+        const int slot = static_cast<int>(nch[sl].size());
+        const int chunks = (len[r] + cap - 1) / cap;
+        for (int c = 0; c < chunks; ++c) {
+          const int e0 = static_cast<int>(E.size());
+          const int a = beg[r] + c * cap, b = std::min(a + cap, beg[r] + len[r]);
+          for (int j = a; j < b; ++j) E.push_back(static_cast<uint32_t>(ci2[j] - lo));
+          I.push_back({r, -(slot + 1), e0, static_cast<int>(E.size())});
+        }
+        nch[sl].push_back(chunks);
+        ++r;
+        continue;
+      }
+      const int32_t r0 = r;
+      logical.clear();
+      while (r < n && r - r0 < kSliceRows && len[r] <= cap &&
+             static_cast<int>(logical.size()) + len[r] <= cap) {
+        for (int j = beg[r]; j < beg[r] + len[r]; ++j)
+          logical.push_back((static_cast<uint32_t>(ci2[j] - lo) << kSliceRowBits) |
+                            static_cast<uint32_t>(r - r0));
+        ++r;
+      }
+      // Wavefront w takes logical entries [w*64*kSliceNpt, ...), lane l a
+      // contiguous run of RL = ceil(len/64) of them, stored transposed
+      // (run element i of lane l at i*64 + l) so the loads stay coalesced.
+      const int e0 = static_cast<int>(E.size());
+      const int L = static_cast<int>(logical.size());
+      for (int q0 = 0; q0 < L; q0 += 64 * kSliceNpt) {
+        const int Lw = std::min(64 * kSliceNpt, L - q0);
+        const int RL = (Lw + 63) / 64;
+        const size_t pb = E.size();
+        E.resize(pb + static_cast<size_t>(64) * RL, kSliceNone);
+        for (int q = 0; q < Lw; ++q) E[pb + (q % RL) * 64 + q / RL] = logical[q0 + q];
+      }
+      I.push_back({r0, r, e0, e0 + L});   // nnz1 - nnz0 = logical length
+    }
+  });
+  entries.clear();
+  items.clear();
+  split_nchunks.clear();
+  item_off[0] = 0;
+  for (int sl = 0; sl < kSlices; ++sl) {
+    const int ebase = static_cast<int>(entries.size());
+    const int sbase = static_cast<int>(split_nchunks.size());
+    for (WorkItem it : its[sl]) {
+      it.nnz0 += ebase;
+      it.nnz1 += ebase;
+      if (it.row1 < 0) it.row1 -= sbase;
+      items.push_back(it);
+    }
+    entries.insert(entries.end(), ent[sl].begin(), ent[sl].end());
+    split_nchunks.insert(split_nchunks.end(), nch[sl].begin(), nch[sl].end());
+    item_off[sl + 1] = static_cast<int>(items.size());
+  }
+}
+
 }  // namespace
 }  // namespace cpaa
 
@@ -217,6 +355,12 @@ void cpaa_plan_destroy(cpaa_plan_t pl) {
     if (m.d_items) (void)hipFree(m.d_items);
     if (m.d_split_nchunks) (void)hipFree(m.d_split_nchunks);
   }
+  if (pl->sliced) {
+    void* sp[] = {pl->d_rp_w1, pl->d_ci_w1, pl->d_perm, pl->slc.d_entries, pl->slc.d_items,
+                  pl->slc.d_split_nchunks};
+    for (void* p : sp)
+      if (p) (void)hipFree(p);
+  }
   void* ptrs[] = {pl->d_row_ptr, pl->d_col_idx, pl->d_titems, pl->d_tsplit_nchunks,
                   pl->d_graph_ptr, pl->d_graph_order, pl->d_queue};
   for (void* p : ptrs)
@@ -253,6 +397,14 @@ cpaa_status cpaa_plan(const cpaa_csr* g, double c, const cpaa_opts* opts, cpaa_p
   }
   if (o.tile_w != 0 && o.tile_w != 8 && o.tile_w != 16 && o.tile_w != 32 && o.tile_w != 64) {
     set_error("tile_w must be 0, 8, 16, 32 or 64");
+    return CPAA_EINVAL;
+  }
+  if (o.column_slices != 0 && o.column_slices != 1 && o.column_slices != kSlices) {
+    set_error("column_slices must be 0, 1 or 8");
+    return CPAA_EINVAL;
+  }
+  if (o.column_slices == kSlices && (g->num_graphs > 1 || g->n >= kSliceMaxN)) {
+    set_error("column slices need one graph with n < 8 (2^21 - 1)");
     return CPAA_EINVAL;
   }
   if (o.k_max < 0 || o.max_refine < 0) {
@@ -354,14 +506,23 @@ cpaa_status cpaa_plan(const cpaa_csr* g, double c, const cpaa_opts* opts, cpaa_p
   // single-vector kernel, so "auto" enables it for tiles only.
   pl->xcd_remap = o.xcd_remap < 0 ? 0 : (o.xcd_remap ? 1 : 0);
   pl->xcd_remap_tile = o.xcd_remap < 0 ? 1 : (o.xcd_remap ? 1 : 0);
+  // Column slices keep each XCD's gathers inside one eighth of the vector
+  // (its L2); they pay off when the vector outgrows an L2 and the degrees are
+  // skewed (a lattice's natural order is already local).
+  pl->sliced = o.column_slices == kSlices ||
+               (o.column_slices == 0 && num_graphs == 1 && n >= (1 << 20) &&
+                n < kSliceMaxN && static_cast<double>(maxd) >= 16.0 * vol / n);
+  std::vector<int32_t> rp2, ci2, perm;
+  if (pl->sliced) slice_relabel(n, rp, ci, rp2, ci2, perm, pl->slc.slice_off);
+  const int32_t* rp1 = pl->sliced ? rp2.data() : rp;   // single-vector labelling
   // candidate work maps: the chosen npt, plus the other sizes when autotuning
   std::vector<int> npts = {pl->npt};
-  if (o.autotune && o.nnz_per_thread == 0 && num_graphs == 1)
+  if (o.autotune && o.nnz_per_thread == 0 && num_graphs == 1 && !pl->sliced)
     for (int c : {8, 16, 32})
       if (c != pl->npt) npts.push_back(c);
   std::vector<std::vector<WorkItem>> item_sets(npts.size());
   std::vector<std::vector<int>> nch_sets(npts.size());
-  for (size_t i = 0; i < npts.size(); ++i) build_items(n, rp, npts[i], item_sets[i], nch_sets[i]);
+  for (size_t i = 0; i < npts.size(); ++i) build_items(n, rp1, npts[i], item_sets[i], nch_sets[i]);
   std::vector<WorkItem> titems;
   std::vector<int> tnch;
   build_tile_items(n, rp, titems, tnch);
@@ -372,6 +533,25 @@ cpaa_status cpaa_plan(const cpaa_csr* g, double c, const cpaa_opts* opts, cpaa_p
   cpaa_status s = CPAA_OK;
   if (s == CPAA_OK) s = dev_upload(&pl->d_row_ptr, rp, n + 1);
   if (s == CPAA_OK) s = dev_upload(&pl->d_col_idx, ci, static_cast<size_t>(nnz));
+  if (s == CPAA_OK && pl->sliced) {
+    std::vector<uint32_t> entries;
+    std::vector<WorkItem> sitems;
+    std::vector<int> snch;
+    build_sliced(n, rp2, ci2, pl->slc.slice_off, entries, sitems, snch, pl->slc.item_off);
+    for (int sl = 0; sl < kSlices; ++sl)
+      pl->slc.max_items =
+          std::max(pl->slc.max_items, pl->slc.item_off[sl + 1] - pl->slc.item_off[sl]);
+    pl->slc.n_split_rows = static_cast<int>(snch.size());
+    s = dev_upload(&pl->d_rp_w1, rp2.data(), rp2.size());
+    if (s == CPAA_OK) s = dev_upload(&pl->d_ci_w1, ci2.data(), ci2.size());
+    if (s == CPAA_OK) s = dev_upload(&pl->d_perm, perm.data(), perm.size());
+    if (s == CPAA_OK) s = dev_upload(&pl->slc.d_entries, entries.data(), entries.size());
+    if (s == CPAA_OK) s = dev_upload(&pl->slc.d_items, sitems.data(), sitems.size());
+    if (s == CPAA_OK) s = dev_upload(&pl->slc.d_split_nchunks, snch.data(), snch.size());
+  } else {
+    pl->d_rp_w1 = pl->d_row_ptr;
+    pl->d_ci_w1 = pl->d_col_idx;
+  }
   pl->maps.resize(npts.size());
   for (size_t i = 0; i < npts.size() && s == CPAA_OK; ++i) {
     WorkMap& m = pl->maps[i];
@@ -426,7 +606,7 @@ cpaa_status cpaa_plan_info_get(cpaa_plan_t pl, cpaa_plan_info* info) {
   info->n = pl->n;
   info->nnz = pl->nnz;
   info->num_graphs = pl->num_graphs;
-  info->reordered = 0;
+  info->reordered = pl->sliced ? 1 : 0;
   info->max_degree = pl->max_deg;
   info->split_rows = pl->n_split_rows;
   info->nnz_per_thread = pl->npt;
@@ -436,6 +616,7 @@ cpaa_status cpaa_plan_info_get(cpaa_plan_t pl, cpaa_plan_info* info) {
   info->beta = pl->beta;
   info->vol = pl->vol;
   info->k_cap_global = mass_rule_terms(pl, 1e-6);
+  info->column_slices = pl->sliced ? kSlices : 1;
   return CPAA_OK;
 }
 

@@ -16,7 +16,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/cpaa.h"
+#include "cpaa.h"
 
 namespace cpaa {
 
@@ -53,6 +53,29 @@ struct WorkItem {
   int nnz1;
 };
 
+// Column-sliced single-vector term (one column slice per XCD).  Vertices are
+// relabelled so that slice s is the contiguous label range
+// [slice_off[s], slice_off[s+1]); slice s's stored entries (row order) are
+// packed as (column - slice_off[s]) << kSliceRowBits | (row - item.row0).
+// Chunks of rows split across workgroups store the plain local column.
+constexpr int kSlices = 8;           // XCDs of the chip
+constexpr int kSliceRowBits = 11;    // rows per sliced work item < 2048
+constexpr int kSliceRows = 1 << kSliceRowBits;
+constexpr int kSliceNpt = 32;        // entries per thread of a sliced work item
+// local columns stay below 2^21 - 1, so no packed entry equals kSliceNone
+constexpr int64_t kSliceMaxN = int64_t(kSlices) * ((int64_t(1) << (32 - kSliceRowBits)) - 1);
+constexpr uint32_t kSliceNone = 0xFFFFFFFFu;   // padding entry
+
+struct SlicedMap {
+  uint32_t* d_entries = nullptr;     // [nnz] slice-major
+  WorkItem* d_items = nullptr;       // slice-major; nnz offsets index d_entries
+  int item_off[kSlices + 1] = {};    // items of slice s: [item_off[s], item_off[s+1])
+  int max_items = 0;                 // most items in one slice
+  int slice_off[kSlices + 1] = {};   // vertex labels of slice s
+  int n_split_rows = 0;
+  int* d_split_nchunks = nullptr;    // [n_split_rows]
+};
+
 // One decomposition of the CSR into single-vector work items (for one npt).
 struct WorkMap {
   int npt = 0;
@@ -77,6 +100,7 @@ struct Workspace {
   int* done = nullptr;           // [tiles]
   int* terms = nullptr;          // [tiles]
   double* series_cert = nullptr; // [cols]
+  float* part = nullptr;         // column-sliced term: [kSlices][n] FP32 partial row sums
   float* split_f = nullptr;      // [split slots * W] FP32 partial sums
   double* split_d = nullptr;     // [split slots * W] FP64 partial sums (residual)
   int* split_count = nullptr;    // [split slots] arrivals
@@ -104,6 +128,14 @@ struct cpaa_plan_s {
 
   int32_t* d_row_ptr = nullptr;
   int32_t* d_col_idx = nullptr;
+
+  // single-vector path: its own labelling of the graph (relabelled when
+  // column-sliced; otherwise these alias d_row_ptr / d_col_idx)
+  int32_t* d_rp_w1 = nullptr;
+  int32_t* d_ci_w1 = nullptr;
+  int32_t* d_perm = nullptr;         // [n] single-vector label -> caller's label, or null
+  bool sliced = false;
+  cpaa::SlicedMap slc;
 
   // single-vector work map in use (one of `maps`)
   int npt = 8;                       // nnz per thread of a work item

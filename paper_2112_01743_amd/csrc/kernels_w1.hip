@@ -21,6 +21,47 @@
 namespace cpaa {
 namespace {
 
+// Chunk of a row split over several workgroups: the block's partial sums
+// (s, and sa = sum of magnitudes with ABS) go to the row's atomic slot; the
+// last arriving block reads the full sums, resets the slot and counter, and
+// runs the row's epilogue.
+template <typename V, bool ABS, typename Epi>
+__device__ __forceinline__ void split_chunk_finish(const WorkItem it, const int* __restrict__ rp,
+                                                   V s, V sa, V* __restrict__ split_part,
+                                                   int* __restrict__ split_count,
+                                                   const int* __restrict__ split_nchunks,
+                                                   Epi& epi) {
+  __shared__ V wsum[4];
+  __shared__ V wabs[4];
+  const int t = threadIdx.x;
+  s = wave_sum(s);
+  if (ABS) sa = wave_sum(sa);
+  if ((t & 63) == 0) {
+    wsum[t >> 6] = s;
+    wabs[t >> 6] = sa;
+  }
+  __syncthreads();
+  if (t == 0) {
+    const int slot = -(it.row1 + 1);
+    const int ps = ABS ? 2 * slot : slot;
+    atomic_add(&split_part[ps], (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]));
+    if (ABS) atomic_add(&split_part[ps + 1], (wabs[0] + wabs[1]) + (wabs[2] + wabs[3]));
+    __threadfence();
+    const int prev = atomicAdd(&split_count[slot], 1);
+    if (prev == split_nchunks[slot] - 1) {
+      __threadfence();
+      const V full = __hip_atomic_exchange(&split_part[ps], V(0), __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+      V full_abs = V(0);
+      if (ABS)
+        full_abs = __hip_atomic_exchange(&split_part[ps + 1], V(0), __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_exchange(&split_count[slot], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      epi.row(it.row0, rp[it.row0 + 1] - rp[it.row0], full, full_abs);
+    }
+  }
+}
+
 // Sum of x over N(u) for the rows of one work item; calls
 // epi.row(u, d_u, sum, sum_of_magnitudes) exactly once per row, from one thread.
 // With ABS the sum of |x| over N(u) is formed too (split partials then use
@@ -33,8 +74,6 @@ __device__ __forceinline__ void spmv_item(const WorkItem it, const int* __restri
   constexpr int CAP = kWG * NPT;
   __shared__ V vals[CAP];
   __shared__ int lrp[kWG * 4 + 1];
-  __shared__ V wsum[4];
-  __shared__ V wabs[4];
   const int t = threadIdx.x;
   const int nb = it.nnz0, ne = it.nnz1;
 
@@ -56,32 +95,7 @@ __device__ __forceinline__ void spmv_item(const WorkItem it, const int* __restri
       s += v[i];
       if (ABS) sa += fabs(v[i]);
     }
-    s = wave_sum(s);
-    if (ABS) sa = wave_sum(sa);
-    if ((t & 63) == 0) {
-      wsum[t >> 6] = s;
-      wabs[t >> 6] = sa;
-    }
-    __syncthreads();
-    if (t == 0) {
-      const int slot = -(it.row1 + 1);
-      const int ps = ABS ? 2 * slot : slot;
-      atomic_add(&split_part[ps], (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]));
-      if (ABS) atomic_add(&split_part[ps + 1], (wabs[0] + wabs[1]) + (wabs[2] + wabs[3]));
-      __threadfence();
-      const int prev = atomicAdd(&split_count[slot], 1);
-      if (prev == split_nchunks[slot] - 1) {
-        __threadfence();
-        const V full = __hip_atomic_exchange(&split_part[ps], V(0), __ATOMIC_RELAXED,
-                                             __HIP_MEMORY_SCOPE_AGENT);
-        V full_abs = V(0);
-        if (ABS)
-          full_abs = __hip_atomic_exchange(&split_part[ps + 1], V(0), __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_exchange(&split_count[slot], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        epi.row(it.row0, rp[it.row0 + 1] - rp[it.row0], full, full_abs);
-      }
-    }
+    split_chunk_finish<V, ABS>(it, rp, s, sa, split_part, split_count, split_nchunks, epi);
     return;
   }
 
@@ -183,6 +197,144 @@ __global__ __launch_bounds__(kWG) void k_term_w1(TermArgs a) {
   }
 }
 
+// ---- column-sliced term ----
+// Pass 1 (k_term_sliced): workgroup b runs on XCD b % 8 (the hardware's
+// round-robin dispatch) and takes work items of column slice b % 8, so an
+// XCD's gathers stay inside one eighth of z_k, which its L2 holds.  Each item
+// writes the partial row sums of its rows into part[slice][row] (zeros for
+// rows without entries in the slice).  Pass 2 (k_combine_w1) adds the eight
+// partials in a fixed order and runs the term epilogue.
+struct SlicedArgs {
+  const uint32_t* entries;
+  const WorkItem* items;
+  const int* rp;
+  const float* zc;
+  float* part;
+  const int* done;
+  float* split_part;
+  int* split_count;
+  const int* split_nchunks;
+  int n;
+  int item_off[kSlices + 1];
+  int slice_off[kSlices + 1];
+};
+
+struct PartEpi {
+  float* __restrict__ out;
+  __device__ __forceinline__ void row(int r, int, float s, float) { out[r] = s; }
+};
+
+template <int NPT>
+__global__ __launch_bounds__(kWG) void k_term_sliced(SlicedArgs a) {
+  if (a.done != nullptr && *a.done) return;
+  const int sl = blockIdx.x % kSlices;
+  const int k = a.item_off[sl] + static_cast<int>(blockIdx.x / kSlices);
+  if (k >= a.item_off[sl + 1]) return;
+  const WorkItem it = a.items[k];
+  const float* __restrict__ xs = a.zc + a.slice_off[sl];
+  PartEpi epi{a.part + static_cast<size_t>(sl) * a.n};
+  constexpr uint32_t kNone = kSliceNone;
+  const int t = threadIdx.x;
+  if (it.row1 < 0) {
+    // chunk of a split row: plain local columns
+    float sum = 0.f;
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+      const int j = it.nnz0 + t + i * kWG;
+      if (j < it.nnz1) sum += xs[__builtin_nontemporal_load(a.entries + j)];
+    }
+    split_chunk_finish<float, false>(it, a.rp, sum, 0.f, a.split_part, a.split_count,
+                                     a.split_nchunks, epi);
+    return;
+  }
+  __shared__ float rsum[kSliceRows];
+  const int lane = t & 63;
+  const int nrows = it.row1 - it.row0;
+  for (int r = t; r < nrows; r += kWG) rsum[r] = 0.f;
+  // Wavefront w owns the logical entries [q0, q0 + Lw); lane l owns the
+  // contiguous run [l*RL, (l+1)*RL) of them, stored transposed (element i of
+  // the run at physical i*64 + l), so every load below is coalesced while each
+  // lane walks its own rows in order.
+  const int q0 = (t >> 6) * 64 * NPT;
+  const int Lw = min(64 * NPT, (it.nnz1 - it.nnz0) - q0);
+  const int RL = Lw > 0 ? (Lw + 63) >> 6 : 0;
+  const uint32_t* __restrict__ pe = a.entries + it.nnz0 + q0 + lane;
+  uint32_t e[NPT];
+#pragma unroll
+  for (int i = 0; i < NPT; ++i) e[i] = (i < RL) ? __builtin_nontemporal_load(pe + i * 64) : kNone;
+  float v[NPT];
+#pragma unroll
+  for (int i = 0; i < NPT; ++i) v[i] = (e[i] != kNone) ? xs[e[i] >> kSliceRowBits] : 0.f;
+  __syncthreads();
+  // Row sums of the run in a register.  A row that starts and ends strictly
+  // inside the run has no other contributor: plain store.  The first and the
+  // last row of a run may be shared with neighbouring runs: LDS atomic.
+  constexpr uint32_t kMask = (1u << kSliceRowBits) - 1u;
+  int row = -1;
+  float sum = 0.f;
+  bool first = true;
+#pragma unroll
+  for (int i = 0; i < NPT; ++i) {
+    if (e[i] != kNone) {
+      const int r = static_cast<int>(e[i] & kMask);
+      if (r != row) {
+        if (row >= 0) {
+          if (first)
+            atomicAdd(&rsum[row], sum);
+          else
+            rsum[row] = sum;
+          first = false;
+        }
+        row = r;
+        sum = v[i];
+      } else {
+        sum += v[i];
+      }
+    }
+  }
+  // a row that covers every run of the wavefront: one wavefront sum
+  const int row_l0 = __builtin_amdgcn_readfirstlane(row);
+  if (__all(row == row_l0) && row_l0 >= 0) {
+    const float ws = wave_sum(sum);
+    if (lane == 0) atomicAdd(&rsum[row_l0], ws);
+  } else if (row >= 0) {
+    atomicAdd(&rsum[row], sum);
+  }
+  __syncthreads();
+  for (int r = t; r < nrows; r += kWG) epi.out[it.row0 + r] = rsum[r];
+}
+
+struct CombineArgs {
+  const int* rp;
+  const float* part;
+  const float* zc;
+  const float* zp;
+  float* zn;
+  double* acc;
+  float alpha, gamma;
+  double a_next, beta;
+  double* cert;
+  const int* done;
+  int n;
+};
+
+__global__ __launch_bounds__(kWG) void k_combine_w1(CombineArgs a) {
+  if (a.done != nullptr && *a.done) return;
+  TermEpi epi{a.zc, a.zp, a.zn, a.acc, a.alpha, a.gamma, a.a_next, a.beta,
+              a.cert != nullptr, 0.0};
+  const size_t n = static_cast<size_t>(a.n);
+  for (int u = blockIdx.x * kWG + threadIdx.x; u < a.n; u += gridDim.x * kWG) {
+    float s = 0.f;
+#pragma unroll
+    for (int k = 0; k < kSlices; ++k) s += a.part[k * n + u];
+    epi.row(u, a.rp[u + 1] - a.rp[u], s, 0.f);
+  }
+  if (a.cert != nullptr) {
+    const double c = block_sum256(epi.cert);
+    if (threadIdx.x == 0 && c != 0.0) atomic_add(&a.cert[blockIdx.x % kSlots], c);
+  }
+}
+
 struct ResidEpi {
   const double* __restrict__ acc;
   const double* __restrict__ b;
@@ -250,6 +402,7 @@ __global__ __launch_bounds__(kWG) void k_resid_w1(ResidArgs a) {
 // z_0 = b / d (FP32), acc (+)= (c_0/2) b / d (FP64), b = scale * src.
 // Statistics: [0] sum src, [2] sum b^2/d, [4] #negative src, [5] #non-finite src.
 __global__ __launch_bounds__(kWG) void k_init_w1(int n, const int* __restrict__ rp,
+                                                 const int* __restrict__ perm,
                                                  const double* __restrict__ src, double scale,
                                                  int add, int store_b, int series, double c0h,
                                                  double* __restrict__ b, float* __restrict__ z0,
@@ -257,7 +410,7 @@ __global__ __launch_bounds__(kWG) void k_init_w1(int n, const int* __restrict__ 
                                                  double* __restrict__ stat_slots) {
   double f_sum = 0, f_q = 0, f_neg = 0, f_bad = 0;
   for (int u = blockIdx.x * kWG + threadIdx.x; u < n; u += gridDim.x * kWG) {
-    const double p = src[u];
+    const double p = src[perm ? perm[u] : u];
     const double bu = scale * p;
     const double d = static_cast<double>(rp[u + 1] - rp[u]);
     const double y = bu / d;
@@ -284,12 +437,13 @@ __global__ __launch_bounds__(kWG) void k_init_w1(int n, const int* __restrict__ 
 
 // acc = x0 / d; statistic [1] counts non-finite x0 entries.
 __global__ __launch_bounds__(kWG) void k_load_x0_w1(int n, const int* __restrict__ rp,
+                                                    const int* __restrict__ perm,
                                                     const double* __restrict__ x0,
                                                     double* __restrict__ acc,
                                                     double* __restrict__ stat_slots) {
   double f_bad = 0;
   for (int u = blockIdx.x * kWG + threadIdx.x; u < n; u += gridDim.x * kWG) {
-    const double v = x0[u];
+    const double v = x0[perm ? perm[u] : u];
     f_bad += isfinite(v) ? 0.0 : 1.0;
     acc[u] = v / static_cast<double>(rp[u + 1] - rp[u]);
   }
@@ -300,10 +454,11 @@ __global__ __launch_bounds__(kWG) void k_load_x0_w1(int n, const int* __restrict
 
 // x = scale * D acc
 __global__ __launch_bounds__(kWG) void k_finalize_w1(int n, const int* __restrict__ rp,
+                                                     const int* __restrict__ perm,
                                                      const double* __restrict__ acc, double scale,
                                                      double* __restrict__ x) {
   for (int u = blockIdx.x * kWG + threadIdx.x; u < n; u += gridDim.x * kWG)
-    x[u] = scale * static_cast<double>(rp[u + 1] - rp[u]) * acc[u];
+    x[perm ? perm[u] : u] = scale * static_cast<double>(rp[u + 1] - rp[u]) * acc[u];
 }
 
 int elem_grid(int64_t n) {
@@ -315,23 +470,58 @@ int elem_grid(int64_t n) {
 
 hipError_t init_w1(const cpaa_plan_s* pl, Workspace& ws, const double* src, double scale,
                    bool add, bool store_b, bool series, hipStream_t st) {
-  hipLaunchKernelGGL(k_init_w1, dim3(elem_grid(pl->n)), dim3(kWG), 0, st, pl->n, pl->d_row_ptr,
-                     src, scale, add ? 1 : 0, store_b ? 1 : 0, series ? 1 : 0, pl->ck[0] / 2.0,
+  hipLaunchKernelGGL(k_init_w1, dim3(elem_grid(pl->n)), dim3(kWG), 0, st, pl->n, pl->d_rp_w1,
+                     src == ws.r ? nullptr : pl->d_perm, src, scale, add ? 1 : 0, store_b ? 1 : 0, series ? 1 : 0, pl->ck[0] / 2.0,
                      ws.b, ws.z[0], ws.acc, ws.stat_slots);
   return hipGetLastError();
 }
 
 hipError_t load_x0_w1(const cpaa_plan_s* pl, Workspace& ws, const double* x0, hipStream_t st) {
   hipLaunchKernelGGL(k_load_x0_w1, dim3(elem_grid(pl->n)), dim3(kWG), 0, st, pl->n,
-                     pl->d_row_ptr, x0, ws.acc, ws.stat_slots);
+                     pl->d_rp_w1, pl->d_perm, x0, ws.acc, ws.stat_slots);
   return hipGetLastError();
 }
 
 hipError_t term_w1(const cpaa_plan_s* pl, Workspace& ws, int cur, int prev, int next, bool first,
                    double a_next, double* cert_slot, const int* done, hipStream_t st) {
+  if (pl->sliced) {
+    SlicedArgs s;
+    s.entries = pl->slc.d_entries;
+    s.items = pl->slc.d_items;
+    s.rp = pl->d_rp_w1;
+    s.zc = ws.z[cur];
+    s.part = ws.part;
+    s.done = done;
+    s.split_part = ws.split_f;
+    s.split_count = ws.split_count;
+    s.split_nchunks = pl->slc.d_split_nchunks;
+    s.n = pl->n;
+    for (int i = 0; i <= kSlices; ++i) {
+      s.item_off[i] = pl->slc.item_off[i];
+      s.slice_off[i] = pl->slc.slice_off[i];
+    }
+    hipLaunchKernelGGL(k_term_sliced<kSliceNpt>, dim3(kSlices * pl->slc.max_items), dim3(kWG), 0,
+                       st, s);
+    CombineArgs c;
+    c.rp = pl->d_rp_w1;
+    c.part = ws.part;
+    c.zc = ws.z[cur];
+    c.zp = first ? nullptr : ws.z[prev];
+    c.zn = ws.z[next];
+    c.acc = ws.acc;
+    c.alpha = first ? 1.f : 2.f;
+    c.gamma = first ? 0.f : 1.f;
+    c.a_next = a_next;
+    c.beta = pl->beta;
+    c.cert = cert_slot;
+    c.done = done;
+    c.n = pl->n;
+    hipLaunchKernelGGL(k_combine_w1, dim3(elem_grid(pl->n)), dim3(kWG), 0, st, c);
+    return hipGetLastError();
+  }
   TermArgs a;
-  a.rp = pl->d_row_ptr;
-  a.ci = pl->d_col_idx;
+  a.rp = pl->d_rp_w1;
+  a.ci = pl->d_ci_w1;
   a.items = pl->d_items;
   a.zc = ws.z[cur];
   a.zp = first ? nullptr : ws.z[prev];
@@ -359,8 +549,8 @@ hipError_t term_w1(const cpaa_plan_s* pl, Workspace& ws, int cur, int prev, int 
 
 hipError_t residual_w1(const cpaa_plan_s* pl, Workspace& ws, hipStream_t st) {
   ResidArgs a;
-  a.rp = pl->d_row_ptr;
-  a.ci = pl->d_col_idx;
+  a.rp = pl->d_rp_w1;
+  a.ci = pl->d_ci_w1;
   a.items = pl->d_items;
   a.acc = ws.acc;
   a.b = ws.b;
@@ -384,7 +574,7 @@ hipError_t residual_w1(const cpaa_plan_s* pl, Workspace& ws, hipStream_t st) {
 hipError_t finalize_w1(const cpaa_plan_s* pl, Workspace& ws, double* x, double scale,
                        hipStream_t st) {
   hipLaunchKernelGGL(k_finalize_w1, dim3(elem_grid(pl->n)), dim3(kWG), 0, st, pl->n,
-                     pl->d_row_ptr, ws.acc, scale, x);
+                     pl->d_rp_w1, pl->d_perm, ws.acc, scale, x);
   return hipGetLastError();
 }
 

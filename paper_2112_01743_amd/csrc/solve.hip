@@ -26,7 +26,7 @@
 namespace cpaa {
 
 void free_workspace(Workspace& ws) {
-  void* ptrs[] = {ws.z[0], ws.z[1], ws.z[2], ws.acc, ws.b, ws.r, ws.slots, ws.stat_slots,
+  void* ptrs[] = {ws.z[0], ws.z[1], ws.z[2], ws.acc, ws.part, ws.b, ws.r, ws.slots, ws.stat_slots,
                   ws.stat, ws.done, ws.terms, ws.series_cert, ws.split_f, ws.split_d,
                   ws.split_count, ws.active, ws.plain, ws.col_scale};
   for (void* p : ptrs)
@@ -50,7 +50,8 @@ cpaa_status ensure_workspace(cpaa_plan_s* pl, Workspace& ws, int W, int tiles) {
   ws.cols = static_cast<int64_t>(tiles) * W;
   ws.vec_elems = static_cast<size_t>(pl->n) * ws.cols;
   // split-row partial sums: one set per tile (tiles run concurrently)
-  const size_t nsplit = (size_t)std::max(W == 1 ? pl->max_split_rows : pl->n_tsplit_rows, 1);
+  const size_t nsplit = (size_t)std::max(
+      W == 1 ? std::max(pl->max_split_rows, pl->slc.n_split_rows) : pl->n_tsplit_rows, 1);
   const size_t split_sets = (size_t)tiles;
   auto alloc = [&](void** p, size_t bytes) -> bool {
     if (bytes == 0) bytes = 8;
@@ -64,6 +65,8 @@ cpaa_status ensure_workspace(cpaa_plan_s* pl, Workspace& ws, int W, int tiles) {
   bool ok = true;
   for (int i = 0; i < 3; ++i) ok = ok && alloc((void**)&ws.z[i], ws.vec_elems * sizeof(float));
   ok = ok && alloc((void**)&ws.acc, ws.vec_elems * sizeof(double));
+  if (W == 1 && pl->sliced)
+    ok = ok && alloc((void**)&ws.part, (size_t)kSlices * pl->n * sizeof(float));
   ok = ok && alloc((void**)&ws.b, ws.vec_elems * sizeof(double));
   ok = ok && alloc((void**)&ws.r, ws.vec_elems * sizeof(double));
   ok = ok && alloc((void**)&ws.slots, (size_t)(kMaxTerms + 2) * kSlots * ws.cols * sizeof(double));
@@ -371,7 +374,7 @@ extern "C" cpaa_status cpaa_solve(cpaa_plan_t pl, const double* p, double tol, c
     if ((s = read_back(ws, st)) != CPAA_OK) return s;
     if (!p_checked && (s = check_p_stats(ws, 0)) != CPAA_OK) return s;
     q0 = stat_at(ws, 0, 0, 2);
-    if (pl->opts.autotune && !pl->tuned_w1 && pl->maps.size() > 1) {
+    if (pl->opts.autotune && !pl->tuned_w1 && pl->maps.size() > 1 && !pl->sliced) {
       // autotune the work-item size on this input: time a few terms per candidate
       size_t best = 0;
       float best_ms = 1e30f;

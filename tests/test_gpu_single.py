@@ -145,6 +145,44 @@ def test_work_item_sizes_agree(torch_cuda, npt):
     _assert_parity(g, p, x, rep, 1e-8)
 
 
+@pytest.mark.parametrize("case", ["chung_lu", "grid", "star", "path", "complete", "big_star"])
+def test_column_sliced_term_agrees(torch_cuda, case):
+    """Column-sliced term (relabelled vertices, one column slice per XCD,
+    partial row sums combined per term), forced on graphs of every shape;
+    big_star's centre has more entries per slice than a work item holds."""
+    g = {"chung_lu": lambda: gg.chung_lu(60000, 12, 2.1, seed=5, dmax=20000),
+         "grid": lambda: gg.perturbed_grid(150, 0.05, 0.01, seed=4),
+         "star": lambda: gg.star(40), "path": lambda: gg.path(7),
+         "complete": lambda: gg.complete(30), "big_star": lambda: gg.star(100000)}[case]()
+    for p in (gg.uniform_personalization(g.n), gg.source_personalization(g.n, [g.n // 2])[0],
+              gg.source_personalization(g.n, [0])[0]):
+        x, rep, plan = _solve(torch_cuda, g, p, 1e-9, column_slices=8)
+        info = plan.info()
+        assert info["column_slices"] == 8 and info["reordered"] == 1
+        _assert_parity(g, p, x, rep, 1e-9)
+
+
+def test_column_sliced_warm_start_and_host_io(torch_cuda):
+    from paper_2112_01743_amd import Plan
+    g = gg.chung_lu(30000, 10, 2.2, seed=31)
+    p = gg.source_personalization(g.n, [5])[0]
+    pi = _truth(g, p)
+    guess = np.abs(pi * (1 + 1e-3 * gg.philox(2).standard_normal(g.n)))
+    guess /= guess.sum()
+    _, plain, _ = _solve(torch_cuda, g, p, 1e-9, column_slices=8)
+    x, rep, _ = _solve(torch_cuda, g, p, 1e-9, x0=guess, column_slices=8)
+    assert rep["fallback_used"] == 0 and rep["terms"] < plain["terms"]
+    _assert_parity(g, p, x, rep, 1e-9)
+    from paper_2112_01743_amd import binding as B
+    plan = Plan.from_graph(g, C, column_slices=8, io_device=0)
+    ph = np.ascontiguousarray(p)
+    xh = np.zeros(g.n)
+    st, reph = B.cpaa_solve(plan.handle, ph.ctypes.data, 1e-9, None, xh.ctypes.data)
+    assert st == B.CPAA_OK, B.cpaa_last_error()
+    reph = dict(reph.as_dict(), status="CPAA_OK")
+    _assert_parity(g, p, xh, reph, 1e-9)
+
+
 def test_autotuned_work_items(torch_cuda):
     """The autotuner times candidate work-item sizes on the first plain solve,
     keeps the fastest, and every later solve uses it."""

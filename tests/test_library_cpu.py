@@ -29,10 +29,34 @@ def test_library_exports_nothing_else():
     assert exported == B.header_functions()
 
 
-def test_struct_sizes_match_header_layout():
-    assert ctypes.sizeof(B.cpaa_opts) == 10 * 4
-    assert ctypes.sizeof(B.cpaa_report) == 6 * 4 + 7 * 8 + 2 * 8
-    assert ctypes.sizeof(B.cpaa_csr) == 56
+def test_struct_layout_matches_header(tmp_path):
+    """Every ctypes structure has the size and field offsets the C compiler
+    gives the header's declaration."""
+    import os
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    structs = [B.cpaa_opts, B.cpaa_report, B.cpaa_csr, B.cpaa_plan_info]
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "cpaa.h"', "int main(void) {"]
+    for S in structs:
+        name = S.__name__
+        lines.append(f'  printf("{name} %zu\\n", sizeof({name}));')
+        for f, _ in S._fields_:
+            lines.append(f'  printf("{name}.{f} %zu\\n", offsetof({name}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", inc, str(src), "-o", str(exe)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                   check=True).stdout.splitlines())
+    for S in structs:
+        name = S.__name__
+        assert int(got[name]) == ctypes.sizeof(S), name
+        for f, _ in S._fields_:
+            assert int(got[f"{name}.{f}"]) == getattr(S, f).offset, (name, f)
 
 
 def test_default_opts():
@@ -76,6 +100,8 @@ def test_plan_rejects_bad_damping_and_options():
     assert _plan_status(g.row_ptr, g.col_idx, nnz_per_thread=3) == B.CPAA_EINVAL
     assert _plan_status(g.row_ptr, g.col_idx, tile_w=7) == B.CPAA_EINVAL
     assert "tile_w" in B.cpaa_last_error()
+    assert _plan_status(g.row_ptr, g.col_idx, column_slices=4) == B.CPAA_EINVAL
+    assert "column_slices" in B.cpaa_last_error()
 
 
 def test_plan_rejects_edge_across_graph_boundary():
