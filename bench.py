@@ -8,9 +8,12 @@ solve (all terms of the series, the FP64 residual, any correction series and
 the output), with p and x resident in HBM.
 
 Prints one JSON line.  `value` is GTEPS = (stored entries x Chebyshev terms)
-per second over the timed steps.  `roofline` covers the dominant kernel (the
-fused term kernel): algorithmic bytes per launch over its average duration,
-measured with HIP events on the solve's stream inside the library.
+per second over the timed steps.  `roofline` covers one term of the series,
+the dominant work: with column slices (the default on this graph) a term is
+two launches, the sliced gather pass (k_term_sliced) and the combine pass
+(k_combine_w1); otherwise the fused k_term_w1.  Algorithmic bytes per term
+over the term's average duration, measured with HIP events around the term's
+launches on the solve's stream inside the library.
 `cpu_baseline` times the FP64 oracle's CPAA on the host on a bounded sample of
 the same workload (rank 0, N = 1 only).
 """
@@ -30,7 +33,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "GTEPS (nnz·terms/s) + PPR solves/s at ≤1e-6 L1, warm-start vs plain CPAA"
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "term_w1_chung_lu_n4m_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "term_chung_lu_n4m_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2112_01743_amd", "csrc", "kernels_w1.hip")
 
 
@@ -39,7 +42,7 @@ def log(msg):
 
 
 def term_bytes(n: int, nnz: int) -> int:
-    """Algorithmic HBM bytes of one fused term launch (single right-hand side).
+    """Algorithmic HBM bytes of one term (single right-hand side).
 
     col_idx 4*nnz + row_ptr 4*(n+1) + z_k gathered once 4n + z_{k-1} read 4n
     + z_{k+1} written 4n + FP64 accumulator read and written 16n.
@@ -52,8 +55,9 @@ def kernel_hash() -> str:
 
 
 def load_traffic(n, nnz):
-    """Measured HBM bytes per term launch from the committed counter runs, if they
-    were taken on the current kernel source and the same workload."""
+    """Measured HBM bytes per term (all of its launches) from the committed
+    counter runs, if they were taken on the current kernel source and the same
+    workload."""
     try:
         t = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
@@ -71,7 +75,7 @@ def cpu_baseline(g, c, seconds_target=15.0):
     t0 = time.perf_counter()
     oracle.cpaa(g, b, c, 1)
     one = time.perf_counter() - t0
-    terms = int(max(2, min(40, seconds_target / max(one / 2, 1e-3))))
+    terms = int(max(2, min(400, seconds_target / max(one / 2, 1e-3))))
     t0 = time.perf_counter()
     oracle.cpaa(g, b, c, terms)
     dt = time.perf_counter() - t0
@@ -196,6 +200,8 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--nnz-per-thread", type=int, default=0)
     ap.add_argument("--xcd-remap", type=int, default=-1)
+    ap.add_argument("--column-slices", type=int, default=0,
+                    help="0 auto (column-sliced on this graph), 1 off, 8 on")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="chung_lu",
                     choices=["chung_lu", "grid_batched", "graph_batch"],
@@ -238,9 +244,10 @@ def main():
         f"({time.perf_counter() - t0:.1f} s)")
     t0 = time.perf_counter()
     plan = Plan.from_graph(g, c, time_kernels=1, nnz_per_thread=args.nnz_per_thread,
-                           xcd_remap=args.xcd_remap)
+                           xcd_remap=args.xcd_remap, column_slices=args.column_slices)
     info = plan.info()
-    log(f"plan {info} ({time.perf_counter() - t0:.1f} s)")
+    plan_s = time.perf_counter() - t0
+    log(f"plan {info} ({plan_s:.1f} s)")
     p = torch.full((g.n,), 1.0 / g.n, dtype=torch.float64, device="cuda")
     x = torch.empty_like(p)
     stream = torch.cuda.current_stream()
@@ -280,7 +287,8 @@ def main():
         "config": {"workload": "chung_lu_global_pagerank", "n": g.n, "nnz": g.nnz,
                    "avg_degree_target": args.avg_deg, "gamma": 2.1, "max_degree_cap": 50000,
                    "seed": 2112001, "c": c, "tol_l1": args.tol, "personalization": "uniform",
-                   "solves": args.steps},
+                   "solves": args.steps, "column_slices": info["column_slices"],
+                   "plan_seconds": round(plan_s, 2)},
         "solves_per_s": args.steps / wall,
         "terms": reps[-1]["terms"],
         "refine_terms": reps[-1]["refine_terms"],
@@ -288,8 +296,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
-                     "kernel": "k_term_w1", "bytes_per_launch": alg_bytes,
-                     "avg_launch_us": avg_launch_s * 1e6},
+                     "kernel": ("term = k_term_sliced<32> + k_combine_w1"
+                                if info["column_slices"] == 8 else "term = k_term_w1"),
+                     "bytes_per_launch": alg_bytes, "avg_launch_us": avg_launch_s * 1e6},
     }
     if not args.no_cpu_baseline:
         log("cpu baseline ...")

@@ -65,6 +65,7 @@ constexpr int kSliceNpt = 32;        // entries per thread of a sliced work item
 // local columns stay below 2^21 - 1, so no packed entry equals kSliceNone
 constexpr int64_t kSliceMaxN = int64_t(kSlices) * ((int64_t(1) << (32 - kSliceRowBits)) - 1);
 constexpr uint32_t kSliceNone = 0xFFFFFFFFu;   // padding entry
+constexpr int kSliceHub = 2048;      // leading vertices of a slice cached in LDS per work item
 
 struct SlicedMap {
   uint32_t* d_entries = nullptr;     // [nnz] slice-major

@@ -248,9 +248,14 @@ __global__ __launch_bounds__(kWG) void k_term_sliced(SlicedArgs a) {
     return;
   }
   __shared__ float rsum[kSliceRows];
+  __shared__ float hub[kSliceHub];
   const int lane = t & 63;
   const int nrows = it.row1 - it.row0;
   for (int r = t; r < nrows; r += kWG) rsum[r] = 0.f;
+  // The slice's first kSliceHub vertices (its highest degrees, the targets of
+  // a large share of all gathers) are copied to LDS with coalesced loads.
+  const int nhub = min(kSliceHub, a.slice_off[sl + 1] - a.slice_off[sl]);
+  for (int c = t; c < nhub; c += kWG) hub[c] = xs[c];
   // Wavefront w owns the logical entries [q0, q0 + Lw); lane l owns the
   // contiguous run [l*RL, (l+1)*RL) of them, stored transposed (element i of
   // the run at physical i*64 + l), so every load below is coalesced while each
@@ -262,10 +267,16 @@ __global__ __launch_bounds__(kWG) void k_term_sliced(SlicedArgs a) {
   uint32_t e[NPT];
 #pragma unroll
   for (int i = 0; i < NPT; ++i) e[i] = (i < RL) ? __builtin_nontemporal_load(pe + i * 64) : kNone;
+  __syncthreads();
   float v[NPT];
 #pragma unroll
-  for (int i = 0; i < NPT; ++i) v[i] = (e[i] != kNone) ? xs[e[i] >> kSliceRowBits] : 0.f;
-  __syncthreads();
+  for (int i = 0; i < NPT; ++i) {
+    float h = 0.f, g = 0.f;
+    const uint32_t c = e[i] >> kSliceRowBits;
+    if (e[i] != kNone && c < static_cast<uint32_t>(kSliceHub)) h = hub[c];
+    if (e[i] != kNone && c >= static_cast<uint32_t>(kSliceHub)) g = xs[c];
+    v[i] = h + g;
+  }
   // Row sums of the run in a register.  A row that starts and ends strictly
   // inside the run has no other contributor: plain store.  The first and the
   // last row of a run may be shared with neighbouring runs: LDS atomic.
