@@ -101,7 +101,7 @@ def bench_grid_batched(args):
     c, B = 0.85, 256
     g = gg.perturbed_grid(1000, 0.05, 0.01, seed=2112002)
     src = gg.random_sources(g.n, B, seed=2112002)
-    plan = Plan.from_graph(g, c, time_kernels=1)
+    plan = Plan.from_graph(g, c, time_kernels=1, tile_w=args.tile_w)
     P = torch.zeros((B, g.n), dtype=torch.float64, device="cuda")
     P[torch.arange(B), torch.as_tensor(src, device="cuda")] = 1.0
     X = torch.empty_like(P)
@@ -200,6 +200,8 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--nnz-per-thread", type=int, default=0)
     ap.add_argument("--xcd-remap", type=int, default=-1)
+    ap.add_argument("--tile-w", type=int, default=0,
+                    help="grid_batched: right-hand sides per tile (0 = library default)")
     ap.add_argument("--column-slices", type=int, default=0,
                     help="0 auto (column-sliced on this graph), 1 off, 8 on")
     ap.add_argument("--no-cpu-baseline", action="store_true")

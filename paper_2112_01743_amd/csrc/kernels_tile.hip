@@ -15,6 +15,7 @@ namespace cpaa {
 namespace {
 
 constexpr int kWaves = kWG / 64;
+constexpr int kBurst = 8;   // neighbour gathers issued together for a short row
 
 // Sum over N(u) of X[v*W + j] for one wavefront work item; epi.row(u, d, j, s, sa)
 // is called once per (row, column) by the lane that owns it.
@@ -26,24 +27,95 @@ __device__ __forceinline__ void spmm_item(const WorkItem it, const int* __restri
   constexpr int G = 64 / W;
   const int lane = threadIdx.x & 63;
   const int q = lane / W, j = lane % W;
-  if (it.row1 >= 0) {
-    for (int r = it.row0 + q; r < it.row1; r += G) {
-      const int beg = rp[r], end = rp[r + 1];
-      V s0 = V(0), s1 = V(0), sa = V(0);
-      int k = beg;
-      for (; k + 2 <= end; k += 2) {
-        const V a = X[(size_t)ci[k] * W + j];
-        const V b = X[(size_t)ci[k + 1] * W + j];
-        s0 += a;
-        s1 += b;
-        if (ABS) sa += fabs(a) + fabs(b);
+  if (it.row1 >= 0 && G == 1) {
+    // Rows over the whole wavefront (W = 64), two in flight.  The item's row
+    // pointers (at most 64 rows) and its first 128 column indices are loaded
+    // once, coalesced, and read back with readlane, so the only dependent
+    // memory access per row is the burst of neighbour gathers.
+    const int nr = it.row1 - it.row0;
+    const int cnt = it.nnz1 - it.nnz0;
+    const int rpv = lane < nr ? rp[it.row0 + lane] : 0;
+    const int civ0 = lane < cnt ? ci[it.nnz0 + lane] : 0;
+    const int civ1 = 64 + lane < cnt ? ci[it.nnz0 + 64 + lane] : 0;
+    // gathers of row i: up to kBurst neighbours at once (column indices from the
+    // item's registers), the rest of a longer row one by one
+    auto burst = [&](int beg, int end, V* x) {
+#pragma unroll
+      for (int u = 0; u < kBurst; ++u) {
+        const int k = beg + u - it.nnz0;
+        x[u] = V(0);
+        if (beg + u < end) {
+          int c;
+          if (k < 64) c = __builtin_amdgcn_readlane(civ0, k);
+          else if (k < 128) c = __builtin_amdgcn_readlane(civ1, k - 64);
+          else c = ci[beg + u];
+          x[u] = X[(size_t)c * W + j];
+        }
       }
-      if (k < end) {
+    };
+    auto finish = [&](int r, int beg, int end, const V* x, const typename Epi::Pre& pre) {
+      V s0 = V(0), s1 = V(0), sa = V(0);
+#pragma unroll
+      for (int u = 0; u < kBurst; u += 2) {
+        s0 += x[u];
+        s1 += x[u + 1];
+        if (ABS) sa += fabs(x[u]) + fabs(x[u + 1]);
+      }
+      for (int k = beg + kBurst; k < end; ++k) {
         const V a = X[(size_t)ci[k] * W + j];
         s0 += a;
         if (ABS) sa += fabs(a);
       }
-      epi.row(r, end - beg, j, s0 + s1, sa);
+      epi.row(r, end - beg, j, s0 + s1, sa, pre);
+    };
+    auto row_end = [&](int i) {
+      return i + 1 < nr ? __builtin_amdgcn_readlane(rpv, i + 1) : it.nnz1;
+    };
+    // two rows in flight
+    int i = 0;
+    for (; i + 1 < nr; i += 2) {
+      const int ba = __builtin_amdgcn_readlane(rpv, i), ea = row_end(i);
+      const int bb = ea, eb = row_end(i + 1);
+      const typename Epi::Pre pa = epi.prefetch(it.row0 + i, j);
+      const typename Epi::Pre pb = epi.prefetch(it.row0 + i + 1, j);
+      V xa[kBurst], xb[kBurst];
+      burst(ba, ea, xa);
+      burst(bb, eb, xb);
+      finish(it.row0 + i, ba, ea, xa, pa);
+      finish(it.row0 + i + 1, bb, eb, xb, pb);
+    }
+    if (i < nr) {
+      const int ba = __builtin_amdgcn_readlane(rpv, i), ea = row_end(i);
+      const typename Epi::Pre pa = epi.prefetch(it.row0 + i, j);
+      V xa[kBurst];
+      burst(ba, ea, xa);
+      finish(it.row0 + i, ba, ea, xa, pa);
+    }
+    return;
+  }
+  if (it.row1 >= 0) {
+    for (int r = it.row0 + q; r < it.row1; r += G) {
+      const int beg = rp[r], end = rp[r + 1];
+      // the epilogue's own loads go out first; then up to kBurst neighbour
+      // gathers at once, so a short row costs about one memory latency
+      const typename Epi::Pre pre = epi.prefetch(r, j);
+      V x[kBurst];
+#pragma unroll
+      for (int u = 0; u < kBurst; ++u)
+        x[u] = (beg + u < end) ? X[(size_t)ci[beg + u] * W + j] : V(0);
+      V s0 = V(0), s1 = V(0), sa = V(0);
+#pragma unroll
+      for (int u = 0; u < kBurst; u += 2) {
+        s0 += x[u];
+        s1 += x[u + 1];
+        if (ABS) sa += fabs(x[u]) + fabs(x[u + 1]);
+      }
+      for (int k = beg + kBurst; k < end; ++k) {
+        const V a = X[(size_t)ci[k] * W + j];
+        s0 += a;
+        if (ABS) sa += fabs(a);
+      }
+      epi.row(r, end - beg, j, s0 + s1, sa, pre);
     }
     return;
   }
@@ -78,7 +150,8 @@ __device__ __forceinline__ void spmm_item(const WorkItem it, const int* __restri
       if (ABS)
         full_abs = __hip_atomic_exchange(&part[W + j], V(0), __ATOMIC_RELAXED,
                                          __HIP_MEMORY_SCOPE_AGENT);
-      epi.row(it.row0, rp[it.row0 + 1] - rp[it.row0], j, full, full_abs);
+      epi.row(it.row0, rp[it.row0 + 1] - rp[it.row0], j, full, full_abs,
+              epi.prefetch(it.row0, j));
     }
     if (lane == 0)
       __hip_atomic_exchange(&split_count[slot], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -121,15 +194,23 @@ struct TileTermEpi {
   double a_next, beta;
   int want_cert;
   double cert;
-  __device__ __forceinline__ void row(int r, int d, int j, float s, float) {
+  struct Pre {
+    float zp, zc;
+    double acc;
+  };
+  __device__ __forceinline__ Pre prefetch(int r, int j) const {
+    const size_t idx = (size_t)r * W + j;
+    return {gamma != 0.f ? zp[idx] : 0.f, want_cert ? zc[idx] : 0.f, acc[idx]};
+  }
+  __device__ __forceinline__ void row(int r, int d, int j, float s, float, const Pre& p) {
     const size_t idx = (size_t)r * W + j;
     float y = alpha * (s / static_cast<float>(d));
-    if (gamma != 0.f) y -= gamma * zp[idx];
+    if (gamma != 0.f) y -= gamma * p.zp;
     zn[idx] = y;
-    acc[idx] += a_next * static_cast<double>(y);
+    acc[idx] = p.acc + a_next * static_cast<double>(y);
     if (want_cert)
       cert += static_cast<double>(d) *
-              fabs(static_cast<double>(y) - beta * static_cast<double>(zc[idx]));
+              fabs(static_cast<double>(y) - beta * static_cast<double>(p.zc));
   }
 };
 
@@ -160,7 +241,7 @@ __global__ __launch_bounds__(kWG) void k_term_tile(TileTermArgs a) {
   const int t = blockIdx.y;
   if (a.done != nullptr && a.done[t]) return;
   const int lb = xcd_logical(blockIdx.x, gridDim.x, a.xcd);
-  const int item = lb * kWaves + (threadIdx.x >> 6);
+  const int item = __builtin_amdgcn_readfirstlane(lb * kWaves + (threadIdx.x >> 6));
   const size_t off = (size_t)t * a.n * W;
   TileTermEpi epi{a.z_cur + off, a.z_prev ? a.z_prev + off : nullptr, a.z_next + off,
                   a.acc + off, W, a.alpha, a.gamma, a.a_next, a.beta, a.cert != nullptr, 0.0};
@@ -183,11 +264,18 @@ struct TileResidEpi {
   int W;
   double c;
   double f_abs, f_max, f_q, f_mass, f_round, f_bad;
-  __device__ __forceinline__ void row(int r, int d, int j, double s, double sa) {
+  struct Pre {
+    double acc, b;
+  };
+  __device__ __forceinline__ Pre prefetch(int r, int j) const {
     const size_t idx = (size_t)r * W + j;
-    const double av = acc[idx];
+    return {acc[idx], b[idx]};
+  }
+  __device__ __forceinline__ void row(int r, int d, int j, double s, double sa, const Pre& p) {
+    const size_t idx = (size_t)r * W + j;
+    const double av = p.acc;
     const double dd = static_cast<double>(d);
-    const double bb = b[idx];
+    const double bb = p.b;
     const double res = bb - dd * av + c * s;
     r_out[idx] = res;
     const double ar = fabs(res);
@@ -225,7 +313,7 @@ __global__ __launch_bounds__(kWG) void k_resid_tile(TileResidArgs a) {
   const int t = blockIdx.y;
   if (a.active != nullptr && !a.active[t]) return;
   const int lb = xcd_logical(blockIdx.x, gridDim.x, a.xcd);
-  const int item = lb * kWaves + (threadIdx.x >> 6);
+  const int item = __builtin_amdgcn_readfirstlane(lb * kWaves + (threadIdx.x >> 6));
   const size_t off = (size_t)t * a.n * W;
   TileResidEpi epi{a.acc + off, a.b + off, a.r + off, W, a.c, 0, 0, 0, 0, 0, 0};
   if (item < a.n_items)
