@@ -35,6 +35,8 @@ METRIC = "GTEPS (nnz·terms/s) + PPR solves/s at ≤1e-6 L1, warm-start vs plain
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "term_chung_lu_n4m_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2112_01743_amd", "csrc", "kernels_w1.hip")
+TILE_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "term_tile_grid_256_traffic.json")
+TILE_KERNEL_SRC = os.path.join(ROOT, "paper_2112_01743_amd", "csrc", "kernels_tile.hip")
 
 
 def log(msg):
@@ -50,19 +52,19 @@ def term_bytes(n: int, nnz: int) -> int:
     return 4 * nnz + 4 * (n + 1) + 28 * n
 
 
-def kernel_hash() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+def kernel_hash(src: str = KERNEL_SRC) -> str:
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
 
 
-def load_traffic(n, nnz):
+def load_traffic(n, nnz, path: str = TRAFFIC_FILE, src: str = KERNEL_SRC):
     """Measured HBM bytes per term (all of its launches) from the committed
     counter runs, if they were taken on the current kernel source and the same
     workload."""
     try:
-        t = json.load(open(TRAFFIC_FILE))
+        t = json.load(open(path))
     except (OSError, ValueError):
         return None
-    if t.get("kernel_sha") != kernel_hash() or t.get("n") != n or t.get("nnz") != nnz:
+    if t.get("kernel_sha") != kernel_hash(src) or t.get("n") != n or t.get("nnz") != nnz:
         return None
     return t.get("bytes_per_launch")
 
@@ -133,8 +135,9 @@ def bench_grid_batched(args):
            "terms_mean": float(np.mean([r["terms"] + r["refine_terms"] for r in allreps[-1]])),
            "certified": all(r["certified"] for reps in allreps for r in reps),
            "roofline": {"bound": "hbm", "achieved": alg / avg / 1e9, "peak": HBM_PEAK_GBS,
-                        "unit": "GB/s", "frac": alg / avg / 1e9 / HBM_PEAK_GBS, "traffic": None,
-                        "kernel": "k_term_tile", "bytes_per_launch": alg,
+                        "unit": "GB/s", "frac": alg / avg / 1e9 / HBM_PEAK_GBS,
+                        "traffic": load_traffic(g.n, g.nnz, TILE_TRAFFIC_FILE, TILE_KERNEL_SRC),
+                        "kernel": f"k_term_tile<{W}>", "bytes_per_launch": alg,
                         "avg_launch_us": avg * 1e6}}
     print(json.dumps(out), flush=True)
 
