@@ -61,6 +61,20 @@ __device__ __forceinline__ void atomic_max_nonneg(double* addr, double v) {
 __device__ __forceinline__ void atomic_add(double* addr, double v) { unsafeAtomicAdd(addr, v); }
 __device__ __forceinline__ void atomic_add(float* addr, float v) { unsafeAtomicAdd(addr, v); }
 
+// Split-row protocols (a row's chunks on several workgroups) exchange their
+// partial sums only through device-scope atomics and count arrivals with one
+// more atomic.  All that is needed between the two is that this wave's data
+// atomics have been performed before its counter atomic is issued: wait for
+// every outstanding memory operation, and keep the compiler from moving
+// memory operations across the wait.  An agent-scope fence (__threadfence)
+// would also write back and invalidate the XCD's whole L2 on this chip,
+// which made the tiled term on a power-law graph 2.3x slower.
+__device__ __forceinline__ void atomics_done() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
 __device__ __forceinline__ int prev_pow2(int v) {
   return v <= 1 ? 1 : (1 << (31 - __clz(v)));
 }

@@ -15,7 +15,8 @@ namespace cpaa {
 namespace {
 
 constexpr int kWaves = kWG / 64;
-constexpr int kBurst = 8;   // neighbour gathers issued together for a short row
+constexpr int kBurst = 8;         // neighbour gathers issued together for a short row
+constexpr int kRowsInFlight = 2;  // W = 64: rows whose loads are issued together
 
 // Sum over N(u) of X[v*W + j] for one wavefront work item; epi.row(u, d, j, s, sa)
 // is called once per (row, column) by the lane that owns it.
@@ -28,7 +29,7 @@ __device__ __forceinline__ void spmm_item(const WorkItem it, const int* __restri
   const int lane = threadIdx.x & 63;
   const int q = lane / W, j = lane % W;
   if (it.row1 >= 0 && G == 1) {
-    // Rows over the whole wavefront (W = 64), two in flight.  The item's row
+    // Rows over the whole wavefront (W = 64), several in flight.  The item's row
     // pointers (at most 64 rows) and its first 128 column indices are loaded
     // once, coalesced, and read back with readlane, so the only dependent
     // memory access per row is the burst of neighbour gathers.
@@ -71,25 +72,30 @@ __device__ __forceinline__ void spmm_item(const WorkItem it, const int* __restri
     auto row_end = [&](int i) {
       return i + 1 < nr ? __builtin_amdgcn_readlane(rpv, i + 1) : it.nnz1;
     };
-    // two rows in flight
+    // kRowsInFlight rows at a time: their operand loads and gathers all go out
+    // before the first row's sums are needed
     int i = 0;
-    for (; i + 1 < nr; i += 2) {
-      const int ba = __builtin_amdgcn_readlane(rpv, i), ea = row_end(i);
-      const int bb = ea, eb = row_end(i + 1);
-      const typename Epi::Pre pa = epi.prefetch(it.row0 + i, j);
-      const typename Epi::Pre pb = epi.prefetch(it.row0 + i + 1, j);
-      V xa[kBurst], xb[kBurst];
-      burst(ba, ea, xa);
-      burst(bb, eb, xb);
-      finish(it.row0 + i, ba, ea, xa, pa);
-      finish(it.row0 + i + 1, bb, eb, xb, pb);
+    for (; i + kRowsInFlight <= nr; i += kRowsInFlight) {
+      int b[kRowsInFlight], e[kRowsInFlight];
+      typename Epi::Pre pr[kRowsInFlight];
+      V x[kRowsInFlight][kBurst];
+#pragma unroll
+      for (int f = 0; f < kRowsInFlight; ++f) {
+        b[f] = __builtin_amdgcn_readlane(rpv, i + f);
+        e[f] = row_end(i + f);
+        pr[f] = epi.prefetch(it.row0 + i + f, j);
+      }
+#pragma unroll
+      for (int f = 0; f < kRowsInFlight; ++f) burst(b[f], e[f], x[f]);
+#pragma unroll
+      for (int f = 0; f < kRowsInFlight; ++f) finish(it.row0 + i + f, b[f], e[f], x[f], pr[f]);
     }
-    if (i < nr) {
-      const int ba = __builtin_amdgcn_readlane(rpv, i), ea = row_end(i);
-      const typename Epi::Pre pa = epi.prefetch(it.row0 + i, j);
-      V xa[kBurst];
-      burst(ba, ea, xa);
-      finish(it.row0 + i, ba, ea, xa, pa);
+    for (; i < nr; ++i) {
+      const int b = __builtin_amdgcn_readlane(rpv, i), e = row_end(i);
+      const typename Epi::Pre pr = epi.prefetch(it.row0 + i, j);
+      V x[kBurst];
+      burst(b, e, x);
+      finish(it.row0 + i, b, e, x, pr);
     }
     return;
   }
@@ -137,12 +143,12 @@ __device__ __forceinline__ void spmm_item(const WorkItem it, const int* __restri
     atomic_add(&part[j], s);
     if (ABS) atomic_add(&part[W + j], sa);
   }
-  __threadfence();
+  atomics_done();
   int prev = 0;
   if (lane == 0) prev = atomicAdd(&split_count[slot], 1);
   prev = __shfl(prev, 0);
   if (prev == split_nchunks[slot] - 1) {
-    __threadfence();
+    atomics_done();
     if (lane < W) {
       const V full = __hip_atomic_exchange(&part[j], V(0), __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_AGENT);

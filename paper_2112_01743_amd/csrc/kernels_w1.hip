@@ -46,10 +46,10 @@ __device__ __forceinline__ void split_chunk_finish(const WorkItem it, const int*
     const int ps = ABS ? 2 * slot : slot;
     atomic_add(&split_part[ps], (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]));
     if (ABS) atomic_add(&split_part[ps + 1], (wabs[0] + wabs[1]) + (wabs[2] + wabs[3]));
-    __threadfence();
+    atomics_done();
     const int prev = atomicAdd(&split_count[slot], 1);
     if (prev == split_nchunks[slot] - 1) {
-      __threadfence();
+      atomics_done();
       const V full = __hip_atomic_exchange(&split_part[ps], V(0), __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_AGENT);
       V full_abs = V(0);

@@ -151,10 +151,10 @@ __global__ __launch_bounds__(kWG) void k_agg2(const WorkItem* __restrict__ items
   if (lane == 0) {
     atomicAdd(&part[2 * slot], a0);
     atomicAdd(&part[2 * slot + 1], a1);
-    __threadfence();
+    atomics_done();
     prev = atomicAdd(&count[slot], 1);
     if (prev == nchunks[slot] - 1) {
-      __threadfence();
+      atomics_done();
       const float f0 = __hip_atomic_exchange(&part[2 * slot], 0.f, __ATOMIC_RELAXED,
                                              __HIP_MEMORY_SCOPE_AGENT);
       const float f1 = __hip_atomic_exchange(&part[2 * slot + 1], 0.f, __ATOMIC_RELAXED,
@@ -216,12 +216,12 @@ __global__ __launch_bounds__(kWG) void k_agg64(const WorkItem* __restrict__ item
   }
   if (j < it.nnz1) a0 += load(ci[j]);
   atomicAdd(&part[(size_t)slot * kHid + lane], a0 + a1);
-  __threadfence();
+  atomics_done();
   int prev = 0;
   if (lane == 0) prev = atomicAdd(&count[slot], 1);
   prev = __shfl(prev, 0);
   if (prev == nchunks[slot] - 1) {
-    __threadfence();
+    atomics_done();
     const float full = __hip_atomic_exchange(&part[(size_t)slot * kHid + lane], 0.f,
                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     finish(it.row0, full);
