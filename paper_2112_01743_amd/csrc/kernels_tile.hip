@@ -23,7 +23,8 @@ constexpr int kRowsInFlight = 2;  // W = 64: rows whose loads are issued togethe
 template <typename V, int W, bool ABS, typename Epi>
 __device__ __forceinline__ void spmm_item(const WorkItem it, const int* __restrict__ rp,
                                           const int* __restrict__ ci, const V* __restrict__ X,
-                                          V* __restrict__ split_part, int* __restrict__ split_count,
+                                          double* __restrict__ split_part,
+                                          int* __restrict__ split_count,
                                           const int* __restrict__ split_nchunks, Epi& epi) {
   constexpr int G = 64 / W;
   const int lane = threadIdx.x & 63;
@@ -62,12 +63,28 @@ __device__ __forceinline__ void spmm_item(const WorkItem it, const int* __restri
         s1 += x[u + 1];
         if (ABS) sa += fabs(x[u]) + fabs(x[u + 1]);
       }
-      for (int k = beg + kBurst; k < end; ++k) {
-        const V a = X[(size_t)ci[k] * W + j];
-        s0 += a;
-        if (ABS) sa += fabs(a);
+      if (end - beg <= kBurst) {
+        epi.row(r, end - beg, j, s0 + s1, sa, pre);
+        return;
       }
-      epi.row(r, end - beg, j, s0 + s1, sa, pre);
+      // rows longer than a burst (up to kTileLongDeg entries, one lane each):
+      // the rest is summed in FP64 to keep the rounding independent of degree
+      double t0 = static_cast<double>(s0) + static_cast<double>(s1), t1 = 0.0;
+      double ta = static_cast<double>(sa);
+      int k = beg + kBurst;
+      for (; k + 1 < end; k += 2) {
+        const V a = X[(size_t)ci[k] * W + j];
+        const V b = X[(size_t)ci[k + 1] * W + j];
+        t0 += static_cast<double>(a);
+        t1 += static_cast<double>(b);
+        if (ABS) ta += fabs(static_cast<double>(a)) + fabs(static_cast<double>(b));
+      }
+      if (k < end) {
+        const V a = X[(size_t)ci[k] * W + j];
+        t0 += static_cast<double>(a);
+        if (ABS) ta += fabs(static_cast<double>(a));
+      }
+      epi.row(r, end - beg, j, static_cast<V>(t0 + t1), static_cast<V>(ta), pre);
     };
     auto row_end = [&](int i) {
       return i + 1 < nr ? __builtin_amdgcn_readlane(rpv, i + 1) : it.nnz1;
@@ -125,20 +142,31 @@ __device__ __forceinline__ void spmm_item(const WorkItem it, const int* __restri
     }
     return;
   }
-  // chunk of a long row
-  V s = V(0), sa = V(0);
-  for (int k = it.nnz0 + q; k < it.nnz1; k += G) {
+  // chunk of a long row: with W = 64 every lane walks the whole chunk, so the
+  // chunk and row sums are formed in FP64 (a hub's FP32 sum over thousands of
+  // entries would otherwise dominate the recurrence's rounding error)
+  double s = 0.0, s2 = 0.0, sa = 0.0;
+  int k = it.nnz0 + q;
+  for (; k + G < it.nnz1; k += 2 * G) {
     const V a = X[(size_t)ci[k] * W + j];
-    s += a;
-    if (ABS) sa += fabs(a);
+    const V b = X[(size_t)ci[k + G] * W + j];
+    s += static_cast<double>(a);
+    s2 += static_cast<double>(b);
+    if (ABS) sa += fabs(static_cast<double>(a)) + fabs(static_cast<double>(b));
   }
+  if (k < it.nnz1) {
+    const V a = X[(size_t)ci[k] * W + j];
+    s += static_cast<double>(a);
+    if (ABS) sa += fabs(static_cast<double>(a));
+  }
+  s += s2;
 #pragma unroll
   for (int off = W; off < 64; off <<= 1) {
     s += __shfl_xor(s, off);
     if (ABS) sa += __shfl_xor(sa, off);
   }
   const int slot = -(it.row1 + 1);
-  V* part = split_part + (size_t)slot * (ABS ? 2 * W : W);
+  double* part = split_part + (size_t)slot * (ABS ? 2 * W : W);
   if (lane < W) {
     atomic_add(&part[j], s);
     if (ABS) atomic_add(&part[W + j], sa);
@@ -150,14 +178,14 @@ __device__ __forceinline__ void spmm_item(const WorkItem it, const int* __restri
   if (prev == split_nchunks[slot] - 1) {
     atomics_done();
     if (lane < W) {
-      const V full = __hip_atomic_exchange(&part[j], V(0), __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-      V full_abs = V(0);
+      const double full = __hip_atomic_exchange(&part[j], 0.0, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+      double full_abs = 0.0;
       if (ABS)
-        full_abs = __hip_atomic_exchange(&part[W + j], V(0), __ATOMIC_RELAXED,
+        full_abs = __hip_atomic_exchange(&part[W + j], 0.0, __ATOMIC_RELAXED,
                                          __HIP_MEMORY_SCOPE_AGENT);
-      epi.row(it.row0, rp[it.row0 + 1] - rp[it.row0], j, full, full_abs,
-              epi.prefetch(it.row0, j));
+      epi.row(it.row0, rp[it.row0 + 1] - rp[it.row0], j, static_cast<V>(full),
+              static_cast<V>(full_abs), epi.prefetch(it.row0, j));
     }
     if (lane == 0)
       __hip_atomic_exchange(&split_count[slot], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -235,7 +263,7 @@ struct TileTermArgs {
   double* cert;        // [kSlots][cols] or null
   int64_t cols;
   const int* done;     // [tiles] or null
-  float* split_part;   // [tiles][split slots][W]
+  double* split_part;  // [tiles][split slots][W]
   int* split_count;    // [tiles][split slots]
   const int* split_nchunks;
   int n_split;
@@ -526,7 +554,7 @@ hipError_t term_tile(const cpaa_plan_s* pl, Workspace& ws, int cur, int prev, in
   a.cert = cert_slot;
   a.cols = ws.cols;
   a.done = done;
-  a.split_part = ws.split_f;
+  a.split_part = ws.split_d;
   a.split_count = ws.split_count;
   a.split_nchunks = pl->d_tsplit_nchunks;
   a.n_split = pl->n_tsplit_rows;
