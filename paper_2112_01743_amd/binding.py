@@ -189,6 +189,18 @@ def cpaa_solve_graphs(plan, p_ptr: int, tol: float, x_ptr: int, num_graphs: int,
     return st, reps
 
 
+_CTYPE_TO_NP = {ctypes.c_int32: np.int32, ctypes.c_int64: np.int64, ctypes.c_double: np.float64}
+
+
+def _report_records(reps) -> np.ndarray:
+    """cpaa_report[k] -> numpy structured array (one copy; no per-record Python objects)."""
+    dt = np.dtype({"names": [f for f, _ in cpaa_report._fields_],
+                   "formats": [_CTYPE_TO_NP[t] for _, t in cpaa_report._fields_],
+                   "offsets": [getattr(cpaa_report, f).offset for f, _ in cpaa_report._fields_],
+                   "itemsize": ctypes.sizeof(cpaa_report)})
+    return np.frombuffer(reps, dtype=dt).copy()
+
+
 # ----------------------------------------------------------------------------
 # convenience object over torch HIP tensors
 # ----------------------------------------------------------------------------
@@ -266,7 +278,8 @@ class Plan:
         return out, d
 
     def solve_batched(self, P, tol: float = 1e-6, X0=None, out=None, stream=None, check=True):
-        """P: (B, n) float64 HIP tensor, row j = personalization j.  Returns (X, [reports])."""
+        """P: (B, n) float64 HIP tensor, row j = personalization j.  Returns (X, reports):
+        reports is a numpy structured array with one cpaa_report record per column."""
         import torch
         B = int(P.shape[0])
         if out is None:
@@ -277,15 +290,11 @@ class Plan:
                                       out.data_ptr(), _ld(out, self.n), _stream_handle(stream))
         if check and st not in (CPAA_OK, CPAA_ENOCONV):
             raise CpaaError(st, "cpaa_solve_batched")
-        out_reps = []
-        for r in reps:
-            d = r.as_dict()
-            d["status"] = STATUS.get(st, st)
-            out_reps.append(d)
-        return out, out_reps
+        return out, _report_records(reps)
 
     def solve_graphs(self, p, tol: float = 1e-6, out=None, stream=None, check=True):
-        """p: (n,) float64 HIP tensor of concatenated per-graph personalizations."""
+        """p: (n,) float64 HIP tensor of concatenated per-graph personalizations.  Returns
+        (x, reports): one cpaa_report record per graph (numpy structured array)."""
         import torch
         if out is None:
             out = torch.empty_like(p)
@@ -293,7 +302,7 @@ class Plan:
                                      self.num_graphs, _stream_handle(stream))
         if check and st not in (CPAA_OK, CPAA_ENOCONV):
             raise CpaaError(st, "cpaa_solve_graphs")
-        return out, [dict(r.as_dict(), status=STATUS.get(st, st)) for r in reps]
+        return out, _report_records(reps)
 
     def close(self):
         if getattr(self, "handle", None):

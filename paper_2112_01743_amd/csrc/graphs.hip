@@ -30,13 +30,17 @@ namespace cpaa {
 namespace {
 
 constexpr int kRec = 12;
+constexpr int kGraphRunMax = 16;               // longest per-lane run of packed entries
+constexpr uint32_t kGraphPad = 0xFFFFFFFFu;    // padding entry (row 0xffff never exists)
 // record fields
 enum { R_TERMS, R_REF_TERMS, R_REFS, R_BOUND, R_RL1, R_RMAX, R_MASS, R_SCERT, R_PSUM, R_PNEG,
        R_PBAD, R_CERTIFIED };
 
 struct GraphArgs {
   const int* rp;
-  const uint32_t* coo;      // (local_row << 16) | local_col, row-major per graph
+  const uint32_t* coo;      // (local_row << 16) | local_col, per graph in transposed runs
+  const int* coo_off;       // [num_graphs] first packed entry of each graph
+  const int* coo_meta;      // [num_graphs] chunks << 5 | run length
   const int* graph_ptr;
   const int* order;
   int num_graphs;
@@ -76,31 +80,52 @@ __device__ __forceinline__ double block_allmax(double v, double* red) {
 }
 
 // y[row] += src[col] over the graph's entries (LDS gathers, LDS atomics).
+// One pass y[row] += src[col] (or |src[col]|) over a graph's packed entries.
+// The entries of each chunk of 64*rl (row-ordered) entries are stored
+// transposed: lane l owns the contiguous run [l*rl, (l+1)*rl), element i at
+// i*64 + l, so the loads stay coalesced while a lane sums its rows in a
+// register.  A row that starts and ends inside a run has no other contributor
+// (plain LDS store into the zeroed y); the first and last row of a run may be
+// shared with neighbouring runs (LDS atomic).  Per-entry LDS atomics, with
+// the lanes of a wavefront mostly hitting the same row, cost 4x more.
 template <int BLOCK, typename T, bool ABS>
-__device__ __forceinline__ void coo_pass(const uint32_t* __restrict__ coo, int mg,
+__device__ __forceinline__ void coo_pass(const uint32_t* __restrict__ coo, int nch, int rl,
                                          const T* src, T* y) {
-  int e = threadIdx.x;
-  for (; e + 3 * BLOCK < mg; e += 4 * BLOCK) {
-    const uint32_t w0 = coo[e], w1 = coo[e + BLOCK], w2 = coo[e + 2 * BLOCK],
-                   w3 = coo[e + 3 * BLOCK];
-    T v0 = src[w0 & 0xffffu], v1 = src[w1 & 0xffffu], v2 = src[w2 & 0xffffu],
-      v3 = src[w3 & 0xffffu];
-    if (ABS) {
-      v0 = fabs(v0);
-      v1 = fabs(v1);
-      v2 = fabs(v2);
-      v3 = fabs(v3);
+  const int lane = threadIdx.x & 63;
+  for (int c = threadIdx.x >> 6; c < nch; c += BLOCK / 64) {
+    const uint32_t* pc = coo + (size_t)c * 64 * rl + lane;
+    uint32_t e[kGraphRunMax];
+#pragma unroll
+    for (int i = 0; i < kGraphRunMax; ++i) e[i] = i < rl ? pc[i * 64] : kGraphPad;
+    T v[kGraphRunMax];
+#pragma unroll
+    for (int i = 0; i < kGraphRunMax; ++i) {
+      v[i] = e[i] != kGraphPad ? src[e[i] & 0xffffu] : T(0);
+      if (ABS) v[i] = fabs(v[i]);
     }
-    atomicAdd(&y[w0 >> 16], v0);
-    atomicAdd(&y[w1 >> 16], v1);
-    atomicAdd(&y[w2 >> 16], v2);
-    atomicAdd(&y[w3 >> 16], v3);
-  }
-  for (; e < mg; e += BLOCK) {
-    const uint32_t w = coo[e];
-    T v = src[w & 0xffffu];
-    if (ABS) v = fabs(v);
-    atomicAdd(&y[w >> 16], v);
+    int row = -1;
+    T sum = T(0);
+    bool first = true;
+#pragma unroll
+    for (int i = 0; i < kGraphRunMax; ++i) {
+      if (e[i] != kGraphPad) {
+        const int r = static_cast<int>(e[i] >> 16);
+        if (r != row) {
+          if (row >= 0) {
+            if (first)
+              atomicAdd(&y[row], sum);
+            else
+              y[row] = sum;
+            first = false;
+          }
+          row = r;
+          sum = v[i];
+        } else {
+          sum += v[i];
+        }
+      }
+    }
+    if (row >= 0) atomicAdd(&y[row], sum);
   }
 }
 
@@ -110,9 +135,8 @@ __device__ void solve_graph(const GraphArgs& a, int g, unsigned char* lds, doubl
   const int t = threadIdx.x;
   const int v0 = a.graph_ptr[g];
   const int ng = a.graph_ptr[g + 1] - v0;
-  const int e0 = a.rp[v0];
-  const int mg = a.rp[v0 + ng] - e0;
-  const uint32_t* coo = a.coo + e0;
+  const uint32_t* coo = a.coo + a.coo_off[g];
+  const int nch = a.coo_meta[g] >> 5, rl = a.coo_meta[g] & 31;
   // LDS regions: A = 8*max_ng bytes, B = 8*max_ng bytes
   float* za = reinterpret_cast<float*>(lds);
   float* zb = za + a.max_ng;
@@ -175,7 +199,7 @@ __device__ void solve_graph(const GraphArgs& a, int g, unsigned char* lds, doubl
     int terms = 0;
     double ck = 2.0 * a.c0h;   // c_0
     if (k_cap >= 1) {
-      coo_pass<BLOCK, float, false>(coo, mg, za, yf);
+      coo_pass<BLOCK, float, false>(coo, nch, rl, za, yf);
       __syncthreads();
       ck *= a.beta;            // c_1
 #pragma unroll
@@ -195,7 +219,7 @@ __device__ void solve_graph(const GraphArgs& a, int g, unsigned char* lds, doubl
     float* prv = za;
     double bpow = a.beta * a.beta;   // beta^{k+1} for k = 1
     for (int k = 1; k < k_cap; ++k) {
-      coo_pass<BLOCK, float, false>(coo, mg, cur, yf);
+      coo_pass<BLOCK, float, false>(coo, nch, rl, cur, yf);
       __syncthreads();
       ck *= a.beta;            // c_{k+1}
       const bool want = k >= k_min;
@@ -242,7 +266,7 @@ __device__ void solve_graph(const GraphArgs& a, int g, unsigned char* lds, doubl
       }
     }
     __syncthreads();
-    coo_pass<BLOCK, double, false>(coo, mg, ad, yd);
+    coo_pass<BLOCK, double, false>(coo, nch, rl, ad, yd);
     __syncthreads();
     double f_abs = 0.0, f_max = 0.0, f_q = 0.0, f_mass = 0.0, f_round = 0.0;
 #pragma unroll
@@ -260,7 +284,7 @@ __device__ void solve_graph(const GraphArgs& a, int g, unsigned char* lds, doubl
       }
     }
     __syncthreads();
-    coo_pass<BLOCK, double, true>(coo, mg, ad, yd);
+    coo_pass<BLOCK, double, true>(coo, nch, rl, ad, yd);
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
@@ -407,6 +431,8 @@ static hipError_t set_lds_limit(int block, int rpt, size_t lds) {
 // Graph-batch resources hung off the plan's multi-graph workspace.
 struct GraphState {
   uint32_t* d_coo = nullptr;
+  int* d_coo_off = nullptr;
+  int* d_coo_meta = nullptr;
   double* d_rec = nullptr;
   int* d_abort = nullptr;
   double* h_rec = nullptr;
@@ -423,6 +449,8 @@ void free_graph_state(cpaa_plan_s* pl) {
   if (gs->run.exec) (void)hipGraphExecDestroy(gs->run.exec);
   if (gs->run.graph) (void)hipGraphDestroy(gs->run.graph);
   if (gs->d_coo) (void)hipFree(gs->d_coo);
+  if (gs->d_coo_off) (void)hipFree(gs->d_coo_off);
+  if (gs->d_coo_meta) (void)hipFree(gs->d_coo_meta);
   if (gs->d_rec) (void)hipFree(gs->d_rec);
   if (gs->d_abort) (void)hipFree(gs->d_abort);
   if (gs->h_rec) (void)hipHostFree(gs->h_rec);
@@ -439,14 +467,37 @@ cpaa_status build_graph_state(cpaa_plan_s* pl, const int32_t* rp, const int32_t*
   }
   pl->graph_state = gs;
   const int G = pl->num_graphs;
-  std::vector<uint32_t> coo(static_cast<size_t>(pl->nnz));
+  // per graph: runs of rl entries per lane, rl = clamp(nnz_g / 1024, 4, 16),
+  // chunks of 64*rl entries, the last one padded
+  std::vector<int> off(G), meta(G);
+  size_t total = 0;
   for (int gi = 0; gi < G; ++gi) {
-    const int v0 = gp[gi];
+    const int mg = rp[gp[gi + 1]] - rp[gp[gi]];
+    const int rl = std::min(kGraphRunMax, std::max(4, (mg + 1023) / 1024));
+    const int nch = (mg + 64 * rl - 1) / (64 * rl);
+    off[gi] = static_cast<int>(total);
+    meta[gi] = (nch << 5) | rl;
+    total += static_cast<size_t>(nch) * 64 * rl;
+  }
+  if (total >= (size_t(1) << 31)) {
+    set_error("graph batch too large for the packed layout");
+    return CPAA_EINVAL;
+  }
+  std::vector<uint32_t> coo(total, kGraphPad);
+  for (int gi = 0; gi < G; ++gi) {
+    const int v0 = gp[gi], e0 = rp[v0];
+    const int rl = meta[gi] & 31, ch = 64 * rl;
+    int q = 0;
     for (int u = gp[gi]; u < gp[gi + 1]; ++u)
-      for (int j = rp[u]; j < rp[u + 1]; ++j)
-        coo[j] = (static_cast<uint32_t>(u - v0) << 16) | static_cast<uint32_t>(ci[j] - v0);
+      for (int j = rp[u]; j < rp[u + 1]; ++j, ++q) {
+        const int c = q / ch, w = q % ch;
+        coo[off[gi] + static_cast<size_t>(c) * ch + (w % rl) * 64 + w / rl] =
+            (static_cast<uint32_t>(u - v0) << 16) | static_cast<uint32_t>(ci[j] - v0);
+      }
   }
   if (hipMalloc(&gs->d_coo, std::max<size_t>(coo.size(), 1) * 4) != hipSuccess ||
+      hipMalloc(&gs->d_coo_off, (size_t)G * sizeof(int)) != hipSuccess ||
+      hipMalloc(&gs->d_coo_meta, (size_t)G * sizeof(int)) != hipSuccess ||
       hipMalloc(&gs->d_rec, (size_t)G * kRec * sizeof(double)) != hipSuccess ||
       hipMalloc(&gs->d_abort, sizeof(int)) != hipSuccess ||
       hipHostMalloc((void**)&gs->h_rec, (size_t)G * kRec * sizeof(double),
@@ -456,6 +507,8 @@ cpaa_status build_graph_state(cpaa_plan_s* pl, const int32_t* rp, const int32_t*
     return CPAA_ENOMEM;
   }
   CPAA_HIP(hipMemcpy(gs->d_coo, coo.data(), coo.size() * 4, hipMemcpyHostToDevice));
+  CPAA_HIP(hipMemcpy(gs->d_coo_off, off.data(), (size_t)G * sizeof(int), hipMemcpyHostToDevice));
+  CPAA_HIP(hipMemcpy(gs->d_coo_meta, meta.data(), (size_t)G * sizeof(int), hipMemcpyHostToDevice));
   hipDeviceProp_t prop;
   CPAA_HIP(hipGetDeviceProperties(&prop, pl->device));
   gs->num_cus = prop.multiProcessorCount;
@@ -477,6 +530,8 @@ static cpaa_status capture_run(cpaa_plan_s* pl, GraphState* gs, const double* p,
   GraphArgs a;
   a.rp = pl->d_row_ptr;
   a.coo = gs->d_coo;
+  a.coo_off = gs->d_coo_off;
+  a.coo_meta = gs->d_coo_meta;
   a.graph_ptr = pl->d_graph_ptr;
   a.order = pl->d_graph_order;
   a.num_graphs = pl->num_graphs;

@@ -124,3 +124,13 @@ def test_param_packing_roundtrip():
     back = B.unpack_params(flat, 3)
     for k, v in p.items():
         assert np.array_equal(back[k], v)
+
+
+def test_batched_reports_become_structured_records():
+    reps = (B.cpaa_report * 3)()
+    reps[1].terms, reps[1].refine_terms, reps[1].cert_bound = 7, 2, 1.5e-7
+    reps[2].edges, reps[2].certified = 123, 1
+    rec = B._report_records(reps)
+    assert rec.shape == (3,) and rec.dtype.itemsize == ctypes.sizeof(B.cpaa_report)
+    assert rec[1]["terms"] + rec[1]["refine_terms"] == 9 and rec[1]["cert_bound"] == 1.5e-7
+    assert rec[2]["edges"] == 123 and rec[2]["certified"] == 1 and rec[0]["terms"] == 0
