@@ -33,10 +33,13 @@ sys.path.insert(0, ROOT)
 
 METRIC = "GTEPS (nnz·terms/s) + PPR solves/s at ≤1e-6 L1, warm-start vs plain CPAA"
 HBM_PEAK_GBS = 8000.0
+CSRC = os.path.join(ROOT, "paper_2112_01743_amd", "csrc")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "term_chung_lu_n4m_traffic.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2112_01743_amd", "csrc", "kernels_w1.hip")
+# sources that decide what the term kernels do (kernels, shared headers, the plan builder)
+KERNEL_SRC = [os.path.join(CSRC, f) for f in ("kernels_w1.hip", "internal.h", "device.h", "api.hip")]
 TILE_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "term_tile_grid_256_traffic.json")
-TILE_KERNEL_SRC = os.path.join(ROOT, "paper_2112_01743_amd", "csrc", "kernels_tile.hip")
+TILE_KERNEL_SRC = [os.path.join(CSRC, f)
+                   for f in ("kernels_tile.hip", "internal.h", "device.h", "api.hip")]
 
 
 def log(msg):
@@ -52,11 +55,14 @@ def term_bytes(n: int, nnz: int) -> int:
     return 4 * nnz + 4 * (n + 1) + 28 * n
 
 
-def kernel_hash(src: str = KERNEL_SRC) -> str:
-    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+def kernel_hash(src=KERNEL_SRC) -> str:
+    h = hashlib.sha256()
+    for f in src:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
-def load_traffic(n, nnz, path: str = TRAFFIC_FILE, src: str = KERNEL_SRC):
+def load_traffic(n, nnz, path: str = TRAFFIC_FILE, src=KERNEL_SRC):
     """Measured HBM bytes per term (all of its launches) from the committed
     counter runs, if they were taken on the current kernel source and the same
     workload."""

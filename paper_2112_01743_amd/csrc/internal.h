@@ -61,7 +61,7 @@ struct WorkItem {
 constexpr int kSlices = 8;           // XCDs of the chip
 constexpr int kSliceRowBits = 11;    // rows per sliced work item < 2048
 constexpr int kSliceRows = 1 << kSliceRowBits;
-constexpr int kSliceNpt = 32;        // entries per thread of a sliced work item
+constexpr int kSliceNpt = 24;        // entries per thread of a sliced work item
 // local columns stay below 2^21 - 1, so no packed entry equals kSliceNone
 constexpr int64_t kSliceMaxN = int64_t(kSlices) * ((int64_t(1) << (32 - kSliceRowBits)) - 1);
 constexpr uint32_t kSliceNone = 0xFFFFFFFFu;   // padding entry
