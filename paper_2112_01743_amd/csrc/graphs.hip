@@ -40,7 +40,7 @@ struct GraphArgs {
   const int* rp;
   const uint32_t* coo;      // (local_row << 16) | local_col, per graph in transposed runs
   const int* coo_off;       // [num_graphs] first packed entry of each graph
-  const int* coo_meta;      // [num_graphs] chunks << 5 | run length
+  const int* coo_meta;      // [num_graphs] chunks << 6 | run length
   const int* graph_ptr;
   const int* order;
   int num_graphs;
@@ -136,7 +136,7 @@ __device__ void solve_graph(const GraphArgs& a, int g, unsigned char* lds, doubl
   const int v0 = a.graph_ptr[g];
   const int ng = a.graph_ptr[g + 1] - v0;
   const uint32_t* coo = a.coo + a.coo_off[g];
-  const int nch = a.coo_meta[g] >> 5, rl = a.coo_meta[g] & 31;
+  const int nch = a.coo_meta[g] >> 6, rl = a.coo_meta[g] & 63;
   // LDS regions: A = 8*max_ng bytes, B = 8*max_ng bytes
   float* za = reinterpret_cast<float*>(lds);
   float* zb = za + a.max_ng;
@@ -467,16 +467,16 @@ cpaa_status build_graph_state(cpaa_plan_s* pl, const int32_t* rp, const int32_t*
   }
   pl->graph_state = gs;
   const int G = pl->num_graphs;
-  // per graph: runs of rl entries per lane, rl = clamp(nnz_g / 1024, 4, 16),
+  // per graph: runs of rl entries per lane, rl = clamp(nnz_g / 512, 2, 16),
   // chunks of 64*rl entries, the last one padded
   std::vector<int> off(G), meta(G);
   size_t total = 0;
   for (int gi = 0; gi < G; ++gi) {
     const int mg = rp[gp[gi + 1]] - rp[gp[gi]];
-    const int rl = std::min(kGraphRunMax, std::max(4, (mg + 1023) / 1024));
+    const int rl = std::min(kGraphRunMax, std::max(2, (mg + 511) / 512));
     const int nch = (mg + 64 * rl - 1) / (64 * rl);
     off[gi] = static_cast<int>(total);
-    meta[gi] = (nch << 5) | rl;
+    meta[gi] = (nch << 6) | rl;
     total += static_cast<size_t>(nch) * 64 * rl;
   }
   if (total >= (size_t(1) << 31)) {
@@ -486,7 +486,7 @@ cpaa_status build_graph_state(cpaa_plan_s* pl, const int32_t* rp, const int32_t*
   std::vector<uint32_t> coo(total, kGraphPad);
   for (int gi = 0; gi < G; ++gi) {
     const int v0 = gp[gi], e0 = rp[v0];
-    const int rl = meta[gi] & 31, ch = 64 * rl;
+    const int rl = meta[gi] & 63, ch = 64 * rl;
     int q = 0;
     for (int u = gp[gi]; u < gp[gi + 1]; ++u)
       for (int j = rp[u]; j < rp[u + 1]; ++j, ++q) {
