@@ -109,7 +109,8 @@ def evaluate(plan, model, g, sources, *, tol=1e-6, chunk=256):
         out["fallback"] += sum(r["fallback_used"] for r in rw)
         diff = (Xw - Xp).abs().sum(dim=1).cpu().numpy()
         bounds = np.array([a["cert_bound"] + b["cert_bound"] for a, b in zip(rw, rp)])
-        if not (np.all(diff <= bounds) and all(r["certified"] for r in rw + rp)):
+        certified = np.all(rw["certified"] == 1) and np.all(rp["certified"] == 1)
+        if not (np.all(diff <= bounds) and certified):
             raise RuntimeError("warm-started and plain results disagree beyond their bounds")
         out["agree_max"] = max(out["agree_max"], float(diff.max()))
         out["x0_l1"] += (X0 - Xp).abs().sum(dim=1).cpu().numpy().tolist()
