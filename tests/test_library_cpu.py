@@ -134,3 +134,13 @@ def test_batched_reports_become_structured_records():
     assert rec.shape == (3,) and rec.dtype.itemsize == ctypes.sizeof(B.cpaa_report)
     assert rec[1]["terms"] + rec[1]["refine_terms"] == 9 and rec[1]["cert_bound"] == 1.5e-7
     assert rec[2]["edges"] == 123 and rec[2]["certified"] == 1 and rec[0]["terms"] == 0
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    res = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                         capture_output=True, text=True, timeout=120)
+    assert res.returncode == 2 and "one GPU" in res.stderr and res.stdout == ""
