@@ -188,9 +188,9 @@ void parallel_for(int64_t count, F body) {
 }
 
 // Labelling of the column-sliced path: vertices ranked by degree (descending,
-// ties by label) and dealt round-robin into kSlices slices, slice s taking the
-// contiguous labels [slice_off[s], slice_off[s+1]).  Every slice gets n/8
-// vertices and about vol/8 stored entries as columns.  Returns the relabelled
+// ties by label) and dealt round-robin, in groups of 8 ranks, into kSlices
+// slices, slice s taking the contiguous labels [slice_off[s], slice_off[s+1]).
+// Every slice gets n/8 vertices and about vol/8 stored entries as columns.  Returns the relabelled
 // CSR (rows and columns in new labels, columns sorted) and perm[new] = old.
 void slice_relabel(int32_t n, const int32_t* rp, const int32_t* ci, std::vector<int32_t>& rp2,
                    std::vector<int32_t>& ci2, std::vector<int32_t>& perm,
@@ -200,13 +200,19 @@ void slice_relabel(int32_t n, const int32_t* rp, const int32_t* ci, std::vector<
   std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
     return rp[a + 1] - rp[a] > rp[b + 1] - rp[b];
   });
+  // ranks are dealt in groups of kDeal (8 doubles = one 64-byte line), so
+  // vertices that are neighbours in the caller's order and in rank stay
+  // neighbours in a slice (cheap gathers and scatters of p and x)
+  constexpr int32_t kDeal = 8;
+  auto slice_of = [&](int32_t r) { return (r / kDeal) % kSlices; };
+  int32_t count[kSlices] = {};
+  for (int32_t r = 0; r < n; ++r) ++count[slice_of(r)];
   slice_off[0] = 0;
-  for (int sl = 0; sl < kSlices; ++sl)
-    slice_off[sl + 1] = slice_off[sl] + (n > sl ? (n - sl + kSlices - 1) / kSlices : 0);
+  for (int sl = 0; sl < kSlices; ++sl) slice_off[sl + 1] = slice_off[sl] + count[sl];
   std::vector<int32_t> new_of(n);
   perm.assign(n, 0);
   for (int32_t r = 0; r < n; ++r) {
-    const int32_t u = slice_off[r % kSlices] + r / kSlices;
+    const int32_t u = slice_off[slice_of(r)] + (r / (kDeal * kSlices)) * kDeal + r % kDeal;
     new_of[order[r]] = u;
     perm[u] = order[r];
   }
