@@ -580,13 +580,28 @@ cpaa_status cpaa_plan(const cpaa_csr* g, double c, const cpaa_opts* opts, cpaa_p
       pl->max_graph_n = std::max(pl->max_graph_n, gp[gi + 1] - gp[gi]);
       pl->max_graph_nnz = std::max(pl->max_graph_nnz, gnnz[gi]);
     }
+    // size classes: class 0 holds graphs with more than max_n/2 vertices, class 1
+    // more than max_n/4, class 2 the rest; each class is launched with the LDS
+    // its own largest graph needs, so small graphs get more workgroups per CU
+    auto cls = [&](int gi) {
+      const int ng = gp[gi + 1] - gp[gi];
+      return ng * 2 > pl->max_graph_n ? 0 : (ng * 4 > pl->max_graph_n ? 1 : 2);
+    };
     std::vector<int32_t> order(num_graphs);
     for (int gi = 0; gi < num_graphs; ++gi) order[gi] = gi;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int32_t a, int32_t b) { return gnnz[a] > gnnz[b]; });
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+      return cls(a) != cls(b) ? cls(a) < cls(b) : gnnz[a] > gnnz[b];
+    });
+    for (int k = 0; k <= kGraphClasses; ++k) pl->graph_cls_off[k] = 0;
+    for (int gi = 0; gi < num_graphs; ++gi) {
+      const int k = cls(gi);
+      ++pl->graph_cls_off[k + 1];
+      pl->graph_cls_n[k] = std::max(pl->graph_cls_n[k], gp[gi + 1] - gp[gi]);
+    }
+    for (int k = 0; k < kGraphClasses; ++k) pl->graph_cls_off[k + 1] += pl->graph_cls_off[k];
     s = dev_upload(&pl->d_graph_ptr, gp, num_graphs + 1);
     if (s == CPAA_OK) s = dev_upload(&pl->d_graph_order, order.data(), order.size());
-    if (s == CPAA_OK) s = dev_alloc(&pl->d_queue, 1);
+    if (s == CPAA_OK) s = dev_alloc(&pl->d_queue, kGraphClasses);
     if (s == CPAA_OK) s = build_graph_state(pl, rp, ci, gp);
   }
   if (s == CPAA_OK) {

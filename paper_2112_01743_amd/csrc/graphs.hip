@@ -8,16 +8,16 @@
 //     accumulator, right-hand side and residual live in registers (a fixed set
 //     of rows per thread);
 //   * one term is one pass over the graph's entries, stored as packed local
-//     (row, column) 16-bit pairs in row-major order: gather z from LDS and add
-//     into the row sum with an LDS atomic (ds_add_f32), so every thread gets
-//     the same number of entries whatever the degree distribution;
+//     (row, column) 16-bit pairs in per-lane runs (see coo_pass): gather z
+//     from LDS, sum rows in registers, so every thread gets the same number
+//     of entries whatever the degree distribution;
 //   * the three-term update, D^{-1} scaling and FP64 accumulation follow in the
 //     epilogue, and from the mass-error bound on (eq. 4.1) the workgroup
 //     evaluates the in-loop certificate and stops that graph on its own;
 //   * the FP64 residual (with its rounding allowance) and, if needed,
 //     correction series run in the same workgroup, then D acc is written out.
-// The host captures "reset queue -> validate p -> persistent solve" once in a
-// HIP graph per (p, x, tol) and replays it.
+// The host captures "reset queues -> validate p -> persistent solves" once in
+// a HIP graph per (p, x, tol) and replays it.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -347,10 +347,8 @@ __global__ __launch_bounds__(BLOCK) void k_graphs(GraphArgs a) {
 // graph's block is not a probability vector.  One workgroup per graph.
 __global__ __launch_bounds__(kWG) void k_validate_graphs(const int* __restrict__ graph_ptr,
                                                          const double* __restrict__ p,
-                                                         double* __restrict__ rec, int* abort,
-                                                         int* queue) {
+                                                         double* __restrict__ rec, int* abort) {
   const int g = blockIdx.x;
-  if (g == 0 && threadIdx.x == 0) *queue = 0;
   const int v0 = graph_ptr[g], v1 = graph_ptr[g + 1];
   double s = 0.0, neg = 0.0, bad = 0.0;
   for (int u = v0 + threadIdx.x; u < v1; u += kWG) {
@@ -371,8 +369,9 @@ __global__ __launch_bounds__(kWG) void k_validate_graphs(const int* __restrict__
   }
 }
 
-__global__ void k_reset_graph_run(int* abort) {
+__global__ void k_reset_graph_run(int* abort, int* queue) {
   if (threadIdx.x == 0) *abort = 0;
+  if (threadIdx.x < kGraphClasses) queue[threadIdx.x] = 0;
 }
 
 }  // namespace
@@ -517,26 +516,12 @@ cpaa_status build_graph_state(cpaa_plan_s* pl, const int32_t* rp, const int32_t*
 
 static cpaa_status capture_run(cpaa_plan_s* pl, GraphState* gs, const double* p, double tol,
                                double* x, int block, hipStream_t st) {
-  int rpt = 0;
-  if (!pick_shape(pl->max_graph_n, block, &rpt)) {
-    set_error("graphs too large for the batched kernel");
-    return CPAA_EINVAL;
-  }
-  const size_t lds = 16 * (size_t)pl->max_graph_n;
-  CPAA_HIP(set_lds_limit(block, rpt, lds));
-  // resident workgroups per CU: 2048 threads and 160 KB of LDS per CU
-  const int per_cu =
-      std::max(1, std::min(2048 / block, (int)((160 * 1024) / (lds + (size_t)block / 8 + 64))));
   GraphArgs a;
   a.rp = pl->d_row_ptr;
   a.coo = gs->d_coo;
   a.coo_off = gs->d_coo_off;
   a.coo_meta = gs->d_coo_meta;
   a.graph_ptr = pl->d_graph_ptr;
-  a.order = pl->d_graph_order;
-  a.num_graphs = pl->num_graphs;
-  a.max_ng = pl->max_graph_n;
-  a.queue = pl->d_queue;
   a.abort = gs->d_abort;
   a.p = p;
   a.x = x;
@@ -552,7 +537,41 @@ static cpaa_status capture_run(cpaa_plan_s* pl, GraphState* gs, const double* p,
   a.max_refine = pl->opts.max_refine;
   a.normalize = pl->opts.normalize;
   a.rec = gs->d_rec;
-  const dim3 grid(std::min(pl->num_graphs, gs->num_cus * per_cu));
+  // one persistent launch per size class, each with the LDS of its largest graph
+  struct ClassLaunch {
+    GraphArgs a;
+    int rpt;
+    size_t lds;
+    dim3 grid;
+  };
+  std::vector<ClassLaunch> launches;
+  for (int k = 0; k < kGraphClasses; ++k) {
+    const int count = pl->graph_cls_off[k + 1] - pl->graph_cls_off[k];
+    if (count == 0) continue;
+    ClassLaunch L;
+    L.a = a;
+    L.a.order = pl->d_graph_order + pl->graph_cls_off[k];
+    L.a.num_graphs = count;
+    L.a.max_ng = pl->graph_cls_n[k];
+    L.a.queue = pl->d_queue + k;
+    if (!pick_shape(L.a.max_ng, block, &L.rpt)) {
+      set_error("graphs too large for the batched kernel");
+      return CPAA_EINVAL;
+    }
+    L.lds = 16 * (size_t)L.a.max_ng;
+    // resident workgroups per CU: 2048 threads and 160 KB of LDS per CU
+    const int per_cu = std::max(
+        1, std::min(2048 / block, (int)((160 * 1024) / (L.lds + (size_t)block / 8 + 64))));
+    L.grid = dim3(std::min(count, gs->num_cus * per_cu));
+    launches.push_back(L);
+  }
+  // classes can share a (block, rpt) instantiation: raise its LDS limit to the largest use
+  for (const ClassLaunch& L : launches) {
+    size_t lds = L.lds;
+    for (const ClassLaunch& M : launches)
+      if (M.rpt == L.rpt) lds = std::max(lds, M.lds);
+    CPAA_HIP(set_lds_limit(block, L.rpt, lds));
+  }
 
   GraphRun& run = gs->run;
   if (run.exec) (void)hipGraphExecDestroy(run.exec);
@@ -562,10 +581,12 @@ static cpaa_status capture_run(cpaa_plan_s* pl, GraphState* gs, const double* p,
   CPAA_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
   hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_reset_graph_run, dim3(1), dim3(64), 0, cs, gs->d_abort);
+    hipLaunchKernelGGL(k_reset_graph_run, dim3(1), dim3(64), 0, cs, gs->d_abort, pl->d_queue);
     hipLaunchKernelGGL(k_validate_graphs, dim3(pl->num_graphs), dim3(kWG), 0, cs,
-                       pl->d_graph_ptr, p, gs->d_rec, gs->d_abort, pl->d_queue);
-    hipError_t el = launch_graphs(block, rpt, grid, lds, cs, a);
+                       pl->d_graph_ptr, p, gs->d_rec, gs->d_abort);
+    hipError_t el = hipSuccess;
+    for (const ClassLaunch& L : launches)
+      if (el == hipSuccess) el = launch_graphs(block, L.rpt, L.grid, L.lds, cs, L.a);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(cs, &graph);
     if (el != hipSuccess) e = el;
