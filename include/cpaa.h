@@ -153,9 +153,14 @@ typedef struct {
 CPAA_API void cpaa_default_opts(cpaa_opts* o);
 
 /* Build a plan for graph g and damping c (Sec. 2.1).  Validates the pattern
- * (if opts->validate), computes degrees, the degree bins / workgroup map,
- * the coefficient table c_k (Prop. 1: c_k = c_0 beta^k), and uploads the
- * pattern to the current device.  opts may be NULL (defaults).
+ * (if opts->validate), computes degrees, the work-item maps, the coefficient
+ * table c_k (Prop. 1: c_k = c_0 beta^k), and uploads the pattern to the
+ * current device.  With column slices (opts->column_slices) the plan also
+ * holds a relabelled copy of the pattern and the per-slice packed entries:
+ * about three times the pattern's 4 (n + 1 + nnz) bytes in device memory, plus
+ * 32 n bytes of partial sums once a solve runs.  For a block-diagonal batch
+ * (num_graphs > 1) it packs each graph's entries for cpaa_solve_graphs.
+ * opts may be NULL (defaults).
  * Errors: CPAA_EINVAL, CPAA_ENOTSYM, CPAA_EISOLATED, CPAA_ESELFLOOP,
  * CPAA_EPATTERN, CPAA_ENOMEM, CPAA_EDEVICE.  On success *out owns the plan. */
 CPAA_API cpaa_status cpaa_plan(const cpaa_csr* g, double c, const cpaa_opts* opts, cpaa_plan_t* out);
