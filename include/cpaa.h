@@ -107,7 +107,7 @@ typedef struct {
                              in its L2, and a combine pass adds the 8 partial row sums and
                              applies the term update.  Auto: on for one graph with n >= 2^20
                              and max degree >= 16 x average degree.  Needs one graph and
-                             n < 8 (2^21 - 1) (else CPAA_EINVAL).  Inputs and outputs keep the caller's
+                             n < 8 (2^21 - 16) (else CPAA_EINVAL).  Inputs and outputs keep the caller's
                              labels. */
 } cpaa_opts;
 

@@ -230,14 +230,14 @@ void slice_relabel(int32_t n, const int32_t* rp, const int32_t* ci, std::vector<
 // Work items and packed entries of the column-sliced term (relabelled CSR).
 // Per slice the items cover every row (rows without entries in the slice
 // still get their zero partial written): consecutive rows with at most
-// kWG * kSliceNpt entries and kSliceRows rows per item; a row with more entries
+// kWG * kSliceNpt entries and 2^row_bits rows per item; a row with more entries
 // in one slice than an item holds is cut into split chunks (plain local
 // columns, nnz1 = physical end).  Multi-row items store their entries in the
 // transposed per-wavefront layout described below; nnz0 is the physical start
 // and nnz1 - nnz0 the number of entries (the layout pads each wavefront's
 // share to a multiple of 64 with kSliceNone).
 void build_sliced(int32_t n, const std::vector<int32_t>& rp2, const std::vector<int32_t>& ci2,
-                  const int slice_off[kSlices + 1], std::vector<uint32_t>& entries,
+                  const int slice_off[kSlices + 1], int row_bits, std::vector<uint32_t>& entries,
                   std::vector<WorkItem>& items, std::vector<int>& split_nchunks,
                   int item_off[kSlices + 1]) {
   const int cap = kWG * kSliceNpt;
@@ -275,10 +275,10 @@ void build_sliced(int32_t n, const std::vector<int32_t>& rp2, const std::vector<
       }
       const int32_t r0 = r;
       logical.clear();
-      while (r < n && r - r0 < kSliceRows && len[r] <= cap &&
+      while (r < n && r - r0 < (1 << row_bits) && len[r] <= cap &&
              static_cast<int>(logical.size()) + len[r] <= cap) {
         for (int j = beg[r]; j < beg[r] + len[r]; ++j)
-          logical.push_back((static_cast<uint32_t>(ci2[j] - lo) << kSliceRowBits) |
+          logical.push_back((static_cast<uint32_t>(ci2[j] - lo) << row_bits) |
                             static_cast<uint32_t>(r - r0));
         ++r;
       }
@@ -410,7 +410,7 @@ cpaa_status cpaa_plan(const cpaa_csr* g, double c, const cpaa_opts* opts, cpaa_p
     return CPAA_EINVAL;
   }
   if (o.column_slices == kSlices && (g->num_graphs > 1 || g->n >= kSliceMaxN)) {
-    set_error("column slices need one graph with n < 8 (2^21 - 1)");
+    set_error("column slices need one graph with n < 8 (2^21 - 16)");
     return CPAA_EINVAL;
   }
   if (o.k_max < 0 || o.max_refine < 0) {
@@ -543,12 +543,23 @@ cpaa_status cpaa_plan(const cpaa_csr* g, double c, const cpaa_opts* opts, cpaa_p
     std::vector<uint32_t> entries;
     std::vector<WorkItem> sitems;
     std::vector<int> snch;
-    build_sliced(n, rp2, ci2, pl->slc.slice_off, entries, sitems, snch, pl->slc.item_off);
+    int max_slice = 0;
+    for (int sl = 0; sl < kSlices; ++sl)
+      max_slice = std::max(max_slice, pl->slc.slice_off[sl + 1] - pl->slc.slice_off[sl]);
+    // 12 row bits (bigger items) while local columns fit 20 bits below kSliceNone
+    pl->slc.row_bits = max_slice <= (1 << 20) - 1 ? kSliceRowBitsMax : 11;
+    if (max_slice > (1 << 21) - 2) {
+      set_error("column slice too large for the packed entries");
+      s = CPAA_EINVAL;
+    }
+    if (s == CPAA_OK)
+      build_sliced(n, rp2, ci2, pl->slc.slice_off, pl->slc.row_bits, entries, sitems, snch,
+                   pl->slc.item_off);
     for (int sl = 0; sl < kSlices; ++sl)
       pl->slc.max_items =
           std::max(pl->slc.max_items, pl->slc.item_off[sl + 1] - pl->slc.item_off[sl]);
     pl->slc.n_split_rows = static_cast<int>(snch.size());
-    s = dev_upload(&pl->d_rp_w1, rp2.data(), rp2.size());
+    if (s == CPAA_OK) s = dev_upload(&pl->d_rp_w1, rp2.data(), rp2.size());
     if (s == CPAA_OK) s = dev_upload(&pl->d_ci_w1, ci2.data(), ci2.size());
     if (s == CPAA_OK) s = dev_upload(&pl->d_perm, perm.data(), perm.size());
     if (s == CPAA_OK) s = dev_upload(&pl->slc.d_entries, entries.data(), entries.size());

@@ -57,14 +57,16 @@ struct WorkItem {
 // Column-sliced single-vector term (one column slice per XCD).  Vertices are
 // relabelled so that slice s is the contiguous label range
 // [slice_off[s], slice_off[s+1]); slice s's stored entries (row order) are
-// packed as (column - slice_off[s]) << kSliceRowBits | (row - item.row0).
+// packed as (column - slice_off[s]) << row_bits | (row - item.row0), with
+// row_bits = 12 when every slice has fewer than 2^20 - 1 vertices, else 11.
 // Chunks of rows split across workgroups store the plain local column.
 constexpr int kSlices = 8;           // XCDs of the chip
-constexpr int kSliceRowBits = 11;    // rows per sliced work item < 2048
-constexpr int kSliceRows = 1 << kSliceRowBits;
-constexpr int kSliceNpt = 24;        // entries per thread of a sliced work item
-// local columns stay below 2^21 - 1, so no packed entry equals kSliceNone
-constexpr int64_t kSliceMaxN = int64_t(kSlices) * ((int64_t(1) << (32 - kSliceRowBits)) - 1);
+constexpr int kSliceRowBitsMax = 12;
+constexpr int kSliceRowsMax = 1 << kSliceRowBitsMax;   // LDS row sums of a sliced work item
+constexpr int kSliceNpt = 32;        // entries per thread of a sliced work item
+// with 11 row bits local columns stay below 2^21 - 1, so no packed entry
+// equals kSliceNone (slices hold at most n/8 + 8 vertices)
+constexpr int64_t kSliceMaxN = int64_t(kSlices) * ((int64_t(1) << 21) - 16);
 constexpr uint32_t kSliceNone = 0xFFFFFFFFu;   // padding entry
 constexpr int kSliceHub = 2048;      // leading vertices of a slice cached in LDS per work item
 
@@ -74,6 +76,7 @@ struct SlicedMap {
   int item_off[kSlices + 1] = {};    // items of slice s: [item_off[s], item_off[s+1])
   int max_items = 0;                 // most items in one slice
   int slice_off[kSlices + 1] = {};   // vertex labels of slice s
+  int row_bits = 11;                 // local row field of a packed entry
   int n_split_rows = 0;
   int* d_split_nchunks = nullptr;    // [n_split_rows]
 };

@@ -224,7 +224,7 @@ struct PartEpi {
   __device__ __forceinline__ void row(int r, int, float s, float) { out[r] = s; }
 };
 
-template <int NPT>
+template <int NPT, int RB>
 __global__ __launch_bounds__(kWG) void k_term_sliced(SlicedArgs a) {
   if (a.done != nullptr && *a.done) return;
   const int sl = blockIdx.x % kSlices;
@@ -247,7 +247,7 @@ __global__ __launch_bounds__(kWG) void k_term_sliced(SlicedArgs a) {
                                      a.split_nchunks, epi);
     return;
   }
-  __shared__ float rsum[kSliceRows];
+  __shared__ float rsum[kSliceRowsMax];
   __shared__ float hub[kSliceHub];
   const int lane = t & 63;
   const int nrows = it.row1 - it.row0;
@@ -272,7 +272,7 @@ __global__ __launch_bounds__(kWG) void k_term_sliced(SlicedArgs a) {
 #pragma unroll
   for (int i = 0; i < NPT; ++i) {
     float h = 0.f, g = 0.f;
-    const uint32_t c = e[i] >> kSliceRowBits;
+    const uint32_t c = e[i] >> RB;
     if (e[i] != kNone && c < static_cast<uint32_t>(kSliceHub)) h = hub[c];
     if (e[i] != kNone && c >= static_cast<uint32_t>(kSliceHub)) g = xs[c];
     v[i] = h + g;
@@ -280,14 +280,14 @@ __global__ __launch_bounds__(kWG) void k_term_sliced(SlicedArgs a) {
   // Row sums of the run in a register.  A row that starts and ends strictly
   // inside the run has no other contributor: plain store.  The first and the
   // last row of a run may be shared with neighbouring runs: LDS atomic.
-  constexpr uint32_t kMask = (1u << kSliceRowBits) - 1u;
+  constexpr uint32_t row_mask = (1u << RB) - 1u;
   int row = -1;
   float sum = 0.f;
   bool first = true;
 #pragma unroll
   for (int i = 0; i < NPT; ++i) {
     if (e[i] != kNone) {
-      const int r = static_cast<int>(e[i] & kMask);
+      const int r = static_cast<int>(e[i] & row_mask);
       if (r != row) {
         if (row >= 0) {
           if (first)
@@ -511,8 +511,11 @@ hipError_t term_w1(const cpaa_plan_s* pl, Workspace& ws, int cur, int prev, int 
       s.item_off[i] = pl->slc.item_off[i];
       s.slice_off[i] = pl->slc.slice_off[i];
     }
-    hipLaunchKernelGGL(k_term_sliced<kSliceNpt>, dim3(kSlices * pl->slc.max_items), dim3(kWG), 0,
-                       st, s);
+    const dim3 grid(kSlices * pl->slc.max_items);
+    if (pl->slc.row_bits == kSliceRowBitsMax)
+      hipLaunchKernelGGL((k_term_sliced<kSliceNpt, kSliceRowBitsMax>), grid, dim3(kWG), 0, st, s);
+    else
+      hipLaunchKernelGGL((k_term_sliced<kSliceNpt, 11>), grid, dim3(kWG), 0, st, s);
     CombineArgs c;
     c.rp = pl->d_rp_w1;
     c.part = ws.part;
