@@ -88,6 +88,8 @@ def _plan_status(rp, ci, c=0.85, **kw):
     ("duplicate", [0, 2, 3], [1, 1, 0], B.CPAA_EPATTERN),
     ("out_of_range", [0, 1, 2], [5, 0], B.CPAA_EPATTERN),
     ("bad_rowptr", [0, 2, 1], [1, 0], B.CPAA_EPATTERN),
+    ("empty", [0], [], B.CPAA_EINVAL),
+    ("no_edges", [0, 0, 0], [], B.CPAA_EISOLATED),
 ])
 def test_plan_rejects_bad_patterns(case, rp, ci, status):
     assert _plan_status(rp, ci) == status, (case, B.cpaa_last_error())
