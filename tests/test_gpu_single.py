@@ -298,3 +298,34 @@ def test_kernel_timing_report(torch_cuda):
     assert rep["term_launches"] == rep["terms"] + rep["refine_terms"]
     assert rep["ms_terms"] > 0 and rep["ms_total"] >= rep["ms_terms"]
     assert rep["edges"] == g.nnz * (rep["terms"] + rep["refine_terms"])
+
+
+def test_independent_plans_on_two_streams(torch_cuda):
+    """Different plans are independent: solves issued from two threads on two
+    torch streams (default priority) give the same results as alone."""
+    import threading
+    from paper_2112_01743_amd import Plan
+    torch = torch_cuda
+    g1 = gg.chung_lu(40000, 12, 2.2, seed=51, dmax=8000)
+    g2 = gg.perturbed_grid(150, 0.05, 0.01, seed=52)
+    cases = [(Plan.from_graph(g1, C), g1, gg.source_personalization(g1.n, [7])[0]),
+             (Plan.from_graph(g2, C), g2, gg.uniform_personalization(g2.n))]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    out = [None, None]
+
+    def run(i):
+        plan, g, p = cases[i]
+        with torch.cuda.stream(streams[i]):
+            pd = _dev(torch, p)
+            for _ in range(3):
+                x, rep = plan.solve(pd, 1e-8, stream=streams[i])
+            out[i] = (x.cpu().numpy(), rep)
+
+    threads = [threading.Thread(target=run, args=(i,)) for i in range(2)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    for i, (plan, g, p) in enumerate(cases):
+        x, rep = out[i]
+        _assert_parity(g, p, x, rep, 1e-8)
