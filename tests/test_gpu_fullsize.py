@@ -113,3 +113,35 @@ def test_uneven_batch_10k_graphs(torch_cuda):
         v0, v1 = gp[k], gp[k + 1]
         pi = oracle.pagerank_exact(sub, p[v0:v1], C)
         assert np.abs(x[v0:v1] - pi).sum() <= TOL
+
+
+@pytest.mark.timeout(600)
+def test_warm_start_network_at_1m(torch_cuda):
+    """The network's forward pass on the 1M-vertex warm-start graph against the
+    bf16-emulating FP64 oracle, and a warm-started solve at that size judged
+    against the plain one."""
+    from paper_2112_01743_amd import Plan
+    from paper_2112_01743_amd.binding import Model
+    from oracle import mpnn as om
+    torch = torch_cuda
+    g = gg.chung_lu(1_000_000, 16, 2.1, seed=2112005, dmax=50000)
+    _note(f"chung-lu n={g.n} nnz={g.nnz}")
+    plan = Plan.from_graph(g, C)
+    params = gg.mpnn_init(2112004)
+    model = Model(plan, params)
+    src = [int(s) for s in gg.random_sources(g.n, 2, seed=2112005)]
+    X0 = model.predict(src)
+    X0n = X0.cpu().numpy()
+    p64 = {k: v.astype(np.float64) for k, v in params.items()}
+    for j, s in enumerate(src):
+        ref, _ = om.mpnn_forward(g, p64, s, bf16=True)
+        l1 = np.abs(X0n[j] - ref).sum()
+        _note(f"source {s}: forward L1 vs oracle {l1:.3e}")
+        assert abs(X0n[j].sum() - 1.0) < 1e-12 and l1 < 5e-3
+    P = torch.zeros((2, g.n), dtype=torch.float64, device="cuda")
+    P[torch.arange(2), torch.as_tensor(src, device="cuda")] = 1.0
+    Xw, rw = plan.solve_batched(P, TOL, X0=X0)
+    Xp, rp = plan.solve_batched(P, TOL)
+    assert np.all(rw["certified"] == 1) and np.all(rp["certified"] == 1)
+    diff = (Xw - Xp).abs().sum(dim=1).cpu().numpy()
+    assert np.all(diff <= rw["cert_bound"] + rp["cert_bound"])
