@@ -105,7 +105,7 @@ typedef struct {
                              column slice, slice s on the workgroups the hardware places on XCD
                              s, so every XCD gathers from one eighth of the vector, which stays
                              in its L2, and a combine pass adds the 8 partial row sums and
-                             applies the term update.  Auto: on for one graph with n >= 2^20
+                             applies the term update.  Auto: on for one graph with n >= 3 * 2^18
                              and max degree >= 16 x average degree.  Needs one graph and
                              n < 8 (2^21 - 16) (else CPAA_EINVAL).  Inputs and outputs keep the caller's
                              labels. */
