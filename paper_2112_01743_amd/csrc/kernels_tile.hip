@@ -117,6 +117,7 @@ __device__ __forceinline__ void spmm_item(const WorkItem it, const int* __restri
     return;
   }
   if (it.row1 >= 0) {
+    // W < 64: 64/W rows at a time, lane (q, j) = (row group, column)
     for (int r = it.row0 + q; r < it.row1; r += G) {
       const int beg = rp[r], end = rp[r + 1];
       // the epilogue's own loads go out first; then up to kBurst neighbour
@@ -133,12 +134,19 @@ __device__ __forceinline__ void spmm_item(const WorkItem it, const int* __restri
         s1 += x[u + 1];
         if (ABS) sa += fabs(x[u]) + fabs(x[u + 1]);
       }
+      if (end - beg <= kBurst) {
+        epi.row(r, end - beg, j, s0 + s1, sa, pre);
+        continue;
+      }
+      // longer rows (one lane each): the rest is summed in FP64
+      double t = static_cast<double>(s0) + static_cast<double>(s1);
+      double ta = static_cast<double>(sa);
       for (int k = beg + kBurst; k < end; ++k) {
         const V a = X[(size_t)ci[k] * W + j];
-        s0 += a;
-        if (ABS) sa += fabs(a);
+        t += static_cast<double>(a);
+        if (ABS) ta += fabs(static_cast<double>(a));
       }
-      epi.row(r, end - beg, j, s0 + s1, sa, pre);
+      epi.row(r, end - beg, j, static_cast<V>(t), static_cast<V>(ta), pre);
     }
     return;
   }
