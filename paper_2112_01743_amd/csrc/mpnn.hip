@@ -524,7 +524,7 @@ __global__ __launch_bounds__(kWG) void k_dh(int n, const float* __restrict__ dz,
     float a = 0.f, b = 0.f;
 #pragma unroll 8
     for (int j = 0; j < kHid; ++j) {
-      const float zj = __shfl(mine, j);
+      const float zj = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mine), j));
       a += zj * ws[lane][j];
       b += zj * wn[lane][j];
     }
@@ -655,7 +655,7 @@ static hipError_t backward(cpaa_model_s* md, const double* x0, const double* pi,
     hipLaunchKernelGGL(k_dz, dim3(gw), dim3(kWG), 0, st, n, md->h[l], md->gs, md->wr, md->o,
                        l == L - 1 ? nullptr : md->dh, md->dz);
     if (l >= 1) {
-      const int chunk = 4096;
+      const int chunk = 1024;   // ~1000 workgroups at n = 1M
       hipLaunchKernelGGL(k_wgrad64, dim3((n + chunk - 1) / chunk), dim3(kWG), 0, st, n,
                          md->h[l - 1], md->m[l - 1], md->dz, md->grads, md->o.w_self[l],
                          md->o.w_nbr[l], md->o.b[l], chunk);
