@@ -190,13 +190,24 @@ hipError_t fill_f64(double* p, double v, size_t count, hipStream_t st);
 hipError_t fill_i32(int* p, int v, size_t count, hipStream_t st);
 hipError_t collapse_stats(Workspace& ws, hipStream_t st);
 
+// What one term launch (producing z_{k+1}) adds to the FP64 accumulator:
+//     on:  acc += a_prev z_{k-1} + a_cur z_k + a_next z_{k+1}
+//     off: nothing (a later launch of the same series adds it).
+// Launches before the first stopping check may leave the update to the next
+// one or two launches, whose epilogues still hold z_{k-1} and z_k: three
+// terms then cost one read-modify-write of acc instead of three.
+struct AccUpdate {
+  double a_prev, a_cur, a_next;
+  int on;
+};
+
 // ---- single-vector path (W = 1) ----
 // src: caller vector (p or x0) or the plan's own residual; b = scale * src.
 hipError_t init_w1(const cpaa_plan_s* pl, Workspace& ws, const double* src, double scale,
                    bool add, bool store_b, bool series, hipStream_t st);
 hipError_t load_x0_w1(const cpaa_plan_s* pl, Workspace& ws, const double* x0, hipStream_t st);
 hipError_t term_w1(const cpaa_plan_s* pl, Workspace& ws, int cur, int prev, int next,
-                   bool first, double a_next, double* cert_slot, const int* done,
+                   bool first, const AccUpdate& au, double* cert_slot, const int* done,
                    hipStream_t st);
 hipError_t check_series(const cpaa_plan_s* pl, Workspace& ws, const double* cert_slot,
                         double scale, double target, int term_index, hipStream_t st);
@@ -212,7 +223,7 @@ hipError_t init_tile_from_r(const cpaa_plan_s* pl, Workspace& ws, const int* act
 hipError_t load_x0_tile(const cpaa_plan_s* pl, Workspace& ws, const double* X0, int64_t ldx0,
                         int B, hipStream_t st);
 hipError_t term_tile(const cpaa_plan_s* pl, Workspace& ws, int cur, int prev, int next,
-                     bool first, double a_next, double* cert_slot, const int* done,
+                     bool first, const AccUpdate& au, double* cert_slot, const int* done,
                      hipStream_t st);
 hipError_t residual_tile(const cpaa_plan_s* pl, Workspace& ws, const int* active, hipStream_t st);
 hipError_t finalize_tile(const cpaa_plan_s* pl, Workspace& ws, double* X, int64_t ldx, int B,

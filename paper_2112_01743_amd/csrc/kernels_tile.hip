@@ -233,7 +233,8 @@ struct TileTermEpi {
   double* __restrict__ acc;
   int W;
   float alpha, gamma;
-  double a_next, beta;
+  AccUpdate au;
+  double beta;
   int want_cert;
   double cert;
   struct Pre {
@@ -242,14 +243,21 @@ struct TileTermEpi {
   };
   __device__ __forceinline__ Pre prefetch(int r, int j) const {
     const size_t idx = (size_t)r * W + j;
-    return {gamma != 0.f ? zp[idx] : 0.f, want_cert ? zc[idx] : 0.f, acc[idx]};
+    return {gamma != 0.f || au.a_prev != 0.0 ? zp[idx] : 0.f,
+            want_cert || au.a_cur != 0.0 ? zc[idx] : 0.f, au.on ? acc[idx] : 0.0};
   }
   __device__ __forceinline__ void row(int r, int d, int j, float s, float, const Pre& p) {
     const size_t idx = (size_t)r * W + j;
     float y = alpha * (s / static_cast<float>(d));
     if (gamma != 0.f) y -= gamma * p.zp;
     zn[idx] = y;
-    acc[idx] = p.acc + a_next * static_cast<double>(y);
+    if (au.on) {
+      // the newest (smallest) term first
+      double add = au.a_next * static_cast<double>(y);
+      if (au.a_cur != 0.0) add += au.a_cur * static_cast<double>(p.zc);
+      if (au.a_prev != 0.0) add += au.a_prev * static_cast<double>(p.zp);
+      acc[idx] = p.acc + add;
+    }
     if (want_cert)
       cert += static_cast<double>(d) *
               fabs(static_cast<double>(y) - beta * static_cast<double>(p.zc));
@@ -267,7 +275,8 @@ struct TileTermArgs {
   float* z_next;
   double* acc;
   float alpha, gamma;
-  double a_next, beta;
+  AccUpdate au;
+  double beta;
   double* cert;        // [kSlots][cols] or null
   int64_t cols;
   const int* done;     // [tiles] or null
@@ -286,7 +295,7 @@ __global__ __launch_bounds__(kWG) void k_term_tile(TileTermArgs a) {
   const int item = __builtin_amdgcn_readfirstlane(lb * kWaves + (threadIdx.x >> 6));
   const size_t off = (size_t)t * a.n * W;
   TileTermEpi epi{a.z_cur + off, a.z_prev ? a.z_prev + off : nullptr, a.z_next + off,
-                  a.acc + off, W, a.alpha, a.gamma, a.a_next, a.beta, a.cert != nullptr, 0.0};
+                  a.acc + off, W, a.alpha, a.gamma, a.au, a.beta, a.cert != nullptr, 0.0};
   if (item < a.n_items)
     spmm_item<float, W, false>(a.items[item], a.rp, a.ci, a.z_cur + off,
                                a.split_part + (size_t)t * a.n_split * W,
@@ -544,7 +553,7 @@ hipError_t init_tile_from_r(const cpaa_plan_s* pl, Workspace& ws, const int* act
 }
 
 hipError_t term_tile(const cpaa_plan_s* pl, Workspace& ws, int cur, int prev, int next, bool first,
-                     double a_next, double* cert_slot, const int* done, hipStream_t st) {
+                     const AccUpdate& au, double* cert_slot, const int* done, hipStream_t st) {
   TileTermArgs a;
   a.rp = pl->d_row_ptr;
   a.ci = pl->d_col_idx;
@@ -557,7 +566,7 @@ hipError_t term_tile(const cpaa_plan_s* pl, Workspace& ws, int cur, int prev, in
   a.acc = ws.acc;
   a.alpha = first ? 1.f : 2.f;
   a.gamma = first ? 0.f : 1.f;
-  a.a_next = a_next;
+  a.au = au;
   a.beta = pl->beta;
   a.cert = cert_slot;
   a.cols = ws.cols;

@@ -3,6 +3,8 @@
 // Hot loop (Alg. 1, Sec. 4.1, in z-space z_k = D^{-1} T_k(P) b):
 //     z_{k+1}(u) = 2 * (sum_{v in N(u)} z_k(v)) / d_u - z_{k-1}(u)
 //     acc(u)    += c_{k+1} * z_{k+1}(u)                     (FP64)
+// (before the first stopping check one launch in three adds the three newest
+// terms at once, from the z_{k-1} and z_k it reads anyway: AccUpdate)
 // so the SpMV runs on the 0/1 pattern A and the D^{-1} scaling, the
 // three-term update, the weighted accumulation and the certificate partial
 // d_u |z_{k+1}(u) - beta z_k(u)| all sit in the epilogue of one kernel.
@@ -151,17 +153,27 @@ struct TermEpi {
   float* __restrict__ zn;
   double* __restrict__ acc;
   float alpha, gamma;
-  double a_next, beta;
+  AccUpdate au;
+  double beta;
   int want_cert;
   double cert;
   __device__ __forceinline__ void row(int r, int d, float s, float) {
     float y = alpha * (s / static_cast<float>(d));
-    if (gamma != 0.f) y -= gamma * zp[r];
+    float p = 0.f, c = 0.f;
+    if (gamma != 0.f || au.a_prev != 0.0) p = zp[r];
+    if (gamma != 0.f) y -= gamma * p;
     zn[r] = y;
-    acc[r] += a_next * static_cast<double>(y);
+    if (want_cert || au.a_cur != 0.0) c = zc[r];
+    if (au.on) {
+      // the newest (smallest) term first
+      double add = au.a_next * static_cast<double>(y);
+      if (au.a_cur != 0.0) add += au.a_cur * static_cast<double>(c);
+      if (au.a_prev != 0.0) add += au.a_prev * static_cast<double>(p);
+      acc[r] += add;
+    }
     if (want_cert)
       cert += static_cast<double>(d) *
-              fabs(static_cast<double>(y) - beta * static_cast<double>(zc[r]));
+              fabs(static_cast<double>(y) - beta * static_cast<double>(c));
   }
 };
 
@@ -174,7 +186,8 @@ struct TermArgs {
   float* zn;
   double* acc;
   float alpha, gamma;
-  double a_next, beta;
+  AccUpdate au;
+  double beta;
   double* cert;          // [kSlots] or null
   const int* done;       // stop flag or null
   float* split_part;
@@ -187,7 +200,7 @@ template <int NPT>
 __global__ __launch_bounds__(kWG) void k_term_w1(TermArgs a) {
   if (a.done != nullptr && *a.done) return;
   const int lb = xcd_logical(blockIdx.x, gridDim.x, a.xcd);
-  TermEpi epi{a.zc, a.zp, a.zn, a.acc, a.alpha, a.gamma, a.a_next, a.beta,
+  TermEpi epi{a.zc, a.zp, a.zn, a.acc, a.alpha, a.gamma, a.au, a.beta,
               a.cert != nullptr, 0.0};
   spmv_item<float, NPT, false>(a.items[lb], a.rp, a.ci, a.zc, a.split_part, a.split_count,
                         a.split_nchunks, epi);
@@ -323,7 +336,8 @@ struct CombineArgs {
   float* zn;
   double* acc;
   float alpha, gamma;
-  double a_next, beta;
+  AccUpdate au;
+  double beta;
   double* cert;
   const int* done;
   int n;
@@ -331,7 +345,7 @@ struct CombineArgs {
 
 __global__ __launch_bounds__(kWG) void k_combine_w1(CombineArgs a) {
   if (a.done != nullptr && *a.done) return;
-  TermEpi epi{a.zc, a.zp, a.zn, a.acc, a.alpha, a.gamma, a.a_next, a.beta,
+  TermEpi epi{a.zc, a.zp, a.zn, a.acc, a.alpha, a.gamma, a.au, a.beta,
               a.cert != nullptr, 0.0};
   const size_t n = static_cast<size_t>(a.n);
   for (int u = blockIdx.x * kWG + threadIdx.x; u < a.n; u += gridDim.x * kWG) {
@@ -494,7 +508,7 @@ hipError_t load_x0_w1(const cpaa_plan_s* pl, Workspace& ws, const double* x0, hi
 }
 
 hipError_t term_w1(const cpaa_plan_s* pl, Workspace& ws, int cur, int prev, int next, bool first,
-                   double a_next, double* cert_slot, const int* done, hipStream_t st) {
+                   const AccUpdate& au, double* cert_slot, const int* done, hipStream_t st) {
   if (pl->sliced) {
     SlicedArgs s;
     s.entries = pl->slc.d_entries;
@@ -525,7 +539,7 @@ hipError_t term_w1(const cpaa_plan_s* pl, Workspace& ws, int cur, int prev, int 
     c.acc = ws.acc;
     c.alpha = first ? 1.f : 2.f;
     c.gamma = first ? 0.f : 1.f;
-    c.a_next = a_next;
+    c.au = au;
     c.beta = pl->beta;
     c.cert = cert_slot;
     c.done = done;
@@ -543,7 +557,7 @@ hipError_t term_w1(const cpaa_plan_s* pl, Workspace& ws, int cur, int prev, int 
   a.acc = ws.acc;
   a.alpha = first ? 1.f : 2.f;
   a.gamma = first ? 0.f : 1.f;
-  a.a_next = a_next;
+  a.au = au;
   a.beta = pl->beta;
   a.cert = cert_slot;
   a.done = done;

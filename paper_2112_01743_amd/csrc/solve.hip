@@ -168,8 +168,36 @@ struct TermTimer {
   }
 };
 
-using TermFn = hipError_t (*)(const cpaa_plan_s*, Workspace&, int, int, int, bool, double,
+using TermFn = hipError_t (*)(const cpaa_plan_s*, Workspace&, int, int, int, bool,
+                              const AccUpdate&,
                               double*, const int*, hipStream_t);
+
+// Accumulator updates of launches 0..k_cap-1 (launch k produces z_{k+1} and
+// owes c_{k+1} z_{k+1}).  No stop can happen at a launch without a check
+// (k < k_min), and an unstopped launch is always followed by the next one, so
+// such launches may leave their term to a later launch: in groups of three
+// (off, off, on with c_{k-1}, c_k, c_{k+1}) or two, where the last launch of a
+// group may itself be checked.  From k_min on every launch adds its own term.
+std::vector<AccUpdate> acc_schedule(const std::vector<double>& ck, int k_cap, int k_min) {
+  std::vector<AccUpdate> plan(std::max(k_cap, 0), AccUpdate{0.0, 0.0, 0.0, 1});
+  int k = 0;
+  while (k < k_cap) {
+    if (k + 1 < k_min && k + 2 < k_cap) {
+      plan[k].on = 0;
+      plan[k + 1].on = 0;
+      plan[k + 2] = AccUpdate{ck[k + 1], ck[k + 2], ck[k + 3], 1};
+      k += 3;
+    } else if (k < k_min && k + 1 < k_cap) {
+      plan[k].on = 0;
+      plan[k + 1] = AccUpdate{0.0, ck[k + 1], ck[k + 2], 1};
+      k += 2;
+    } else {
+      plan[k] = AccUpdate{0.0, 0.0, ck[k + 1], 1};
+      k += 1;
+    }
+  }
+  return plan;
+}
 
 // Launch terms 1..k_cap of a series whose init already ran.  Returns after
 // enqueueing; the stop flag / term count live in ws.done / ws.terms.  With
@@ -182,12 +210,13 @@ cpaa_status run_series(cpaa_plan_s* pl, Workspace& ws, TermFn term, int series_i
   CPAA_HIP(init_done(ws, active, st));
   CPAA_HIP(fill_i32(ws.terms, k_cap, ws.tiles, st));
   CPAA_HIP(fill_f64(ws.series_cert, -1.0, cols, st));
+  const std::vector<AccUpdate> acc_plan = acc_schedule(pl->ck, k_cap, k_min);
   for (int k = 0; k < k_cap; ++k) {
     // this launch produces z_{k+1}; its certificate is that of x_k
     double* cert = (k >= k_min) ? ws.slots + (size_t)k * kSlots * cols : nullptr;
     const int* done = (active != nullptr || (k >= 1 && k - 1 >= k_min)) ? ws.done : nullptr;
     CPAA_HIP(timer.before(series_id, k + 1, st));
-    CPAA_HIP(term(pl, ws, k % 3, (k + 2) % 3, (k + 1) % 3, k == 0, pl->ck[k + 1], cert, done, st));
+    CPAA_HIP(term(pl, ws, k % 3, (k + 2) % 3, (k + 1) % 3, k == 0, acc_plan[k], cert, done, st));
     CPAA_HIP(timer.after(st));
     if (cert) {
       const double scale = (1.0 + pl->s) / pl->s * std::pow(pl->beta, k + 1) / (1.0 - pl->c);
@@ -204,7 +233,8 @@ float time_terms(cpaa_plan_s* pl, Workspace& ws, TermFn term, int reps, hipStrea
                  hipError_t* err) {
   *err = hipEventRecord(pl->ev_begin, st);
   for (int k = 0; k < reps && *err == hipSuccess; ++k)
-    *err = term(pl, ws, k % 3, (k + 2) % 3, (k + 1) % 3, k == 0, 0.0, nullptr, nullptr, st);
+    *err = term(pl, ws, k % 3, (k + 2) % 3, (k + 1) % 3, k == 0, AccUpdate{0.0, 0.0, 0.0, 1},
+                nullptr, nullptr, st);
   if (*err == hipSuccess) *err = hipEventRecord(pl->ev_end, st);
   if (*err == hipSuccess) *err = hipEventSynchronize(pl->ev_end);
   float ms = 0.f;
