@@ -57,15 +57,15 @@ def mass_rule_terms(c: float, target: float) -> int:
 
 
 def acc_launches(launches: int, k_min: int) -> int:
-    """How many of a series' first `launches` term launches read and write the
-    FP64 accumulator: launches before the first check (k < k_min) are grouped in
-    threes (or a final two) whose last launch adds all of the group's terms;
-    from k_min on every launch adds its own."""
+    """How many of a series' `launches` term launches read and write the FP64
+    accumulator: launches before the first check (k + 1 < k_min) are grouped in
+    threes, the rest in pairs, and the last launch of a group adds all of the
+    group's terms (the series' last launch is counted as one that does)."""
     on, k = 0, 0
     while k < launches:
         if k + 1 < k_min and k + 2 < launches:
             k += 3
-        elif k < k_min and k + 1 < launches:
+        elif k + 1 < launches:
             k += 2
         else:
             k += 1

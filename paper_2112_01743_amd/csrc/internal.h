@@ -193,9 +193,9 @@ hipError_t collapse_stats(Workspace& ws, hipStream_t st);
 // What one term launch (producing z_{k+1}) adds to the FP64 accumulator:
 //     on:  acc += a_prev z_{k-1} + a_cur z_k + a_next z_{k+1}
 //     off: nothing (a later launch of the same series adds it).
-// Launches before the first stopping check may leave the update to the next
-// one or two launches, whose epilogues still hold z_{k-1} and z_k: three
-// terms then cost one read-modify-write of acc instead of three.
+// A launch may leave its update to the next one or two launches, whose
+// epilogues still hold z_{k-1} and z_k: two or three terms then cost one
+// read-modify-write of acc.
 struct AccUpdate {
   double a_prev, a_cur, a_next;
   int on;

@@ -3,8 +3,8 @@
 // Hot loop (Alg. 1, Sec. 4.1, in z-space z_k = D^{-1} T_k(P) b):
 //     z_{k+1}(u) = 2 * (sum_{v in N(u)} z_k(v)) / d_u - z_{k-1}(u)
 //     acc(u)    += c_{k+1} * z_{k+1}(u)                     (FP64)
-// (before the first stopping check one launch in three adds the three newest
-// terms at once, from the z_{k-1} and z_k it reads anyway: AccUpdate)
+// (one launch in two or three adds the newest terms at once, from the z_{k-1}
+// and z_k it reads anyway: AccUpdate)
 // so the SpMV runs on the 0/1 pattern A and the D^{-1} scaling, the
 // three-term update, the weighted accumulation and the certificate partial
 // d_u |z_{k+1}(u) - beta z_k(u)| all sit in the epilogue of one kernel.

@@ -173,11 +173,14 @@ using TermFn = hipError_t (*)(const cpaa_plan_s*, Workspace&, int, int, int, boo
                               double*, const int*, hipStream_t);
 
 // Accumulator updates of launches 0..k_cap-1 (launch k produces z_{k+1} and
-// owes c_{k+1} z_{k+1}).  No stop can happen at a launch without a check
-// (k < k_min), and an unstopped launch is always followed by the next one, so
-// such launches may leave their term to a later launch: in groups of three
-// (off, off, on with c_{k-1}, c_k, c_{k+1}) or two, where the last launch of a
-// group may itself be checked.  From k_min on every launch adds its own term.
+// owes c_{k+1} z_{k+1}).  A launch may leave its term to a later launch of
+// the same series, whose epilogue still holds z_{k-1} and z_k:
+//  * before the first check (k + 1 < k_min) in groups of three: off, off, on
+//    with c_{k-1}, c_k, c_{k+1}; no stop can happen inside such a group;
+//  * otherwise in pairs: off, on with c_k, c_{k+1}.  The off launch follows an
+//    on launch, so acc holds exactly x_k = sum_{i<=k} c_i z_i when the off
+//    launch's check certifies x_k; if the series stops there, the pending
+//    term (beyond the certified x_k) is dropped.
 std::vector<AccUpdate> acc_schedule(const std::vector<double>& ck, int k_cap, int k_min) {
   std::vector<AccUpdate> plan(std::max(k_cap, 0), AccUpdate{0.0, 0.0, 0.0, 1});
   int k = 0;
@@ -187,7 +190,7 @@ std::vector<AccUpdate> acc_schedule(const std::vector<double>& ck, int k_cap, in
       plan[k + 1].on = 0;
       plan[k + 2] = AccUpdate{ck[k + 1], ck[k + 2], ck[k + 3], 1};
       k += 3;
-    } else if (k < k_min && k + 1 < k_cap) {
+    } else if (k + 1 < k_cap) {
       plan[k].on = 0;
       plan[k + 1] = AccUpdate{0.0, ck[k + 1], ck[k + 2], 1};
       k += 2;
