@@ -35,11 +35,13 @@ METRIC = "GTEPS (nnz·terms/s) + PPR solves/s at ≤1e-6 L1, warm-start vs plain
 HBM_PEAK_GBS = 8000.0
 CSRC = os.path.join(ROOT, "paper_2112_01743_amd", "csrc")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "term_chung_lu_n4m_traffic.json")
-# sources that decide what the term kernels do (kernels, shared headers, the plan builder)
-KERNEL_SRC = [os.path.join(CSRC, f) for f in ("kernels_w1.hip", "internal.h", "device.h", "api.hip")]
+# sources that decide what the term kernels do (kernels, shared headers, the plan builder,
+# the series driver that schedules the accumulator updates)
+KERNEL_SRC = [os.path.join(CSRC, f)
+              for f in ("kernels_w1.hip", "internal.h", "device.h", "api.hip", "solve.hip")]
 TILE_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "term_tile_grid_256_traffic.json")
 TILE_KERNEL_SRC = [os.path.join(CSRC, f)
-                   for f in ("kernels_tile.hip", "internal.h", "device.h", "api.hip")]
+                   for f in ("kernels_tile.hip", "internal.h", "device.h", "api.hip", "solve.hip")]
 
 
 def log(msg):
