@@ -265,6 +265,24 @@ def perturbed_grid(side: int, delete_frac: float, shortcut_frac: float, seed,
     return g
 
 
+def delaunay(n: int, seed) -> CSR:
+    """Delaunay triangulation of n uniform random points in the unit square
+    (the construction of the delaunay_n* graphs: average degree just under 6,
+    a planar mesh).  Vertices in the order the points were drawn."""
+    from scipy.spatial import Delaunay
+    rng = philox(seed)
+    pts = rng.random((n, 2))
+    tri = Delaunay(pts).simplices.astype(np.int64)
+    del pts
+    u = np.concatenate([tri[:, 0], tri[:, 1], tri[:, 2]])
+    v = np.concatenate([tri[:, 1], tri[:, 2], tri[:, 0]])
+    del tri
+    g = csr_from_edges(n, u, v)
+    g, _ = drop_isolated(g)
+    g.meta.update(model="delaunay")
+    return g
+
+
 def uneven_batch(num_graphs: int, seed, n_lo: int = 100, n_hi: int = 5000,
                  deg_lo: float = 4.0, deg_hi: float = 32.0, gamma_lo: float = 2.1,
                  gamma_hi: float = 3.0) -> CSR:

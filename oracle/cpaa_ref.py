@@ -40,7 +40,7 @@ __all__ = [
     "convergence_rate", "mass_error", "accumulated_mass", "total_mass",
     "series_tail", "terms_for_mass_error", "apriori_error_bound", "terms_for_apriori",
     "adjacency", "transition_matrix", "transition_dense", "pagerank_exact",
-    "pagerank_power", "cpaa", "cpaa_alg1_global", "residual", "residual_l1_bound",
+    "pagerank_power", "power_method", "cpaa", "cpaa_alg1_global", "residual", "residual_l1_bound",
     "series_residual", "l1_error", "max_error", "max_relative_error",
 ]
 
@@ -167,6 +167,26 @@ def pagerank_exact(g, p: np.ndarray, c: float) -> np.ndarray:
     """
     P = transition_dense(g)
     return np.linalg.solve(np.eye(g.n) - c * P, (1.0 - c) * np.asarray(p, dtype=np.float64))
+
+
+def power_method(g, p: np.ndarray, c: float, t: int, return_all: bool = False):
+    """The power method of the comparison in Sec. 5: PageRank as the fixed point
+    pi = P'' pi (eq. 2.1), iterated t times from x_0 = p.
+
+    P'' = cP' + (1-c) p e^T with P' = P for an undirected graph (no dangling
+    vertices), applied here as written: x_{k+1} = cPx_k + (1-c) p (e^T x_k).
+    The paper does not give the start; p (the distribution the definition is
+    built from) is the reading taken.  Returns x_t, or the list x_0..x_t with
+    ``return_all``.
+    """
+    P = transition_matrix(g)
+    p = np.asarray(p, dtype=np.float64)
+    x = p.copy()
+    seq = [x]
+    for _ in range(t):
+        x = c * (P @ x) + (1.0 - c) * p * x.sum(axis=0)
+        seq.append(x)
+    return seq if return_all else x
 
 
 def pagerank_power(g, p: np.ndarray, c: float, tol: float = 1e-13,
