@@ -191,6 +191,77 @@ def bench_grid_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_table3(args):
+    """Table 3 on a synthetic stand-in for delaunay-n21: the Delaunay triangulation
+    of 2^21 uniform random points (seed 2112010), global PageRank, c = 0.85.
+    Rounds and time to ERR < 1e-3 (max relative error against the exact PageRank,
+    Sec. 5) for CPAA and for the power method (eq. 2.1 iterated from p) on the same
+    kernels, and both methods certified to 1e-6 in L1.  The reference PageRank is a
+    CPAA solve certified to 1e-12 in L1."""
+    import torch
+    import graphgen as gg
+    from paper_2112_01743_amd import Plan
+    c = 0.85
+    t0 = time.perf_counter()
+    g = gg.delaunay(1 << 21, seed=2112010)
+    log(f"graph n={g.n} nnz={g.nnz} ({time.perf_counter() - t0:.1f} s)")
+    p = torch.full((g.n,), 1.0 / g.n, dtype=torch.float64, device="cuda")
+    x = torch.empty_like(p)
+    plan = Plan.from_graph(g, c, time_kernels=1)
+    pi, rep = plan.solve(p, 1e-12)
+    pi = pi.clone()
+    assert rep["certified"] == 1, rep
+
+    def err(v):
+        return float(torch.max(torch.abs(v - pi) / pi))
+
+    def rounds(method, lo, hi):
+        for k in range(lo, hi):
+            pk = Plan.from_graph(g, c, k_max=k, max_refine=0, time_kernels=1)
+            getattr(pk, method)(p, 1e-15, out=x)
+            e = err(x)
+            log(f"{method} k={k} ERR={e:.3e}")
+            if e < 1e-3:
+                return k, pk
+        raise RuntimeError(f"{method}: ERR >= 1e-3 after {hi - 1} rounds")
+
+    def timed(pk, method, tol):
+        for _ in range(2):
+            getattr(pk, method)(p, tol, out=x)
+        torch.cuda.synchronize()
+        reps = []
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            reps.append(getattr(pk, method)(p, tol, out=x)[1])
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t1) * 1e3 / args.steps
+        r = reps[-1]
+        return {"ms": ms, "terms": r["terms"] + r["refine_terms"],
+                "ms_per_term": r["ms_terms"] / max(r["term_launches"], 1),
+                "gteps": r["edges"] / (ms / 1e3) / 1e9, "certified": r["certified"],
+                "cert_bound": r["cert_bound"]}
+
+    k_c, plan_c = rounds("solve", 8, 30)
+    k_p, plan_p = rounds("solve_power", 8, 80)
+    at_1e3 = {"cpaa": dict(rounds=k_c, **timed(plan_c, "solve", 1e-15)),
+              "power": dict(rounds=k_p, **timed(plan_p, "solve_power", 1e-15))}
+    cert = {"cpaa": timed(plan, "solve", args.tol), "power": timed(plan, "solve_power", args.tol)}
+    out = {"metric": METRIC, "value": 1e3 / at_1e3["cpaa"]["ms"], "unit": "solves/s", "n_gpus": 1,
+           "steps": args.steps, "higher_is_better": True,
+           "dtype": "f32 recurrence, f64 accumulation", "data": "synthetic",
+           "config": {"workload": "table3_delaunay_n21_standin", "n": g.n, "nnz": g.nnz,
+                      "seed": 2112010, "c": c, "personalization": "uniform",
+                      "reference": "CPAA certified to 1e-12 L1"},
+           "err_below_1e-3": at_1e3,
+           "speedup_at_err_1e-3": at_1e3["power"]["ms"] / at_1e3["cpaa"]["ms"],
+           "certified_l1": {"tol": args.tol, **cert},
+           "speedup_certified": cert["power"]["ms"] / cert["cpaa"]["ms"],
+           "paper_delaunay_n21": {"cpaa_rounds": 12, "power_rounds": 20, "cpaa_s": 1.111,
+                                  "mpi_s": 1.854, "spi_s": 20.175,
+                                  "hardware": "Xeon Silver 4210R, 38 threads, FP64"}}
+    print(json.dumps(out), flush=True)
+
+
 def bench_graph_batch(args):
     """10,000 independent Chung-Lu graphs (n log-uniform in [100, 5000], average
     degree 4-32, exponent 2.1-3.0, seed 2112003), one random source each, solved
@@ -258,11 +329,12 @@ def main():
                     help="0 auto (column-sliced on this graph), 1 off, 8 on")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="chung_lu",
-                    choices=["chung_lu", "grid_batched", "graph_batch"],
+                    choices=["chung_lu", "grid_batched", "graph_batch", "table3"],
                     help="chung_lu: global PageRank on the 4M-vertex power-law graph (default); "
                          "grid_batched: 256 single-source solves on the 1000x1000 perturbed "
                          "lattice in one batched call; graph_batch: 10,000 small Chung-Lu graphs "
-                         "in one persistent launch")
+                         "in one persistent launch; table3: rounds and time to ERR < 1e-3 "
+                         "for CPAA and the power method on a Delaunay stand-in for delaunay-n21")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters against a known byte count)")
@@ -286,6 +358,8 @@ def main():
         return bench_grid_batched(args)
     if args.workload == "graph_batch":
         return bench_graph_batch(args)
+    if args.workload == "table3":
+        return bench_table3(args)
 
     import torch
     import graphgen as gg

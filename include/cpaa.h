@@ -109,6 +109,14 @@ typedef struct {
                              and max degree >= 16 x average degree.  Needs one graph and
                              n < 8 (2^21 - 16) (else CPAA_EINVAL).  Inputs and outputs keep the caller's
                              labels. */
+  int32_t locality_order; /* single-vector path without column slices: 0 auto, 1 off (caller's
+                             labels), 2 reverse Cuthill-McKee.  RCM relabels the vertices by a
+                             breadth-first order from a pseudo-peripheral vertex, so that on
+                             mesh-like graphs the columns of neighbouring rows are close and a
+                             term's gathers stay in L2.  Auto: for one graph with n >= 2^18
+                             whose stored entries span more than 2^14 labels on average, if RCM
+                             shortens that mean span at least 8x.  Inputs and outputs keep the
+                             caller's labels. */
 } cpaa_opts;
 
 /* Per-solve report (one per right-hand side in batched calls, one per graph in
@@ -136,7 +144,8 @@ typedef struct {
   int32_t n;
   int64_t nnz;
   int32_t num_graphs;
-  int32_t reordered;        /* 1 if the single-vector path relabelled the vertices */
+  int32_t reordered;        /* single-vector labelling: 0 the caller's, 1 column slices (degree
+                               rank), 2 reverse Cuthill-McKee */
   int32_t max_degree;
   int32_t split_rows;       /* rows split across workgroups */
   int32_t nnz_per_thread;   /* single-vector work item size / 256 */
@@ -198,6 +207,31 @@ CPAA_API cpaa_status cpaa_solve(cpaa_plan_t plan, const double* p, double tol, c
 CPAA_API cpaa_status cpaa_solve_batched(cpaa_plan_t plan, int32_t B, const double* P, int64_t ldp,
                                double tol, const double* X0, int64_t ldx0, double* X,
                                int64_t ldx, cpaa_report* reps, void* stream);
+
+/* The power method on the same plan and kernels, the baseline the paper
+ * compares CPAA with (Sec. 5, Table 3).  PageRank is the fixed point of
+ * pi = P''pi (eq. 2.1); for an undirected graph this is the iteration
+ *     x_{t+1} = c P x_t + (1-c) p,    x_0 = p,
+ * whose iterates stay distributions and whose error shrinks by c per step.
+ * The library sums it as x_0 plus its increments x_{t+1} - x_t = (cP)^t
+ * (x_1 - x_0): FP32 increments, FP64 sum, stopped when the FP64 norm of the
+ * next increment (the residual of the current iterate) certifies
+ * ||x_t - pi||_1 <= tol/2, then the same FP64 residual check and corrections
+ * as cpaa_solve (a correction runs the iteration on b = r from x_0 = r/(1-c)).
+ * report.terms counts power-method steps (one SpMV each).  With
+ * opts.k_max = t, opts.max_refine = 0 and a tolerance that cannot be met the
+ * output is the t-th iterate x_t itself (and CPAA_ENOCONV is returned).
+ * Arguments, validation, x0 handling, ownership and errors as cpaa_solve. */
+CPAA_API cpaa_status cpaa_solve_power(cpaa_plan_t plan, const double* p, double tol,
+                                      const double* x0, double* x, cpaa_report* rep,
+                                      void* stream);
+
+/* B power-method solves at once, as cpaa_solve_batched (tiles of columns, one
+ * SpMM kernel per step, per-column certificates and reports). */
+CPAA_API cpaa_status cpaa_solve_power_batched(cpaa_plan_t plan, int32_t B, const double* P,
+                                              int64_t ldp, double tol, const double* X0,
+                                              int64_t ldx0, double* X, int64_t ldx,
+                                              cpaa_report* reps, void* stream);
 
 /* Block-diagonal plan (num_graphs > 1): solve every graph for its own
  * personalization in one persistent kernel launch (one workgroup per graph at

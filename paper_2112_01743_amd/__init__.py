@@ -8,8 +8,8 @@ library is missing, ``binding.lib()`` raises.
 """
 from .binding import (CpaaError, Plan, cpaa_default_opts, cpaa_last_error, cpaa_plan,  # noqa: F401
                       cpaa_plan_destroy, cpaa_plan_info_get, cpaa_solve, cpaa_solve_batched,
-                      cpaa_solve_graphs, lib)
+                      cpaa_solve_graphs, cpaa_solve_power, cpaa_solve_power_batched, lib)
 
 __all__ = ["Plan", "CpaaError", "lib", "cpaa_default_opts", "cpaa_last_error", "cpaa_plan",
            "cpaa_plan_destroy", "cpaa_plan_info_get", "cpaa_solve", "cpaa_solve_batched",
-           "cpaa_solve_graphs"]
+           "cpaa_solve_graphs", "cpaa_solve_power", "cpaa_solve_power_batched"]

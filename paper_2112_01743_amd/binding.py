@@ -37,7 +37,7 @@ class cpaa_opts(ctypes.Structure):
                 ("tile_w", ctypes.c_int32), ("validate", ctypes.c_int32),
                 ("io_device", ctypes.c_int32), ("time_kernels", ctypes.c_int32),
                 ("xcd_remap", ctypes.c_int32), ("autotune", ctypes.c_int32),
-                ("column_slices", ctypes.c_int32)]
+                ("column_slices", ctypes.c_int32), ("locality_order", ctypes.c_int32)]
 
 
 class cpaa_report(ctypes.Structure):
@@ -94,6 +94,11 @@ def lib() -> ctypes.CDLL:
     L.cpaa_solve_batched.argtypes = [vp, i32, vp, i64, dbl, vp, i64, vp, i64,
                                      ctypes.POINTER(cpaa_report), vp]
     L.cpaa_solve_batched.restype = ctypes.c_int
+    L.cpaa_solve_power.argtypes = [vp, vp, dbl, vp, vp, ctypes.POINTER(cpaa_report), vp]
+    L.cpaa_solve_power.restype = ctypes.c_int
+    L.cpaa_solve_power_batched.argtypes = [vp, i32, vp, i64, dbl, vp, i64, vp, i64,
+                                           ctypes.POINTER(cpaa_report), vp]
+    L.cpaa_solve_power_batched.restype = ctypes.c_int
     L.cpaa_solve_graphs.argtypes = [vp, vp, dbl, vp, ctypes.POINTER(cpaa_report), vp]
     L.cpaa_solve_graphs.restype = ctypes.c_int
     L.cpaa_last_error.argtypes = []
@@ -182,6 +187,23 @@ def cpaa_solve_batched(plan, B: int, P_ptr: int, ldp: int, tol: float, X0_ptr: i
     return st, reps
 
 
+def cpaa_solve_power(plan, p_ptr: int, tol: float, x0_ptr: int | None, x_ptr: int,
+                     stream: int = 0) -> tuple[int, cpaa_report]:
+    rep = cpaa_report()
+    st = lib().cpaa_solve_power(plan, p_ptr, tol, x0_ptr, x_ptr, ctypes.byref(rep),
+                                stream or None)
+    return st, rep
+
+
+def cpaa_solve_power_batched(plan, B: int, P_ptr: int, ldp: int, tol: float,
+                             X0_ptr: int | None, ldx0: int, X_ptr: int, ldx: int,
+                             stream: int = 0):
+    reps = (cpaa_report * B)()
+    st = lib().cpaa_solve_power_batched(plan, B, P_ptr, ldp, tol, X0_ptr, ldx0, X_ptr, ldx,
+                                        reps, stream or None)
+    return st, reps
+
+
 def cpaa_solve_graphs(plan, p_ptr: int, tol: float, x_ptr: int, num_graphs: int,
                       stream: int = 0):
     reps = (cpaa_report * num_graphs)()
@@ -263,34 +285,52 @@ class Plan:
     def info(self) -> dict:
         return cpaa_plan_info_get(self.handle).as_dict()
 
-    def solve(self, p, tol: float = 1e-6, x0=None, out=None, stream=None, check=True):
-        """p: (n,) float64 HIP tensor.  Returns (x, report dict)."""
+    def _single(self, fn, name, p, tol, x0, out, stream, check):
         import torch
         if out is None:
             out = torch.empty_like(p)
-        st, rep = cpaa_solve(self.handle, p.data_ptr(), tol,
-                             None if x0 is None else x0.data_ptr(), out.data_ptr(),
-                             _stream_handle(stream))
+        st, rep = fn(self.handle, p.data_ptr(), tol, None if x0 is None else x0.data_ptr(),
+                     out.data_ptr(), _stream_handle(stream))
         if check and st not in (CPAA_OK, CPAA_ENOCONV):
-            raise CpaaError(st, "cpaa_solve")
+            raise CpaaError(st, name)
         d = rep.as_dict()
         d["status"] = STATUS.get(st, st)
         return out, d
 
-    def solve_batched(self, P, tol: float = 1e-6, X0=None, out=None, stream=None, check=True):
-        """P: (B, n) float64 HIP tensor, row j = personalization j.  Returns (X, reports):
-        reports is a numpy structured array with one cpaa_report record per column."""
+    def _batched(self, fn, name, P, tol, X0, out, stream, check):
         import torch
         B = int(P.shape[0])
         if out is None:
             out = torch.empty_like(P)
-        st, reps = cpaa_solve_batched(self.handle, B, P.data_ptr(), _ld(P, self.n), tol,
-                                      None if X0 is None else X0.data_ptr(),
-                                      _ld(X0, self.n) if X0 is not None else self.n,
-                                      out.data_ptr(), _ld(out, self.n), _stream_handle(stream))
+        st, reps = fn(self.handle, B, P.data_ptr(), _ld(P, self.n), tol,
+                      None if X0 is None else X0.data_ptr(),
+                      _ld(X0, self.n) if X0 is not None else self.n,
+                      out.data_ptr(), _ld(out, self.n), _stream_handle(stream))
         if check and st not in (CPAA_OK, CPAA_ENOCONV):
-            raise CpaaError(st, "cpaa_solve_batched")
+            raise CpaaError(st, name)
         return out, _report_records(reps)
+
+    def solve(self, p, tol: float = 1e-6, x0=None, out=None, stream=None, check=True):
+        """p: (n,) float64 HIP tensor.  Returns (x, report dict)."""
+        return self._single(cpaa_solve, "cpaa_solve", p, tol, x0, out, stream, check)
+
+    def solve_power(self, p, tol: float = 1e-6, x0=None, out=None, stream=None, check=True):
+        """The power method (x <- cPx + (1-c)p from x = p) on the same plan and kernels;
+        arguments and result as solve; report["terms"] counts power steps."""
+        return self._single(cpaa_solve_power, "cpaa_solve_power", p, tol, x0, out, stream,
+                            check)
+
+    def solve_batched(self, P, tol: float = 1e-6, X0=None, out=None, stream=None, check=True):
+        """P: (B, n) float64 HIP tensor, row j = personalization j.  Returns (X, reports):
+        reports is a numpy structured array with one cpaa_report record per column."""
+        return self._batched(cpaa_solve_batched, "cpaa_solve_batched", P, tol, X0, out, stream,
+                             check)
+
+    def solve_power_batched(self, P, tol: float = 1e-6, X0=None, out=None, stream=None,
+                            check=True):
+        """B power-method solves at once; arguments and result as solve_batched."""
+        return self._batched(cpaa_solve_power_batched, "cpaa_solve_power_batched", P, tol, X0,
+                             out, stream, check)
 
     def solve_graphs(self, p, tol: float = 1e-6, out=None, stream=None, check=True):
         """p: (n,) float64 HIP tensor of concatenated per-graph personalizations.  Returns

@@ -187,6 +187,93 @@ void parallel_for(int64_t count, F body) {
   for (std::thread& th : pool) th.join();
 }
 
+// The CSR of the same graph under new labels: perm[new] = old; columns sorted.
+void relabel_csr(int32_t n, const int32_t* rp, const int32_t* ci, const std::vector<int32_t>& perm,
+                 std::vector<int32_t>& rp2, std::vector<int32_t>& ci2) {
+  std::vector<int32_t> new_of(n);
+  for (int32_t u = 0; u < n; ++u) new_of[perm[u]] = u;
+  rp2.assign(static_cast<size_t>(n) + 1, 0);
+  for (int32_t u = 0; u < n; ++u) rp2[u + 1] = rp2[u] + (rp[perm[u] + 1] - rp[perm[u]]);
+  ci2.resize(static_cast<size_t>(rp2[n]));
+  parallel_for(n, [&](int64_t u) {
+    const int32_t v = perm[u];
+    int32_t* dst = ci2.data() + rp2[u];
+    for (int32_t j = rp[v]; j < rp[v + 1]; ++j) *dst++ = new_of[ci[j]];
+    std::sort(ci2.data() + rp2[u], dst);
+  });
+}
+
+// Mean distance |u - v| between the labels of a stored entry's row and column:
+// how far apart in the vector the gathers of neighbouring rows fall.
+double mean_span(int32_t n, const int32_t* rp, const int32_t* ci) {
+  double sum = 0.0;
+  for (int32_t u = 0; u < n; ++u)
+    for (int32_t j = rp[u]; j < rp[u + 1]; ++j) sum += std::abs(static_cast<double>(ci[j] - u));
+  return rp[n] > 0 ? sum / rp[n] : 0.0;
+}
+
+// Reverse Cuthill-McKee order, perm[new] = old (Cuthill and McKee 1969, reversed
+// as George proposed): per connected component a breadth-first search from a
+// pseudo-peripheral vertex (George and Liu's iteration: from a vertex of least
+// degree, restart from a least-degree vertex of the deepest level while the
+// depth grows) that appends each vertex's unvisited neighbours in increasing
+// degree; the whole sequence is then reversed.  Neighbouring vertices get
+// nearby labels on mesh-like graphs, so a term's gathers stay local.
+void rcm_order(int32_t n, const int32_t* rp, const int32_t* ci, std::vector<int32_t>& perm) {
+  auto deg = [&](int32_t v) { return rp[v + 1] - rp[v]; };
+  std::vector<int32_t> by_deg(n);
+  for (int32_t v = 0; v < n; ++v) by_deg[v] = v;
+  std::stable_sort(by_deg.begin(), by_deg.end(),
+                   [&](int32_t a, int32_t b) { return deg(a) < deg(b); });
+  std::vector<char> placed(n, 0);
+  std::vector<int32_t> dist(n, -1), seen;
+  std::vector<int32_t> order, nb;
+  order.reserve(n);
+  for (int32_t s0 : by_deg) {
+    if (placed[s0]) continue;
+    int32_t root = s0;
+    int depth = -1;
+    for (int it = 0; it < 8; ++it) {
+      // levels of a breadth-first search from root; every vertex of the
+      // component is reached (the component holds no placed vertex yet)
+      seen.clear();
+      seen.push_back(root);
+      dist[root] = 0;
+      for (size_t h = 0; h < seen.size(); ++h) {
+        const int32_t v = seen[h];
+        for (int32_t j = rp[v]; j < rp[v + 1]; ++j)
+          if (dist[ci[j]] < 0) {
+            dist[ci[j]] = dist[v] + 1;
+            seen.push_back(ci[j]);
+          }
+      }
+      const int d = dist[seen.back()];
+      int32_t far = seen.back();
+      for (size_t h = seen.size(); h-- > 0 && dist[seen[h]] == d;)
+        if (deg(seen[h]) < deg(far)) far = seen[h];
+      for (int32_t v : seen) dist[v] = -1;
+      if (d <= depth) break;
+      depth = d;
+      root = far;
+    }
+    size_t head = order.size();
+    order.push_back(root);
+    placed[root] = 1;
+    while (head < order.size()) {
+      const int32_t v = order[head++];
+      nb.clear();
+      for (int32_t j = rp[v]; j < rp[v + 1]; ++j)
+        if (!placed[ci[j]]) {
+          placed[ci[j]] = 1;
+          nb.push_back(ci[j]);
+        }
+      std::stable_sort(nb.begin(), nb.end(), [&](int32_t a, int32_t b) { return deg(a) < deg(b); });
+      order.insert(order.end(), nb.begin(), nb.end());
+    }
+  }
+  perm.assign(order.rbegin(), order.rend());
+}
+
 // Labelling of the column-sliced path: vertices ranked by degree (descending,
 // ties by label) and dealt round-robin, in groups of 8 ranks, into kSlices
 // slices, slice s taking the contiguous labels [slice_off[s], slice_off[s+1]).
@@ -209,22 +296,10 @@ void slice_relabel(int32_t n, const int32_t* rp, const int32_t* ci, std::vector<
   for (int32_t r = 0; r < n; ++r) ++count[slice_of(r)];
   slice_off[0] = 0;
   for (int sl = 0; sl < kSlices; ++sl) slice_off[sl + 1] = slice_off[sl] + count[sl];
-  std::vector<int32_t> new_of(n);
   perm.assign(n, 0);
-  for (int32_t r = 0; r < n; ++r) {
-    const int32_t u = slice_off[slice_of(r)] + (r / (kDeal * kSlices)) * kDeal + r % kDeal;
-    new_of[order[r]] = u;
-    perm[u] = order[r];
-  }
-  rp2.assign(static_cast<size_t>(n) + 1, 0);
-  for (int32_t u = 0; u < n; ++u) rp2[u + 1] = rp2[u] + (rp[perm[u] + 1] - rp[perm[u]]);
-  ci2.resize(static_cast<size_t>(rp2[n]));
-  parallel_for(n, [&](int64_t u) {
-    const int32_t v = perm[u];
-    int32_t* dst = ci2.data() + rp2[u];
-    for (int32_t j = rp[v]; j < rp[v + 1]; ++j) *dst++ = new_of[ci[j]];
-    std::sort(ci2.data() + rp2[u], dst);
-  });
+  for (int32_t r = 0; r < n; ++r)
+    perm[slice_off[slice_of(r)] + (r / (kDeal * kSlices)) * kDeal + r % kDeal] = order[r];
+  relabel_csr(n, rp, ci, perm, rp2, ci2);
 }
 
 // Work items and packed entries of the column-sliced term (relabelled CSR).
@@ -349,6 +424,8 @@ void cpaa_default_opts(cpaa_opts* o) {
   o->time_kernels = 0;
   o->xcd_remap = -1;
   o->autotune = 0;
+  o->column_slices = 0;
+  o->locality_order = 0;
 }
 
 void cpaa_plan_destroy(cpaa_plan_t pl) {
@@ -361,7 +438,7 @@ void cpaa_plan_destroy(cpaa_plan_t pl) {
     if (m.d_items) (void)hipFree(m.d_items);
     if (m.d_split_nchunks) (void)hipFree(m.d_split_nchunks);
   }
-  if (pl->sliced) {
+  if (pl->d_perm) {
     void* sp[] = {pl->d_rp_w1, pl->d_ci_w1, pl->d_perm, pl->slc.d_entries, pl->slc.d_items,
                   pl->slc.d_split_nchunks};
     for (void* p : sp)
@@ -411,6 +488,10 @@ cpaa_status cpaa_plan(const cpaa_csr* g, double c, const cpaa_opts* opts, cpaa_p
   }
   if (o.column_slices == kSlices && (g->num_graphs > 1 || g->n >= kSliceMaxN)) {
     set_error("column slices need one graph with n < 8 (2^21 - 16)");
+    return CPAA_EINVAL;
+  }
+  if (o.locality_order < 0 || o.locality_order > 2) {
+    set_error("locality_order must be 0, 1 or 2");
     return CPAA_EINVAL;
   }
   if (o.k_max < 0 || o.max_refine < 0) {
@@ -503,6 +584,7 @@ cpaa_status cpaa_plan(const cpaa_csr* g, double c, const cpaa_opts* opts, cpaa_p
   pl->vol = vol;
   pl->ck.resize(kMaxTerms + 2);
   for (int k = 0; k < kMaxTerms + 2; ++k) pl->ck[k] = 2.0 / pl->s * std::pow(pl->beta, k);
+  pl->pk.assign(kMaxTerms + 2, 1.0 / (1.0 - pl->c));
 
   // Random gathers into a vector larger than one XCD's L2 are latency bound:
   // large graphs get 32 independent gathers in flight per thread.
@@ -520,8 +602,29 @@ cpaa_status cpaa_plan(const cpaa_csr* g, double c, const cpaa_opts* opts, cpaa_p
                (o.column_slices == 0 && num_graphs == 1 && n >= 3 * (1 << 18) &&
                 n < kSliceMaxN && static_cast<double>(maxd) >= 16.0 * vol / n);
   std::vector<int32_t> rp2, ci2, perm;
-  if (pl->sliced) slice_relabel(n, rp, ci, rp2, ci2, perm, pl->slc.slice_off);
-  const int32_t* rp1 = pl->sliced ? rp2.data() : rp;   // single-vector labelling
+  if (pl->sliced) {
+    slice_relabel(n, rp, ci, rp2, ci2, perm, pl->slc.slice_off);
+    pl->reordered = 1;
+  } else if (num_graphs == 1 && o.locality_order != 1 &&
+             (o.locality_order == 2 || n >= (1 << 18))) {
+    // Row order: gathers run at L2 speed when neighbouring rows have nearby
+    // columns.  Auto relabels by reverse Cuthill-McKee once the vector no longer
+    // fits a fraction of one XCD's L2, the caller's entries span more than 2^14
+    // labels on average, and the new order shortens that span at least 8x.
+    const double span = o.locality_order == 2 ? 0.0 : mean_span(n, rp, ci);
+    if (o.locality_order == 2 || span > 16384.0) {
+      rcm_order(n, rp, ci, perm);
+      relabel_csr(n, rp, ci, perm, rp2, ci2);
+      if (o.locality_order == 2 || 8.0 * mean_span(n, rp2.data(), ci2.data()) <= span) {
+        pl->reordered = 2;
+      } else {
+        std::vector<int32_t>().swap(rp2);
+        std::vector<int32_t>().swap(ci2);
+        std::vector<int32_t>().swap(perm);
+      }
+    }
+  }
+  const int32_t* rp1 = pl->reordered ? rp2.data() : rp;   // single-vector labelling
   // candidate work maps: the chosen npt, plus the other sizes when autotuning
   std::vector<int> npts = {pl->npt};
   if (o.autotune && o.nnz_per_thread == 0 && num_graphs == 1 && !pl->sliced)
@@ -560,12 +663,14 @@ cpaa_status cpaa_plan(const cpaa_csr* g, double c, const cpaa_opts* opts, cpaa_p
       pl->slc.max_items =
           std::max(pl->slc.max_items, pl->slc.item_off[sl + 1] - pl->slc.item_off[sl]);
     pl->slc.n_split_rows = static_cast<int>(snch.size());
-    if (s == CPAA_OK) s = dev_upload(&pl->d_rp_w1, rp2.data(), rp2.size());
-    if (s == CPAA_OK) s = dev_upload(&pl->d_ci_w1, ci2.data(), ci2.size());
-    if (s == CPAA_OK) s = dev_upload(&pl->d_perm, perm.data(), perm.size());
     if (s == CPAA_OK) s = dev_upload(&pl->slc.d_entries, entries.data(), entries.size());
     if (s == CPAA_OK) s = dev_upload(&pl->slc.d_items, sitems.data(), sitems.size());
     if (s == CPAA_OK) s = dev_upload(&pl->slc.d_split_nchunks, snch.data(), snch.size());
+  }
+  if (pl->reordered) {
+    if (s == CPAA_OK) s = dev_upload(&pl->d_rp_w1, rp2.data(), rp2.size());
+    if (s == CPAA_OK) s = dev_upload(&pl->d_ci_w1, ci2.data(), ci2.size());
+    if (s == CPAA_OK) s = dev_upload(&pl->d_perm, perm.data(), perm.size());
   } else {
     pl->d_rp_w1 = pl->d_row_ptr;
     pl->d_ci_w1 = pl->d_col_idx;
@@ -639,7 +744,7 @@ cpaa_status cpaa_plan_info_get(cpaa_plan_t pl, cpaa_plan_info* info) {
   info->n = pl->n;
   info->nnz = pl->nnz;
   info->num_graphs = pl->num_graphs;
-  info->reordered = pl->sliced ? 1 : 0;
+  info->reordered = pl->reordered;
   info->max_degree = pl->max_deg;
   info->split_rows = pl->n_split_rows;
   info->nnz_per_thread = pl->npt;

@@ -90,7 +90,21 @@ struct WorkMap {
   int* d_split_nchunks = nullptr;
 };
 
+// The series a solve sums on the term kernels (z_k in z-space, x = D acc).
+//   kChebyshev (Alg. 1): z_1 = D^{-1}A z_0, z_{k+1} = 2 D^{-1}A z_k - z_{k-1};
+//     acc = c_0/2 z_0 + sum c_k z_k; certificate partial d |z_{k+1} - beta z_k|.
+//   kPower: the power method x_{t+1} = cPx_t + b started at x_0 = b/(1-c) (for
+//     b = (1-c)p: eq. 2.1 iterated from p), summed as x_0 plus its increments
+//     delta_t = x_{t+1} - x_t = (cP)^t delta_0, delta_0 = c(P - I)x_0.  With
+//     z_0 = D^{-1}b: z_1 = c(D^{-1}A z_0 - z_0) = (1-c) D^{-1}delta_0 and
+//     z_{k+1} = c D^{-1}A z_k; every coefficient is 1/(1-c), so acc after the
+//     launch producing z_{k+1} is D^{-1}x_{k+1}.  Certificate partial
+//     d |z_{k+1}| = (1-c) |delta_k|, and ||x_k - x*||_1 <= ||delta_k||_1/(1-c)
+//     because delta_k is the residual b - (I-cP)x_k.
+enum class Method { kChebyshev, kPower };
+
 struct Workspace {
+  Method method = Method::kChebyshev;  // series of the solve in progress
   int W = 0;              // tile width (1 = single vector path)
   int tiles = 0;
   int64_t cols = 0;       // tiles * W
@@ -139,6 +153,7 @@ struct cpaa_plan_s {
   int32_t* d_rp_w1 = nullptr;
   int32_t* d_ci_w1 = nullptr;
   int32_t* d_perm = nullptr;         // [n] single-vector label -> caller's label, or null
+  int reordered = 0;                 // 0 caller's labels, 1 column slices, 2 reverse Cuthill-McKee
   bool sliced = false;
   cpaa::SlicedMap slc;
 
@@ -175,6 +190,7 @@ struct cpaa_plan_s {
   void* graph_state = nullptr;       // graphs.hip: packed local pairs, records, HIP graph
 
   std::vector<double> ck;            // c_k, k = 0..kMaxTerms+1
+  std::vector<double> pk;            // power-method coefficients 1/(1-c), k = 0..kMaxTerms+1
 
   cpaa::Workspace ws1;               // W = 1
   cpaa::Workspace wst;               // tiled
@@ -185,6 +201,31 @@ struct cpaa_plan_s {
 };
 
 namespace cpaa {
+
+// Weight of z_0 in acc and the coefficients of z_1, z_2, ... for the series
+// of the solve in progress.
+inline double series_a0(const cpaa_plan_s* pl, const Workspace& ws) {
+  return ws.method == Method::kPower ? pl->pk[0] : pl->ck[0] / 2.0;
+}
+inline const std::vector<double>& series_coef(const cpaa_plan_s* pl, const Workspace& ws) {
+  return ws.method == Method::kPower ? pl->pk : pl->ck;
+}
+
+// Epilogue constants of a term launch: z_{k+1} = alpha D^{-1}(A z_k) - gamma zp,
+// certificate partial d |z_{k+1} - beta z_k|; zp is z_{k-1}, or z_k itself
+// for the power method's first launch.
+struct TermShape {
+  float alpha, gamma;
+  double beta;
+  bool zp_is_cur;
+};
+inline TermShape term_shape(const cpaa_plan_s* pl, const Workspace& ws, bool first) {
+  if (ws.method == Method::kPower) {
+    const float c = static_cast<float>(pl->c);
+    return {c, first ? c : 0.f, 0.0, first};
+  }
+  return {first ? 1.f : 2.f, first ? 0.f : 1.f, pl->beta, false};
+}
 
 hipError_t fill_f64(double* p, double v, size_t count, hipStream_t st);
 hipError_t fill_i32(int* p, int v, size_t count, hipStream_t st);

@@ -244,7 +244,8 @@ struct TileTermEpi {
   __device__ __forceinline__ Pre prefetch(int r, int j) const {
     const size_t idx = (size_t)r * W + j;
     return {gamma != 0.f || au.a_prev != 0.0 ? zp[idx] : 0.f,
-            want_cert || au.a_cur != 0.0 ? zc[idx] : 0.f, au.on ? acc[idx] : 0.0};
+            (want_cert && beta != 0.0) || au.a_cur != 0.0 ? zc[idx] : 0.f,
+            au.on ? acc[idx] : 0.0};
   }
   __device__ __forceinline__ void row(int r, int d, int j, float s, float, const Pre& p) {
     const size_t idx = (size_t)r * W + j;
@@ -529,7 +530,7 @@ hipError_t init_tile(const cpaa_plan_s* pl, Workspace& ws, const double* P, int6
                      double scale, bool add, bool store_b, bool series, hipStream_t st) {
   CPAA_LAUNCH_W(k_in_tile, ws.W, dim3(vert_blocks(pl->n), ws.tiles), st, 0, (int64_t)pl->n,
                              (const int*)pl->d_row_ptr, P, ldp, B, scale, add ? 1 : 0,
-                             store_b ? 1 : 0, series ? 1 : 0, pl->ck[0] / 2.0, ws.b, ws.z[0],
+                             store_b ? 1 : 0, series ? 1 : 0, series_a0(pl, ws), ws.b, ws.z[0],
                              ws.acc, ws.stat_slots, ws.cols);
   return hipGetLastError();
 }
@@ -548,12 +549,13 @@ hipError_t init_tile_from_r(const cpaa_plan_s* pl, Workspace& ws, const int* act
   int g = static_cast<int>(std::min<size_t>((total + kWG - 1) / kWG, 8192));
   CPAA_LAUNCH_W(k_from_r_tile, ws.W, dim3(g, ws.tiles), st, (int64_t)pl->n,
                                  (const int*)pl->d_row_ptr, ws.r, (const double*)ws.b, ws.z[0],
-                                 ws.acc, pl->ck[0] / 2.0, active, plain);
+                                 ws.acc, series_a0(pl, ws), active, plain);
   return hipGetLastError();
 }
 
 hipError_t term_tile(const cpaa_plan_s* pl, Workspace& ws, int cur, int prev, int next, bool first,
                      const AccUpdate& au, double* cert_slot, const int* done, hipStream_t st) {
+  const TermShape sh = term_shape(pl, ws, first);
   TileTermArgs a;
   a.rp = pl->d_row_ptr;
   a.ci = pl->d_col_idx;
@@ -561,13 +563,13 @@ hipError_t term_tile(const cpaa_plan_s* pl, Workspace& ws, int cur, int prev, in
   a.n_items = pl->n_titems;
   a.n = pl->n;
   a.z_cur = ws.z[cur];
-  a.z_prev = first ? nullptr : ws.z[prev];
+  a.z_prev = first ? (sh.zp_is_cur ? ws.z[cur] : nullptr) : ws.z[prev];
   a.z_next = ws.z[next];
   a.acc = ws.acc;
-  a.alpha = first ? 1.f : 2.f;
-  a.gamma = first ? 0.f : 1.f;
+  a.alpha = sh.alpha;
+  a.gamma = sh.gamma;
   a.au = au;
-  a.beta = pl->beta;
+  a.beta = sh.beta;
   a.cert = cert_slot;
   a.cols = ws.cols;
   a.done = done;

@@ -1,6 +1,7 @@
 // Single-vector CPAA kernels (one right-hand side), gfx950.
 //
-// Hot loop (Alg. 1, Sec. 4.1, in z-space z_k = D^{-1} T_k(P) b):
+// Hot loop (Alg. 1, Sec. 4.1, in z-space z_k = D^{-1} T_k(P) b; the power
+// method runs on the same kernels with other epilogue constants, TermShape):
 //     z_{k+1}(u) = 2 * (sum_{v in N(u)} z_k(v)) / d_u - z_{k-1}(u)
 //     acc(u)    += c_{k+1} * z_{k+1}(u)                     (FP64)
 // (one launch in two or three adds the newest terms at once, from the z_{k-1}
@@ -163,7 +164,7 @@ struct TermEpi {
     if (gamma != 0.f || au.a_prev != 0.0) p = zp[r];
     if (gamma != 0.f) y -= gamma * p;
     zn[r] = y;
-    if (want_cert || au.a_cur != 0.0) c = zc[r];
+    if ((want_cert && beta != 0.0) || au.a_cur != 0.0) c = zc[r];
     if (au.on) {
       // the newest (smallest) term first
       double add = au.a_next * static_cast<double>(y);
@@ -496,7 +497,7 @@ int elem_grid(int64_t n) {
 hipError_t init_w1(const cpaa_plan_s* pl, Workspace& ws, const double* src, double scale,
                    bool add, bool store_b, bool series, hipStream_t st) {
   hipLaunchKernelGGL(k_init_w1, dim3(elem_grid(pl->n)), dim3(kWG), 0, st, pl->n, pl->d_rp_w1,
-                     src == ws.r ? nullptr : pl->d_perm, src, scale, add ? 1 : 0, store_b ? 1 : 0, series ? 1 : 0, pl->ck[0] / 2.0,
+                     src == ws.r ? nullptr : pl->d_perm, src, scale, add ? 1 : 0, store_b ? 1 : 0, series ? 1 : 0, series_a0(pl, ws),
                      ws.b, ws.z[0], ws.acc, ws.stat_slots);
   return hipGetLastError();
 }
@@ -509,6 +510,7 @@ hipError_t load_x0_w1(const cpaa_plan_s* pl, Workspace& ws, const double* x0, hi
 
 hipError_t term_w1(const cpaa_plan_s* pl, Workspace& ws, int cur, int prev, int next, bool first,
                    const AccUpdate& au, double* cert_slot, const int* done, hipStream_t st) {
+  const TermShape sh = term_shape(pl, ws, first);
   if (pl->sliced) {
     SlicedArgs s;
     s.entries = pl->slc.d_entries;
@@ -534,13 +536,13 @@ hipError_t term_w1(const cpaa_plan_s* pl, Workspace& ws, int cur, int prev, int 
     c.rp = pl->d_rp_w1;
     c.part = ws.part;
     c.zc = ws.z[cur];
-    c.zp = first ? nullptr : ws.z[prev];
+    c.zp = first ? (sh.zp_is_cur ? ws.z[cur] : nullptr) : ws.z[prev];
     c.zn = ws.z[next];
     c.acc = ws.acc;
-    c.alpha = first ? 1.f : 2.f;
-    c.gamma = first ? 0.f : 1.f;
+    c.alpha = sh.alpha;
+    c.gamma = sh.gamma;
     c.au = au;
-    c.beta = pl->beta;
+    c.beta = sh.beta;
     c.cert = cert_slot;
     c.done = done;
     c.n = pl->n;
@@ -552,13 +554,13 @@ hipError_t term_w1(const cpaa_plan_s* pl, Workspace& ws, int cur, int prev, int 
   a.ci = pl->d_ci_w1;
   a.items = pl->d_items;
   a.zc = ws.z[cur];
-  a.zp = first ? nullptr : ws.z[prev];
+  a.zp = first ? (sh.zp_is_cur ? ws.z[cur] : nullptr) : ws.z[prev];
   a.zn = ws.z[next];
   a.acc = ws.acc;
-  a.alpha = first ? 1.f : 2.f;
-  a.gamma = first ? 0.f : 1.f;
+  a.alpha = sh.alpha;
+  a.gamma = sh.gamma;
   a.au = au;
-  a.beta = pl->beta;
+  a.beta = sh.beta;
   a.cert = cert_slot;
   a.done = done;
   a.split_part = ws.split_f;

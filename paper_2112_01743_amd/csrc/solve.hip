@@ -124,6 +124,34 @@ int mass_rule_terms(const cpaa_plan_s* pl, double target) {
   return kMaxTerms;
 }
 
+// Launches a series runs at most.  Chebyshev: the a-priori bound's term count
+// for ||x_M - x*||_1 <= target (q = ||D^{-1/2}b||_2^2), x* the solution for
+// the right-hand side b.  Power method: until its own certificate must pass,
+// ||delta_M||_1 / (1-c) <= target, where ||delta_M||_1 <= c^M ||delta_0||_1 and
+// ||delta_0||_1 = c ||(P - I) x_0||_1 <= 2c ||b||_1 / (1-c) (x_0 = b/(1-c)); the
+// check of x_M runs in launch M, so M + 1 launches.  (The residual bound can be
+// 1/(1-c) looser than the error itself, e.g. on bipartite graphs, so a cap from
+// the error's contraction alone can end the series before the check passes.)
+int series_cap(const cpaa_plan_s* pl, const Workspace& ws, double q, double b_l1,
+               double target) {
+  if (ws.method != Method::kPower) return apriori_terms(pl, q, target);
+  const int cap = pl->opts.k_max > 0 ? std::min(pl->opts.k_max, kMaxTerms) : kMaxTerms;
+  const double c = pl->c;
+  double e = 2.0 * c * std::max(b_l1, 0.0) / ((1.0 - c) * (1.0 - c));
+  if (!(e > 0.0)) return 0;
+  for (int M = 0; M < cap; ++M, e *= c)
+    if (e <= target) return M + 1;
+  return cap;
+}
+
+// First launch whose certificate is checked: for a Chebyshev series on
+// b = (1-c)p eq. 4.1's term (no earlier stop is possible for a distribution
+// p), else the first; the power method is checked from its first launch on.
+int series_first_check(const cpaa_plan_s* pl, const Workspace& ws, double target, bool from_p) {
+  if (ws.method == Method::kPower) return 0;
+  return from_p ? mass_rule_terms(pl, target) : 1;
+}
+
 namespace {
 
 struct TermTimer {
@@ -213,7 +241,7 @@ cpaa_status run_series(cpaa_plan_s* pl, Workspace& ws, TermFn term, int series_i
   CPAA_HIP(init_done(ws, active, st));
   CPAA_HIP(fill_i32(ws.terms, k_cap, ws.tiles, st));
   CPAA_HIP(fill_f64(ws.series_cert, -1.0, cols, st));
-  const std::vector<AccUpdate> acc_plan = acc_schedule(pl->ck, k_cap, k_min);
+  const std::vector<AccUpdate> acc_plan = acc_schedule(series_coef(pl, ws), k_cap, k_min);
   for (int k = 0; k < k_cap; ++k) {
     // this launch produces z_{k+1}; its certificate is that of x_k
     double* cert = (k >= k_min) ? ws.slots + (size_t)k * kSlots * cols : nullptr;
@@ -222,7 +250,9 @@ cpaa_status run_series(cpaa_plan_s* pl, Workspace& ws, TermFn term, int series_i
     CPAA_HIP(term(pl, ws, k % 3, (k + 2) % 3, (k + 1) % 3, k == 0, acc_plan[k], cert, done, st));
     CPAA_HIP(timer.after(st));
     if (cert) {
-      const double scale = (1.0 + pl->s) / pl->s * std::pow(pl->beta, k + 1) / (1.0 - pl->c);
+      const double scale = ws.method == Method::kPower
+                               ? 1.0 / ((1.0 - pl->c) * (1.0 - pl->c))
+                               : (1.0 + pl->s) / pl->s * std::pow(pl->beta, k + 1) / (1.0 - pl->c);
       CPAA_HIP(check_series(pl, ws, cert, scale, target, k + 1, st));
     }
   }
@@ -326,8 +356,10 @@ struct TempDev {
 
 using namespace cpaa;
 
-extern "C" cpaa_status cpaa_solve(cpaa_plan_t pl, const double* p, double tol, const double* x0,
-                                  double* x, cpaa_report* rep, void* stream) {
+namespace {
+
+cpaa_status solve_single(cpaa_plan_t pl, const double* p, double tol, const double* x0, double* x,
+                         cpaa_report* rep, void* stream, Method method) {
   set_error("");
   if (!pl || !p || !x) {
     set_error("cpaa_solve: null argument");
@@ -345,6 +377,7 @@ extern "C" cpaa_status cpaa_solve(cpaa_plan_t pl, const double* p, double tol, c
   cpaa_status s = ensure_workspace(pl, pl->ws1, 1, 1);
   if (s != CPAA_OK) return s;
   Workspace& ws = pl->ws1;
+  ws.method = method;
   const int n = pl->n;
   const double c = pl->c;
 
@@ -376,7 +409,8 @@ extern "C" cpaa_status cpaa_solve(cpaa_plan_t pl, const double* p, double tol, c
 
   bool warm = dx0 != nullptr;
   bool p_checked = false;
-  double q0 = 0.0;  // ||D^{-1/2} b'||^2 of the first series' right-hand side
+  double q0 = 0.0;    // ||D^{-1/2} b'||^2 of the first series' right-hand side
+  double b0_l1 = 0.0; // ||b'||_1 of the same
   bool skip_series = false;
   if (warm) {
     CPAA_HIP(load_x0_w1(pl, ws, dx0, st));
@@ -397,6 +431,7 @@ extern "C" cpaa_status cpaa_solve(cpaa_plan_t pl, const double* p, double tol, c
       skip_series = true;
     } else {
       q0 = stat_at(ws, 1, 0, 2);
+      b0_l1 = r0;
       // series on b' = r0, added to acc = D^{-1} x0
       CPAA_HIP(init_w1(pl, ws, ws.r, 1.0, true, false, true, st));
     }
@@ -407,6 +442,7 @@ extern "C" cpaa_status cpaa_solve(cpaa_plan_t pl, const double* p, double tol, c
     if ((s = read_back(ws, st)) != CPAA_OK) return s;
     if (!p_checked && (s = check_p_stats(ws, 0)) != CPAA_OK) return s;
     q0 = stat_at(ws, 0, 0, 2);
+    b0_l1 = (1.0 - c) * stat_at(ws, 0, 0, 0);
     if (pl->opts.autotune && !pl->tuned_w1 && pl->maps.size() > 1 && !pl->sliced) {
       // autotune the work-item size on this input: time a few terms per candidate
       size_t best = 0;
@@ -432,8 +468,8 @@ extern "C" cpaa_status cpaa_solve(cpaa_plan_t pl, const double* p, double tol, c
   const double target_main = 0.5 * tol;
   int k_cap = 0;
   if (!skip_series) {
-    k_cap = apriori_terms(pl, q0, target_main);
-    const int k_min = warm ? 1 : std::min(mass_rule_terms(pl, target_main), k_cap);
+    k_cap = series_cap(pl, ws, q0, b0_l1, target_main);
+    const int k_min = std::min(series_first_check(pl, ws, target_main, !warm), k_cap);
     if ((s = run_series(pl, ws, term_w1, 0, k_cap, k_min, target_main, timer, st)) != CPAA_OK)
       return s;
   }
@@ -461,12 +497,13 @@ extern "C" cpaa_status cpaa_solve(cpaa_plan_t pl, const double* p, double tol, c
     if (bound <= tol || !std::isfinite(bound) || R.refinements >= pl->opts.max_refine) break;
     // correction series on b' = r: x += x_M(r)
     const double target_ref = 0.25 * tol;
-    const int kr = apriori_terms(pl, stat_at(ws, 1, 0, 2), target_ref);
+    const int kr = series_cap(pl, ws, stat_at(ws, 1, 0, 2), stat_at(ws, 1, 0, 0), target_ref);
     CPAA_HIP(init_w1(pl, ws, ws.r, 1.0, true, false, true, st));
     R.refinements++;
     series_terms.push_back(kr);
-    if ((s = run_series(pl, ws, term_w1, (int)series_terms.size() - 1, kr, 1, target_ref, timer,
-                        st)) != CPAA_OK)
+    if ((s = run_series(pl, ws, term_w1, (int)series_terms.size() - 1, kr,
+                        std::min(series_first_check(pl, ws, target_ref, false), kr), target_ref,
+                        timer, st)) != CPAA_OK)
       return s;
   }
   R.cert_bound = bound;
@@ -493,9 +530,9 @@ extern "C" cpaa_status cpaa_solve(cpaa_plan_t pl, const double* p, double tol, c
 // ----------------------------------------------------------------------------
 // Batched solves: tiles of W right-hand sides, one SpMM kernel per term.
 // ----------------------------------------------------------------------------
-extern "C" cpaa_status cpaa_solve_batched(cpaa_plan_t pl, int32_t B, const double* P, int64_t ldp,
-                                          double tol, const double* X0, int64_t ldx0, double* X,
-                                          int64_t ldx, cpaa_report* reps, void* stream) {
+cpaa_status solve_batched(cpaa_plan_t pl, int32_t B, const double* P, int64_t ldp, double tol,
+                          const double* X0, int64_t ldx0, double* X, int64_t ldx,
+                          cpaa_report* reps, void* stream, Method method) {
   set_error("");
   if (!pl || !P || !X || B <= 0) {
     set_error("cpaa_solve_batched: null argument or B <= 0");
@@ -524,6 +561,7 @@ extern "C" cpaa_status cpaa_solve_batched(cpaa_plan_t pl, int32_t B, const doubl
       if (Wc > 16 && Wc / 2 >= B) break;
       const int Tc = (B + Wc - 1) / Wc;
       if ((s = ensure_workspace(pl, pl->wst, Wc, Tc)) != CPAA_OK) return s;
+      pl->wst.method = method;
       CPAA_HIP(fill_f64(pl->wst.stat_slots, 0.0, (size_t)2 * kSlots * pl->wst.cols * kStat, st));
       CPAA_HIP(init_tile(pl, pl->wst, P, ldp, B, 1.0 - pl->c, false, false, true, st));
       hipError_t e = hipSuccess;
@@ -544,6 +582,7 @@ extern "C" cpaa_status cpaa_solve_batched(cpaa_plan_t pl, int32_t B, const doubl
   s = ensure_workspace(pl, pl->wst, W, T);
   if (s != CPAA_OK) return s;
   Workspace& ws = pl->wst;
+  ws.method = method;
   const double c = pl->c;
   const int64_t cols = ws.cols;
 
@@ -594,7 +633,7 @@ extern "C" cpaa_status cpaa_solve_batched(cpaa_plan_t pl, int32_t B, const doubl
 
   const double target_main = 0.5 * tol;
   int k_min;
-  std::vector<double> q(cols, 0.0);
+  std::vector<double> q(cols, 0.0), b_l1(cols, 0.0);
   if (dX0) {
     CPAA_HIP(load_x0_tile(pl, ws, dX0, lx0, B, st));
     CPAA_HIP(init_tile(pl, ws, dP, lp, B, 1.0 - c, false, true, false, st));
@@ -610,19 +649,24 @@ extern "C" cpaa_status cpaa_solve_batched(cpaa_plan_t pl, int32_t B, const doubl
       hv.plain[j] = use_warm ? 0 : 1;
       fallback[j] = (j < B && !use_warm) ? 1 : 0;
       q[j] = use_warm ? stat_at(ws, 1, j, 2) : stat_at(ws, 0, j, 2);
+      b_l1[j] = use_warm ? r0 : bnorm;
     }
     CPAA_HIP(hipMemcpyAsync(ws.plain, hv.plain, cols * sizeof(int), hipMemcpyHostToDevice, st));
     CPAA_HIP(init_tile_from_r(pl, ws, nullptr, ws.plain, st));
-    k_min = 1;
+    k_min = series_first_check(pl, ws, target_main, false);
   } else {
     CPAA_HIP(init_tile(pl, ws, dP, lp, B, 1.0 - c, false, true, true, st));
     if ((s = read_back(ws, st)) != CPAA_OK) return s;
     if ((s = validate_cols()) != CPAA_OK) return s;
-    for (int64_t j = 0; j < cols; ++j) q[j] = stat_at(ws, 0, j, 2);
-    k_min = mass_rule_terms(pl, target_main);
+    for (int64_t j = 0; j < cols; ++j) {
+      q[j] = stat_at(ws, 0, j, 2);
+      b_l1[j] = (1.0 - c) * stat_at(ws, 0, j, 0);
+    }
+    k_min = series_first_check(pl, ws, target_main, true);
   }
   int k_cap = 0;
-  for (int64_t j = 0; j < cols; ++j) k_cap = std::max(k_cap, apriori_terms(pl, q[j], target_main));
+  for (int64_t j = 0; j < cols; ++j)
+    k_cap = std::max(k_cap, series_cap(pl, ws, q[j], b_l1[j], target_main));
   k_min = std::min(k_min, k_cap);
   if ((s = run_series(pl, ws, term_tile, 0, k_cap, k_min, target_main, timer, st)) != CPAA_OK)
     return s;
@@ -667,8 +711,10 @@ extern "C" cpaa_status cpaa_solve_batched(cpaa_plan_t pl, int32_t B, const doubl
       active[t] = (need && refinements[t] < pl->opts.max_refine) ? 1 : 0;
       if (active[t]) {
         any = true;
-        for (int jj = 0; jj < W; ++jj)
-          k_ref = std::max(k_ref, apriori_terms(pl, q_r[(int64_t)t * W + jj], target_ref));
+        for (int jj = 0; jj < W; ++jj) {
+          const int64_t j = (int64_t)t * W + jj;
+          k_ref = std::max(k_ref, series_cap(pl, ws, q_r[j], r_l1[j], target_ref));
+        }
       }
     }
     if (!any) break;
@@ -680,8 +726,9 @@ extern "C" cpaa_status cpaa_solve_batched(cpaa_plan_t pl, int32_t B, const doubl
     masked = true;
     CPAA_HIP(init_tile_from_r(pl, ws, ws.active, nullptr, st));
     series_terms.push_back(k_ref);
-    if ((s = run_series(pl, ws, term_tile, (int)series_terms.size() - 1, k_ref, 1, target_ref,
-                        timer, st, ws.active)) != CPAA_OK)
+    if ((s = run_series(pl, ws, term_tile, (int)series_terms.size() - 1, k_ref,
+                        std::min(series_first_check(pl, ws, target_ref, false), k_ref),
+                        target_ref, timer, st, ws.active)) != CPAA_OK)
       return s;
   }
   const double* col_scale = nullptr;
@@ -729,4 +776,30 @@ extern "C" cpaa_status cpaa_solve_batched(cpaa_plan_t pl, int32_t B, const doubl
     return CPAA_ENOCONV;
   }
   return CPAA_OK;
+}
+
+}  // namespace
+
+extern "C" cpaa_status cpaa_solve(cpaa_plan_t pl, const double* p, double tol, const double* x0,
+                                  double* x, cpaa_report* rep, void* stream) {
+  return solve_single(pl, p, tol, x0, x, rep, stream, Method::kChebyshev);
+}
+
+extern "C" cpaa_status cpaa_solve_power(cpaa_plan_t pl, const double* p, double tol,
+                                        const double* x0, double* x, cpaa_report* rep,
+                                        void* stream) {
+  return solve_single(pl, p, tol, x0, x, rep, stream, Method::kPower);
+}
+
+extern "C" cpaa_status cpaa_solve_batched(cpaa_plan_t pl, int32_t B, const double* P, int64_t ldp,
+                                          double tol, const double* X0, int64_t ldx0, double* X,
+                                          int64_t ldx, cpaa_report* reps, void* stream) {
+  return solve_batched(pl, B, P, ldp, tol, X0, ldx0, X, ldx, reps, stream, Method::kChebyshev);
+}
+
+extern "C" cpaa_status cpaa_solve_power_batched(cpaa_plan_t pl, int32_t B, const double* P,
+                                                int64_t ldp, double tol, const double* X0,
+                                                int64_t ldx0, double* X, int64_t ldx,
+                                                cpaa_report* reps, void* stream) {
+  return solve_batched(pl, B, P, ldp, tol, X0, ldx0, X, ldx, reps, stream, Method::kPower);
 }

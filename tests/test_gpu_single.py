@@ -183,6 +183,52 @@ def test_column_sliced_warm_start_and_host_io(torch_cuda):
     _assert_parity(g, p, xh, reph, 1e-9)
 
 
+def _two_cycles():
+    i = np.arange(9)
+    u = np.concatenate([i, 9 + np.arange(14)])
+    v = np.concatenate([(i + 1) % 9, 9 + (np.arange(14) + 1) % 14])
+    return gg.csr_from_edges(23, u, v)
+
+
+@pytest.mark.parametrize("case", ["delaunay", "chung_lu", "grid", "two_cycles", "star", "path"])
+def test_rcm_relabelled_term_agrees(torch_cuda, case):
+    """Row-order term on reverse Cuthill-McKee labels (forced), on graphs of
+    every shape, disconnected ones included; p, x0 and x stay in the caller's
+    labels."""
+    g = {"delaunay": lambda: gg.delaunay(20000, seed=3),
+         "chung_lu": lambda: gg.chung_lu(30000, 10, 2.2, seed=31),
+         "grid": lambda: gg.perturbed_grid(120, 0.05, 0.01, seed=4),
+         "two_cycles": _two_cycles, "star": lambda: gg.star(40), "path": lambda: gg.path(7)}[case]()
+    for p in (gg.uniform_personalization(g.n), gg.source_personalization(g.n, [g.n // 2])[0],
+              gg.source_personalization(g.n, [0])[0]):
+        x, rep, plan = _solve(torch_cuda, g, p, 1e-9, locality_order=2)
+        info = plan.info()
+        assert info["reordered"] == 2 and info["column_slices"] == 1
+        _assert_parity(g, p, x, rep, 1e-9)
+
+
+def test_rcm_auto_on_random_order_mesh_only(torch_cuda):
+    """Auto: a Delaunay mesh in random point order (n = 300k) is relabelled and
+    solved to 1e-7 (CPAA and the power method, plain and warm-started); a lattice
+    in its natural row-major order (n = 360k) keeps the caller's labels."""
+    from paper_2112_01743_amd import Plan
+    g = gg.delaunay(300000, seed=7)
+    plan = Plan.from_graph(g, C)
+    assert plan.info()["reordered"] == 2
+    p = gg.source_personalization(g.n, [123])[0]
+    pi = _truth(g, p)
+    x, rep = plan.solve(_dev(torch_cuda, p), 1e-7)
+    _assert_parity(g, p, x.cpu().numpy(), rep, 1e-7)
+    x, rep = plan.solve_power(_dev(torch_cuda, p), 1e-7)
+    _assert_parity(g, p, x.cpu().numpy(), rep, 1e-7)
+    guess = np.abs(pi * (1 + 1e-3 * gg.philox(2).standard_normal(g.n)))
+    x, rep = plan.solve(_dev(torch_cuda, p), 1e-7, _dev(torch_cuda, guess))
+    assert rep["fallback_used"] == 0
+    _assert_parity(g, p, x.cpu().numpy(), rep, 1e-7)
+    grid = gg.perturbed_grid(600, 0.05, 0.0, seed=5)
+    assert Plan.from_graph(grid, C).info()["reordered"] == 0
+
+
 def test_autotuned_work_items(torch_cuda):
     """The autotuner times candidate work-item sizes on the first plain solve,
     keeps the fastest, and every later solve uses it."""

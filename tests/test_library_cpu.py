@@ -12,6 +12,7 @@ from paper_2112_01743_amd import binding as B
 def test_library_exports_every_declared_function():
     names = B.header_functions()
     assert {"cpaa_plan", "cpaa_solve", "cpaa_solve_batched", "cpaa_solve_graphs",
+            "cpaa_solve_power", "cpaa_solve_power_batched",
             "cpaa_plan_destroy", "cpaa_last_error", "cpaa_default_opts",
             "cpaa_plan_info_get", "cpaa_model_create", "cpaa_model_predict",
             "cpaa_model_train_step", "cpaa_model_get_state", "cpaa_model_set_state",
@@ -104,6 +105,8 @@ def test_plan_rejects_bad_damping_and_options():
     assert "tile_w" in B.cpaa_last_error()
     assert _plan_status(g.row_ptr, g.col_idx, column_slices=4) == B.CPAA_EINVAL
     assert "column_slices" in B.cpaa_last_error()
+    assert _plan_status(g.row_ptr, g.col_idx, locality_order=3) == B.CPAA_EINVAL
+    assert "locality_order" in B.cpaa_last_error()
 
 
 def test_plan_rejects_edge_across_graph_boundary():
