@@ -37,10 +37,11 @@ import scipy.sparse as sp
 
 __all__ = [
     "beta", "chebyshev_coefficients", "chebyshev_coefficient_integral",
-    "convergence_rate", "mass_error", "accumulated_mass", "total_mass",
+    "interval_map", "chebyshev_interval_coefficients",
+    "chebyshev_interval_coefficient_integral", "convergence_rate", "mass_error", "accumulated_mass", "total_mass",
     "series_tail", "terms_for_mass_error", "apriori_error_bound", "terms_for_apriori",
     "adjacency", "transition_matrix", "transition_dense", "pagerank_exact",
-    "pagerank_power", "power_method", "cpaa", "cpaa_alg1_global", "residual", "residual_l1_bound",
+    "pagerank_power", "power_method", "cpaa", "cpaa_interval", "cpaa_alg1_global", "residual", "residual_l1_bound",
     "series_residual", "l1_error", "max_error", "max_relative_error",
 ]
 
@@ -70,6 +71,35 @@ def chebyshev_coefficient_integral(c: float, k: int) -> float:
         warnings.simplefilter("ignore", scipy.integrate.IntegrationWarning)
         val, _ = scipy.integrate.quad(lambda t: math.cos(k * t) / (1.0 - c * math.cos(t)),
                                       0.0, math.pi, limit=400, epsabs=1e-15, epsrel=1e-14)
+    return 2.0 / math.pi * val
+
+
+def interval_map(c: float, a: float) -> tuple[float, float]:
+    """On x in [a, 1] write x = ((1-a)u + (1+a))/2, u in [-1, 1].  Then
+    1/(1 - cx) = (1/A) / (1 - c' u) with A = 1 - c(1+a)/2 and c' = c(1-a)/(2A)
+    (Sec. 2.2's general interval applied to f(x) = 1/(1-cx)).  Returns (A, c')."""
+    A = 1.0 - c * (1.0 + a) / 2.0
+    return A, c * (1.0 - a) / (2.0 * A)
+
+
+def chebyshev_interval_coefficients(c: float, a: float, M: int) -> np.ndarray:
+    """Coefficients of 1/(1-cx) in the Chebyshev polynomials of u(x) on [a, 1]:
+    the [-1, 1] coefficients of 1/(1 - c'u) (Prop. 1's closed form with c') times
+    1/A.  For a = -1 they are the c_k of ``chebyshev_coefficients``."""
+    A, cp = interval_map(c, a)
+    return chebyshev_coefficients(cp, M) / A
+
+
+def chebyshev_interval_coefficient_integral(c: float, a: float, k: int) -> float:
+    """The general-interval coefficient of Sec. 2.2 for f(x) = 1/(1-cx) on [a, 1],
+    with the factor 2/pi that its [-1, 1] special case carries:
+    c_k = (2/pi) int_0^pi f(((1-a) cos t + (1+a))/2) cos(k t) dt, by quadrature."""
+    def f(t):
+        x = ((1.0 - a) * math.cos(t) + (1.0 + a)) / 2.0
+        return math.cos(k * t) / (1.0 - c * x)
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore", scipy.integrate.IntegrationWarning)
+        val, _ = scipy.integrate.quad(f, 0.0, math.pi, limit=400, epsabs=1e-15, epsrel=1e-14)
     return 2.0 / math.pi * val
 
 
@@ -286,6 +316,30 @@ def residual_l1_bound(g, b: np.ndarray, x: np.ndarray, c: float) -> np.ndarray |
     for a column-stochastic P (sum_k c^k ||P^k||_1 with ||P||_1 = 1)."""
     r = residual(g, b, x, c)
     return np.abs(r).sum(axis=0) / (1.0 - c)
+
+
+def cpaa_interval(g, b: np.ndarray, c: float, a: float, M: int, return_terms: bool = False):
+    """CPAA with the Chebyshev expansion of 1/(1-cx) on [a, 1] instead of [-1, 1]
+    (Sec. 2.2's general interval; valid when the spectrum of P lies in [a, 1]):
+        x_M = (c'_0/2) b + sum_{k=1..M} c'_k T_k(t(P)) b,  t(P) = (2P - (1+a)I)/(1-a),
+    with the c'_k of ``chebyshev_interval_coefficients`` and T_k(t(P)) b from
+    property (3): T_1 = t(P) T_0, T_{k+1} = 2 t(P) T_k - T_{k-1}.
+    With ``return_terms`` also [T_0 b, ..., T_{M+1} b]."""
+    A = adjacency(g)
+    deg = _deg(g)
+    ck = chebyshev_interval_coefficients(c, a, M + 1)
+
+    def t_of(T):
+        return (2.0 * _gather_over_neighbours(g, A, T, deg) - (1.0 + a) * T) / (1.0 - a)
+
+    T = [np.array(b, dtype=np.float64)]
+    T.append(t_of(T[0]))
+    for _ in range(2, M + 2):
+        T.append(2.0 * t_of(T[-1]) - T[-2])
+    acc = (ck[0] / 2.0) * T[0]
+    for k in range(1, M + 1):
+        acc = acc + ck[k] * T[k]
+    return (acc, T) if return_terms else acc
 
 
 def series_residual(c: float, M: int, TM: np.ndarray, TM1: np.ndarray) -> np.ndarray:
