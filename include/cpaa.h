@@ -117,6 +117,14 @@ typedef struct {
                              whose stored entries span more than 2^14 labels on average, if RCM
                              shortens that mean span at least 8x.  Inputs and outputs keep the
                              caller's labels. */
+  int32_t spectral_interval; /* 0 (default): the Chebyshev expansion on [-1, 1] (Alg. 1).
+                             1: estimate the smallest eigenvalue lambda_min of P at plan time
+                             (80 Lanczos steps on D^{-1/2} A D^{-1/2} on the host) and expand on
+                             [a, 1], a = lambda_min - 0.02 (Sec. 2.2's general interval; kept at
+                             -1 when a < -0.95, e.g. for graphs with a bipartite component):
+                             fewer terms when the spectrum stays away from -1.  Results are
+                             certified as always; a wrong a only slows convergence.  Single-graph
+                             plans only (else CPAA_EINVAL); the power method ignores it. */
 } cpaa_opts;
 
 /* Per-solve report (one per right-hand side in batched calls, one per graph in
@@ -153,9 +161,10 @@ typedef struct {
   int32_t tile_w;           /* batched tile width in use */
   int32_t k_cap_global;     /* a-priori term cap for uniform p at tol 1e-6 */
   double c;
-  double beta;
+  double beta;              /* decay ratio of the coefficients in use (of c' on [a, 1]) */
   double vol;               /* sum of degrees */
   int32_t column_slices;    /* single-vector term: 1 (row order) or 8 (column-sliced) */
+  double spectrum_lo;       /* a of the expansion interval [a, 1] (-1: the paper's) */
 } cpaa_plan_info;
 
 /* Fill *o with defaults.  Never fails. */

@@ -37,7 +37,8 @@ class cpaa_opts(ctypes.Structure):
                 ("tile_w", ctypes.c_int32), ("validate", ctypes.c_int32),
                 ("io_device", ctypes.c_int32), ("time_kernels", ctypes.c_int32),
                 ("xcd_remap", ctypes.c_int32), ("autotune", ctypes.c_int32),
-                ("column_slices", ctypes.c_int32), ("locality_order", ctypes.c_int32)]
+                ("column_slices", ctypes.c_int32), ("locality_order", ctypes.c_int32),
+                ("spectral_interval", ctypes.c_int32)]
 
 
 class cpaa_report(ctypes.Structure):
@@ -61,7 +62,7 @@ class cpaa_plan_info(ctypes.Structure):
                 ("work_items", ctypes.c_int32), ("tile_w", ctypes.c_int32),
                 ("k_cap_global", ctypes.c_int32), ("c", ctypes.c_double),
                 ("beta", ctypes.c_double), ("vol", ctypes.c_double),
-                ("column_slices", ctypes.c_int32)]
+                ("column_slices", ctypes.c_int32), ("spectrum_lo", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

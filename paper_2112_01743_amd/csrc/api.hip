@@ -274,6 +274,69 @@ void rcm_order(int32_t n, const int32_t* rp, const int32_t* ci, std::vector<int3
   perm.assign(order.rbegin(), order.rend());
 }
 
+// Smallest eigenvalue of P, estimated by m steps of the Lanczos iteration on
+// the symmetric S = D^{-1/2} A D^{-1/2} (similar to P, so the same spectrum)
+// from a fixed pseudo-random start: the smallest eigenvalue of the Lanczos
+// tridiagonal matrix, found by bisection on its Sturm sequence.  A Ritz value
+// is never below the true smallest eigenvalue and approaches it from above.
+double lanczos_lambda_min(int32_t n, const int32_t* rp, const int32_t* ci, int m) {
+  std::vector<double> isd(n), q(n), qp(n, 0.0), w(n);
+  for (int32_t u = 0; u < n; ++u) isd[u] = 1.0 / std::sqrt(static_cast<double>(rp[u + 1] - rp[u]));
+  uint64_t x = 0x9E3779B97F4A7C15ull;             // xorshift64 start vector
+  double nrm = 0.0;
+  for (int32_t u = 0; u < n; ++u) {
+    x ^= x << 13;
+    x ^= x >> 7;
+    x ^= x << 17;
+    q[u] = static_cast<double>(x >> 11) * 0x1p-53 - 0.5;
+    nrm += q[u] * q[u];
+  }
+  for (double& v : q) v /= std::sqrt(nrm);
+  std::vector<double> al, be;
+  double bprev = 0.0;
+  for (int j = 0; j < m; ++j) {
+    parallel_for(n, [&](int64_t u) {
+      double t = 0.0;
+      for (int32_t k = rp[u]; k < rp[u + 1]; ++k) t += isd[ci[k]] * q[ci[k]];
+      w[u] = isd[u] * t;
+    });
+    double a = 0.0;
+    for (int32_t u = 0; u < n; ++u) a += w[u] * q[u];
+    double b2 = 0.0;
+    for (int32_t u = 0; u < n; ++u) {
+      w[u] -= a * q[u] + bprev * qp[u];
+      b2 += w[u] * w[u];
+    }
+    al.push_back(a);
+    const double b = std::sqrt(b2);
+    if (b < 1e-12 || j + 1 == m) break;
+    be.push_back(b);
+    for (int32_t u = 0; u < n; ++u) {
+      qp[u] = q[u];
+      q[u] = w[u] / b;
+    }
+    bprev = b;
+  }
+  // number of eigenvalues of the tridiagonal matrix below t (Sturm sequence)
+  auto below = [&](double t) {
+    int cnt = 0;
+    double d = 1.0;
+    for (size_t i = 0; i < al.size(); ++i) {
+      const double off = i ? be[i - 1] * be[i - 1] : 0.0;
+      d = al[i] - t - (i ? off / d : 0.0);
+      if (d == 0.0) d = -1e-300;
+      if (d < 0.0) ++cnt;
+    }
+    return cnt;
+  };
+  double lo = -1.5, hi = 1.5;
+  for (int it = 0; it < 100; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (below(mid) >= 1) hi = mid; else lo = mid;
+  }
+  return hi;
+}
+
 // Labelling of the column-sliced path: vertices ranked by degree (descending,
 // ties by label) and dealt round-robin, in groups of 8 ranks, into kSlices
 // slices, slice s taking the contiguous labels [slice_off[s], slice_off[s+1]).
@@ -426,6 +489,7 @@ void cpaa_default_opts(cpaa_opts* o) {
   o->autotune = 0;
   o->column_slices = 0;
   o->locality_order = 0;
+  o->spectral_interval = 0;
 }
 
 void cpaa_plan_destroy(cpaa_plan_t pl) {
@@ -488,6 +552,14 @@ cpaa_status cpaa_plan(const cpaa_csr* g, double c, const cpaa_opts* opts, cpaa_p
   }
   if (o.column_slices == kSlices && (g->num_graphs > 1 || g->n >= kSliceMaxN)) {
     set_error("column slices need one graph with n < 8 (2^21 - 16)");
+    return CPAA_EINVAL;
+  }
+  if (o.spectral_interval != 0 && o.spectral_interval != 1) {
+    set_error("spectral_interval must be 0 or 1");
+    return CPAA_EINVAL;
+  }
+  if (o.spectral_interval == 1 && g->num_graphs > 1) {
+    set_error("spectral_interval needs a single-graph plan");
     return CPAA_EINVAL;
   }
   if (o.locality_order < 0 || o.locality_order > 2) {
@@ -583,7 +655,27 @@ cpaa_status cpaa_plan(const cpaa_csr* g, double c, const cpaa_opts* opts, cpaa_p
   pl->min_deg = mind;
   pl->vol = vol;
   pl->ck.resize(kMaxTerms + 2);
-  for (int k = 0; k < kMaxTerms + 2; ++k) pl->ck[k] = 2.0 / pl->s * std::pow(pl->beta, k);
+  // Chebyshev expansion on [a, 1] (Sec. 2.2's general interval): a = -1 is the
+  // paper's; with spectral_interval, a is a Lanczos estimate of the smallest
+  // eigenvalue of P less a margin (no gain below -0.95).  On x = ((1-a)u +
+  // (1+a))/2, 1/(1-cx) = (1/A)/(1-c'u), A = 1 - c(1+a)/2, c' = c(1-a)/(2A), so
+  // the coefficients are Prop. 1's with c' (beta', s') times 1/A.  The series'
+  // certificate identity is algebraic, so a wrong a slows convergence but never
+  // the certified result.
+  if (o.spectral_interval == 1) {
+    const double lam = lanczos_lambda_min(n, rp, ci, 80);
+    const double a = lam - 0.02;
+    if (a > -0.95) pl->lam_lo = std::min(a, 0.9);
+  }
+  {
+    const double a = pl->lam_lo;
+    pl->cheb_A = 1.0 - c * (1.0 + a) / 2.0;
+    const double cp = c * (1.0 - a) / (2.0 * pl->cheb_A);
+    pl->s = std::sqrt(1.0 - cp * cp);
+    pl->beta = (1.0 - pl->s) / cp;
+  }
+  for (int k = 0; k < kMaxTerms + 2; ++k)
+    pl->ck[k] = 2.0 / (pl->cheb_A * pl->s) * std::pow(pl->beta, k);
   pl->pk.assign(kMaxTerms + 2, 1.0 / (1.0 - pl->c));
 
   // Random gathers into a vector larger than one XCD's L2 are latency bound:
@@ -755,6 +847,7 @@ cpaa_status cpaa_plan_info_get(cpaa_plan_t pl, cpaa_plan_info* info) {
   info->vol = pl->vol;
   info->k_cap_global = mass_rule_terms(pl, 1e-6);
   info->column_slices = pl->sliced ? kSlices : 1;
+  info->spectrum_lo = pl->lam_lo;
   return CPAA_OK;
 }
 

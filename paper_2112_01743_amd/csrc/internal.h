@@ -137,8 +137,10 @@ struct cpaa_plan_s {
   int32_t n = 0;
   int64_t nnz = 0;
   double c = 0.85;
-  double beta = 0.0;
-  double s = 0.0;     // sqrt(1-c^2)
+  double beta = 0.0;  // beta of the expansion in use (of c', below)
+  double s = 0.0;     // sqrt(1-c'^2)
+  double lam_lo = -1.0;  // expansion interval [lam_lo, 1]; c' = c(1-a)/(2A), A below
+  double cheb_A = 1.0;   // 1 - c(1+a)/2
   double vol = 0.0;
   int max_deg = 0;
   int min_deg = 0;
@@ -211,20 +213,24 @@ inline const std::vector<double>& series_coef(const cpaa_plan_s* pl, const Works
   return ws.method == Method::kPower ? pl->pk : pl->ck;
 }
 
-// Epilogue constants of a term launch: z_{k+1} = alpha D^{-1}(A z_k) - gamma zp,
-// certificate partial d |z_{k+1} - beta z_k|; zp is z_{k-1}, or z_k itself
-// for the power method's first launch.
+// Epilogue constants of a term launch: z_{k+1} = alpha D^{-1}(A z_k) - gamma_c z_k
+// - gamma zp, certificate partial d |z_{k+1} - beta z_k|; zp is z_{k-1}, or z_k
+// itself for the power method's first launch.
 struct TermShape {
-  float alpha, gamma;
+  float alpha, gamma_c, gamma;  // z_{k+1} = alpha D^{-1}A z_k - gamma_c z_k - gamma zp
   double beta;
   bool zp_is_cur;
 };
 inline TermShape term_shape(const cpaa_plan_s* pl, const Workspace& ws, bool first) {
   if (ws.method == Method::kPower) {
     const float c = static_cast<float>(pl->c);
-    return {c, first ? c : 0.f, 0.0, first};
+    return {c, 0.f, first ? c : 0.f, 0.0, first};
   }
-  return {first ? 1.f : 2.f, first ? 0.f : 1.f, pl->beta, false};
+  // T_1 = t(P) T_0, T_{k+1} = 2 t(P) T_k - T_{k-1}, t(P) = (2P - (1+a)I)/(1-a)
+  const double a = pl->lam_lo;
+  const float al = static_cast<float>(2.0 / (1.0 - a));
+  const float gc = static_cast<float>((1.0 + a) / (1.0 - a));
+  return {first ? al : 2.f * al, first ? gc : 2.f * gc, first ? 0.f : 1.f, pl->beta, false};
 }
 
 hipError_t fill_f64(double* p, double v, size_t count, hipStream_t st);

@@ -232,7 +232,7 @@ struct TileTermEpi {
   float* __restrict__ zn;
   double* __restrict__ acc;
   int W;
-  float alpha, gamma;
+  float alpha, gamma_c, gamma;
   AccUpdate au;
   double beta;
   int want_cert;
@@ -244,12 +244,13 @@ struct TileTermEpi {
   __device__ __forceinline__ Pre prefetch(int r, int j) const {
     const size_t idx = (size_t)r * W + j;
     return {gamma != 0.f || au.a_prev != 0.0 ? zp[idx] : 0.f,
-            (want_cert && beta != 0.0) || au.a_cur != 0.0 ? zc[idx] : 0.f,
+            (want_cert && beta != 0.0) || au.a_cur != 0.0 || gamma_c != 0.f ? zc[idx] : 0.f,
             au.on ? acc[idx] : 0.0};
   }
   __device__ __forceinline__ void row(int r, int d, int j, float s, float, const Pre& p) {
     const size_t idx = (size_t)r * W + j;
     float y = alpha * (s / static_cast<float>(d));
+    if (gamma_c != 0.f) y -= gamma_c * p.zc;
     if (gamma != 0.f) y -= gamma * p.zp;
     zn[idx] = y;
     if (au.on) {
@@ -275,7 +276,7 @@ struct TileTermArgs {
   const float* z_prev;
   float* z_next;
   double* acc;
-  float alpha, gamma;
+  float alpha, gamma_c, gamma;
   AccUpdate au;
   double beta;
   double* cert;        // [kSlots][cols] or null
@@ -296,7 +297,7 @@ __global__ __launch_bounds__(kWG) void k_term_tile(TileTermArgs a) {
   const int item = __builtin_amdgcn_readfirstlane(lb * kWaves + (threadIdx.x >> 6));
   const size_t off = (size_t)t * a.n * W;
   TileTermEpi epi{a.z_cur + off, a.z_prev ? a.z_prev + off : nullptr, a.z_next + off,
-                  a.acc + off, W, a.alpha, a.gamma, a.au, a.beta, a.cert != nullptr, 0.0};
+                  a.acc + off, W, a.alpha, a.gamma_c, a.gamma, a.au, a.beta, a.cert != nullptr, 0.0};
   if (item < a.n_items)
     spmm_item<float, W, false>(a.items[item], a.rp, a.ci, a.z_cur + off,
                                a.split_part + (size_t)t * a.n_split * W,
@@ -567,6 +568,7 @@ hipError_t term_tile(const cpaa_plan_s* pl, Workspace& ws, int cur, int prev, in
   a.z_next = ws.z[next];
   a.acc = ws.acc;
   a.alpha = sh.alpha;
+  a.gamma_c = sh.gamma_c;
   a.gamma = sh.gamma;
   a.au = au;
   a.beta = sh.beta;

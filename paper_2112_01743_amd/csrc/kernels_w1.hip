@@ -153,7 +153,7 @@ struct TermEpi {
   const float* __restrict__ zp;
   float* __restrict__ zn;
   double* __restrict__ acc;
-  float alpha, gamma;
+  float alpha, gamma_c, gamma;
   AccUpdate au;
   double beta;
   int want_cert;
@@ -162,9 +162,10 @@ struct TermEpi {
     float y = alpha * (s / static_cast<float>(d));
     float p = 0.f, c = 0.f;
     if (gamma != 0.f || au.a_prev != 0.0) p = zp[r];
+    if ((want_cert && beta != 0.0) || au.a_cur != 0.0 || gamma_c != 0.f) c = zc[r];
+    if (gamma_c != 0.f) y -= gamma_c * c;
     if (gamma != 0.f) y -= gamma * p;
     zn[r] = y;
-    if ((want_cert && beta != 0.0) || au.a_cur != 0.0) c = zc[r];
     if (au.on) {
       // the newest (smallest) term first
       double add = au.a_next * static_cast<double>(y);
@@ -186,7 +187,7 @@ struct TermArgs {
   const float* zp;
   float* zn;
   double* acc;
-  float alpha, gamma;
+  float alpha, gamma_c, gamma;
   AccUpdate au;
   double beta;
   double* cert;          // [kSlots] or null
@@ -201,7 +202,7 @@ template <int NPT>
 __global__ __launch_bounds__(kWG) void k_term_w1(TermArgs a) {
   if (a.done != nullptr && *a.done) return;
   const int lb = xcd_logical(blockIdx.x, gridDim.x, a.xcd);
-  TermEpi epi{a.zc, a.zp, a.zn, a.acc, a.alpha, a.gamma, a.au, a.beta,
+  TermEpi epi{a.zc, a.zp, a.zn, a.acc, a.alpha, a.gamma_c, a.gamma, a.au, a.beta,
               a.cert != nullptr, 0.0};
   spmv_item<float, NPT, false>(a.items[lb], a.rp, a.ci, a.zc, a.split_part, a.split_count,
                         a.split_nchunks, epi);
@@ -336,7 +337,7 @@ struct CombineArgs {
   const float* zp;
   float* zn;
   double* acc;
-  float alpha, gamma;
+  float alpha, gamma_c, gamma;
   AccUpdate au;
   double beta;
   double* cert;
@@ -346,7 +347,7 @@ struct CombineArgs {
 
 __global__ __launch_bounds__(kWG) void k_combine_w1(CombineArgs a) {
   if (a.done != nullptr && *a.done) return;
-  TermEpi epi{a.zc, a.zp, a.zn, a.acc, a.alpha, a.gamma, a.au, a.beta,
+  TermEpi epi{a.zc, a.zp, a.zn, a.acc, a.alpha, a.gamma_c, a.gamma, a.au, a.beta,
               a.cert != nullptr, 0.0};
   const size_t n = static_cast<size_t>(a.n);
   for (int u = blockIdx.x * kWG + threadIdx.x; u < a.n; u += gridDim.x * kWG) {
@@ -540,6 +541,7 @@ hipError_t term_w1(const cpaa_plan_s* pl, Workspace& ws, int cur, int prev, int 
     c.zn = ws.z[next];
     c.acc = ws.acc;
     c.alpha = sh.alpha;
+    c.gamma_c = sh.gamma_c;
     c.gamma = sh.gamma;
     c.au = au;
     c.beta = sh.beta;
@@ -558,6 +560,7 @@ hipError_t term_w1(const cpaa_plan_s* pl, Workspace& ws, int cur, int prev, int 
   a.zn = ws.z[next];
   a.acc = ws.acc;
   a.alpha = sh.alpha;
+  a.gamma_c = sh.gamma_c;
   a.gamma = sh.gamma;
   a.au = au;
   a.beta = sh.beta;

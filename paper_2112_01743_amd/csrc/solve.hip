@@ -103,8 +103,8 @@ cpaa_status ensure_workspace(cpaa_plan_s* pl, Workspace& ws, int W, int tiles) {
 }
 
 double series_tail(const cpaa_plan_s* pl, int M) {
-  // sum_{k>M} c_k = (2/s) beta^{M+1} / (1 - beta)
-  return 2.0 / pl->s * std::pow(pl->beta, M + 1) / (1.0 - pl->beta);
+  // sum_{k>M} c_k = (2/(A s)) beta^{M+1} / (1 - beta)
+  return 2.0 / (pl->cheb_A * pl->s) * std::pow(pl->beta, M + 1) / (1.0 - pl->beta);
 }
 
 int apriori_terms(const cpaa_plan_s* pl, double q, double target) {

@@ -62,6 +62,51 @@ def test_chung_lu_4m_global(torch_cuda):
 
 
 @pytest.mark.timeout(600)
+def test_power_method_4m_global(torch_cuda):
+    """The power method on the same plan (column-sliced kernels) at the full size:
+    certified by the oracle's own residual, and the same vector as CPAA's."""
+    from paper_2112_01743_amd import Plan
+    torch = torch_cuda
+    g = gg.chung_lu(4_000_000, 16, 2.1, seed=2112001, dmin=1.0, dmax=50000.0)
+    plan = Plan.from_graph(g, C, time_kernels=1)
+    p = np.full(g.n, 1.0 / g.n)
+    dp = torch.as_tensor(p, device="cuda")
+    xp, rp = plan.solve_power(dp, TOL)
+    xc, rc = plan.solve(dp, TOL)
+    xp, xc = xp.cpu().numpy(), xc.cpu().numpy()
+    bound = _oracle_bound(g, ((1 - C) * p)[None, :], xp[None, :])[0]
+    _note(f"power: steps {rp['terms']}+{rp['refine_terms']} gpu bound {rp['cert_bound']:.3e} "
+          f"oracle bound {bound:.3e}; cpaa terms {rc['terms']}")
+    assert rp["certified"] == 1 and bound <= TOL
+    assert np.abs(xp - xc).sum() <= 2 * TOL
+    assert rp["terms"] > rc["terms"]
+
+
+@pytest.mark.timeout(600)
+def test_delaunay_2m_rcm_table3(torch_cuda):
+    """The Table 3 stand-in at its full size (2^21 points, the bench's seed):
+    relabelled by reverse Cuthill-McKee (auto), certified to 1e-6 by the oracle's
+    residual for CPAA and the power method, and sampled entries against the
+    oracle's power method."""
+    from paper_2112_01743_amd import Plan
+    torch = torch_cuda
+    g = gg.delaunay(1 << 21, seed=2112010)
+    plan = Plan.from_graph(g, C, time_kernels=1)
+    assert plan.info()["reordered"] == 2
+    p = np.full(g.n, 1.0 / g.n)
+    dp = torch.as_tensor(p, device="cuda")
+    pi, _ = oracle.pagerank_power(g, p, C, tol=1e-9)
+    idx = gg.philox(6).choice(g.n, 3000, replace=False)
+    for name in ("solve", "solve_power"):
+        x, rep = getattr(plan, name)(dp, TOL)
+        x = x.cpu().numpy()
+        bound = _oracle_bound(g, ((1 - C) * p)[None, :], x[None, :])[0]
+        _note(f"{name}: terms {rep['terms']} gpu bound {rep['cert_bound']:.3e} oracle {bound:.3e}")
+        assert rep["certified"] == 1 and bound <= TOL
+        assert np.max(np.abs(x[idx] - pi[idx])) <= TOL + 1e-9
+
+
+@pytest.mark.timeout(600)
 def test_grid_256_sources(torch_cuda):
     from paper_2112_01743_amd import Plan
     torch = torch_cuda

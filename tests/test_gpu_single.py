@@ -229,6 +229,63 @@ def test_rcm_auto_on_random_order_mesh_only(torch_cuda):
     assert Plan.from_graph(grid, C).info()["reordered"] == 0
 
 
+def _lambda_min(g):
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spl
+    d = np.diff(g.row_ptr).astype(float)
+    A = sp.csr_matrix((np.ones(g.nnz), g.col_idx, g.row_ptr), shape=(g.n, g.n))
+    S = sp.diags(1 / np.sqrt(d)) @ A @ sp.diags(1 / np.sqrt(d))
+    return float(spl.eigsh(S, k=1, which="SA", tol=1e-8, return_eigenvectors=False)[0])
+
+
+@pytest.mark.parametrize("case", ["er", "delaunay", "chung_lu"])
+def test_spectral_interval(torch_cuda, case):
+    """Expansion on [a, 1], a from the plan's Lanczos estimate: a sits just below
+    lambda_min(P) on graphs whose spectrum stays away from -1 and the solves need
+    fewer terms; a graph with a bipartite component keeps [-1, 1].  Pinned-term
+    results match the oracle's interval series with the same a."""
+    from paper_2112_01743_amd import Plan
+    g = {"er": lambda: gg.erdos_renyi(20000, 10, seed=12),
+         "delaunay": lambda: gg.delaunay(30000, seed=5),
+         "chung_lu": lambda: gg.chung_lu(30000, 10, 2.1, seed=2112001, dmax=3000)}[case]()
+    lam = _lambda_min(g)
+    plan = Plan.from_graph(g, C, spectral_interval=1)
+    a = plan.info()["spectrum_lo"]
+    _note(f"{case}: lambda_min {lam:.4f}, interval from {a:.4f}")
+    if lam < -0.97:
+        assert a == -1.0
+    else:
+        assert lam - 0.03 <= a <= lam
+    base = Plan.from_graph(g, C)
+    for p in (gg.uniform_personalization(g.n), gg.source_personalization(g.n, [g.n // 2])[0]):
+        x, rep = plan.solve(_dev(torch_cuda, p), 1e-9)
+        _assert_parity(g, p, x.cpu().numpy(), rep, 1e-9)
+        _, rep0 = base.solve(_dev(torch_cuda, p), 1e-9)
+        tot, tot0 = rep["terms"] + rep["refine_terms"], rep0["terms"] + rep0["refine_terms"]
+        _note(f"  terms {tot} (interval) vs {tot0}")
+        assert tot <= tot0 if a == -1.0 else tot < tot0
+    p = gg.source_personalization(g.n, [7])[0]
+    for M in (3, 12):
+        pm = Plan.from_graph(g, C, spectral_interval=1, k_max=M, max_refine=0)
+        x, _ = pm.solve(_dev(torch_cuda, p), 1e-15)
+        ref = oracle.cpaa_interval(g, (1 - C) * p, C, a, M)
+        assert np.abs(x.cpu().numpy() - ref).sum() <= 2e-6, M
+
+
+def test_spectral_interval_batched(torch_cuda):
+    from paper_2112_01743_amd import Plan
+    g = gg.erdos_renyi(3000, 12, seed=4)
+    src = gg.random_sources(g.n, 70, seed=8)
+    Pm = gg.source_personalization(g.n, src)
+    plan = Plan.from_graph(g, C, spectral_interval=1)
+    assert plan.info()["spectrum_lo"] > -0.9
+    X, reps = plan.solve_batched(_dev(torch_cuda, Pm), 1e-8)
+    pi = oracle.pagerank_exact(g, Pm.T, C)
+    err = np.abs(X.cpu().numpy().T - pi).sum(axis=0)
+    assert np.all(reps["certified"] == 1) and err.max() <= 1e-8
+    assert np.all(err <= reps["cert_bound"] * (1 + 1e-9) + 2e-13)
+
+
 def test_autotuned_work_items(torch_cuda):
     """The autotuner times candidate work-item sizes on the first plain solve,
     keeps the fastest, and every later solve uses it."""

@@ -107,6 +107,21 @@ def test_plan_rejects_bad_damping_and_options():
     assert "column_slices" in B.cpaa_last_error()
     assert _plan_status(g.row_ptr, g.col_idx, locality_order=3) == B.CPAA_EINVAL
     assert "locality_order" in B.cpaa_last_error()
+    assert _plan_status(g.row_ptr, g.col_idx, spectral_interval=2) == B.CPAA_EINVAL
+    assert "spectral_interval" in B.cpaa_last_error()
+
+
+def test_spectral_interval_needs_one_graph():
+    rp = np.array([0, 1, 2, 3, 4], dtype=np.int32)
+    ci = np.array([1, 0, 3, 2], dtype=np.int32)
+    gp = np.array([0, 2, 4], dtype=np.int32)
+    csr = B.cpaa_csr(n=4, nnz=4, row_ptr=rp.ctypes.data, col_idx=ci.ctypes.data, num_graphs=2,
+                     graph_ptr=gp.ctypes.data, on_device=0)
+    o = B.cpaa_default_opts()
+    o.spectral_interval = 1
+    h = ctypes.c_void_p()
+    st = B.lib().cpaa_plan(ctypes.byref(csr), 0.85, ctypes.byref(o), ctypes.byref(h))
+    assert st == B.CPAA_EINVAL and "single-graph" in B.cpaa_last_error()
 
 
 def test_plan_rejects_edge_across_graph_boundary():
