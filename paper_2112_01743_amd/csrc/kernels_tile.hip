@@ -243,22 +243,24 @@ struct TileTermEpi {
   };
   __device__ __forceinline__ Pre prefetch(int r, int j) const {
     const size_t idx = (size_t)r * W + j;
-    return {gamma != 0.f || au.a_prev != 0.0 ? zp[idx] : 0.f,
+    // z_{k-1} and acc are read once and written once per launch: streamed with
+    // non-temporal accesses so they do not evict the gathered z_k rows
+    return {gamma != 0.f || au.a_prev != 0.0 ? __builtin_nontemporal_load(zp + idx) : 0.f,
             (want_cert && beta != 0.0) || au.a_cur != 0.0 || gamma_c != 0.f ? zc[idx] : 0.f,
-            au.on ? acc[idx] : 0.0};
+            au.on ? __builtin_nontemporal_load(acc + idx) : 0.0};
   }
   __device__ __forceinline__ void row(int r, int d, int j, float s, float, const Pre& p) {
     const size_t idx = (size_t)r * W + j;
     float y = alpha * (s / static_cast<float>(d));
     if (gamma_c != 0.f) y -= gamma_c * p.zc;
     if (gamma != 0.f) y -= gamma * p.zp;
-    zn[idx] = y;
+    __builtin_nontemporal_store(y, zn + idx);
     if (au.on) {
       // the newest (smallest) term first
       double add = au.a_next * static_cast<double>(y);
       if (au.a_cur != 0.0) add += au.a_cur * static_cast<double>(p.zc);
       if (au.a_prev != 0.0) add += au.a_prev * static_cast<double>(p.zp);
-      acc[idx] = p.acc + add;
+      __builtin_nontemporal_store(p.acc + add, acc + idx);
     }
     if (want_cert)
       cert += static_cast<double>(d) *

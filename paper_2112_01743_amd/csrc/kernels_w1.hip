@@ -1,7 +1,8 @@
 // Single-vector CPAA kernels (one right-hand side), gfx950.
 //
-// Hot loop (Alg. 1, Sec. 4.1, in z-space z_k = D^{-1} T_k(P) b; the power
-// method runs on the same kernels with other epilogue constants, TermShape):
+// Hot loop (Alg. 1, Sec. 4.1, in z-space z_k = D^{-1} T_k(P) b; the expansion
+// on [a, 1] adds an own-row term and the power method runs on the same kernels
+// with other epilogue constants, TermShape):
 //     z_{k+1}(u) = 2 * (sum_{v in N(u)} z_k(v)) / d_u - z_{k-1}(u)
 //     acc(u)    += c_{k+1} * z_{k+1}(u)                     (FP64)
 // (one launch in two or three adds the newest terms at once, from the z_{k-1}
