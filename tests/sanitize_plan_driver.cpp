@@ -1,0 +1,156 @@
+// Drives the host-side work of cpaa_plan (pattern validation, degree-rank and
+// reverse Cuthill-McKee relabelling, column slices, work maps, the Lanczos
+// estimate) on graphs of several shapes and with every option that changes it.
+// Built with AddressSanitizer and UndefinedBehaviorSanitizer on the host code
+// by tests/test_sanitize_host.py.  Without a GPU every valid plan stops at its
+// first device allocation (CPAA_ENOMEM); with one it completes.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <random>
+#include <utility>
+#include <vector>
+
+#include "cpaa.h"
+
+namespace {
+
+struct Graph {
+  int32_t n = 0;
+  std::vector<int32_t> rp, ci;
+};
+
+// symmetric pattern from an edge list (loops dropped, duplicates merged)
+Graph from_edges(int32_t n, std::vector<std::pair<int32_t, int32_t>> e) {
+  std::vector<std::pair<int32_t, int32_t>> arcs;
+  for (auto [u, v] : e)
+    if (u != v) {
+      arcs.push_back({u, v});
+      arcs.push_back({v, u});
+    }
+  std::sort(arcs.begin(), arcs.end());
+  arcs.erase(std::unique(arcs.begin(), arcs.end()), arcs.end());
+  Graph g;
+  g.n = n;
+  g.rp.assign(n + 1, 0);
+  for (auto [u, v] : arcs) ++g.rp[u + 1];
+  for (int32_t u = 0; u < n; ++u) g.rp[u + 1] += g.rp[u];
+  for (auto [u, v] : arcs) g.ci.push_back(v);
+  return g;
+}
+
+Graph star(int32_t n) {
+  std::vector<std::pair<int32_t, int32_t>> e;
+  for (int32_t v = 1; v < n; ++v) e.push_back({0, v});
+  return from_edges(n, e);
+}
+
+Graph cycles(int32_t a, int32_t b) {   // two components
+  std::vector<std::pair<int32_t, int32_t>> e;
+  for (int32_t i = 0; i < a; ++i) e.push_back({i, (i + 1) % a});
+  for (int32_t i = 0; i < b; ++i) e.push_back({a + i, a + (i + 1) % b});
+  return from_edges(a + b, e);
+}
+
+Graph lattice(int32_t s) {
+  std::vector<std::pair<int32_t, int32_t>> e;
+  for (int32_t r = 0; r < s; ++r)
+    for (int32_t c = 0; c < s; ++c) {
+      if (c + 1 < s) e.push_back({r * s + c, r * s + c + 1});
+      if (r + 1 < s) e.push_back({r * s + c, (r + 1) * s + c});
+    }
+  return from_edges(s * s, e);
+}
+
+// heavy-tailed degrees: endpoint u drawn with weight ~ (u+1)^(-1/1.1), plus a
+// path through all vertices so none is isolated; labels shuffled
+Graph power_law(int32_t n, uint32_t seed) {
+  std::mt19937 rng(seed);
+  std::vector<double> w(n);
+  for (int32_t u = 0; u < n; ++u) w[u] = 1.0 / std::pow(u + 1.0, 1.0 / 1.1);
+  std::discrete_distribution<int32_t> pick(w.begin(), w.end());
+  std::vector<int32_t> lab(n);
+  for (int32_t u = 0; u < n; ++u) lab[u] = u;
+  std::shuffle(lab.begin(), lab.end(), rng);
+  std::vector<std::pair<int32_t, int32_t>> e;
+  for (int32_t u = 0; u + 1 < n; ++u) e.push_back({lab[u], lab[u + 1]});
+  for (int64_t k = 0; k < 6LL * n; ++k) e.push_back({lab[pick(rng)], lab[pick(rng)]});
+  return from_edges(n, e);
+}
+
+int failures = 0;
+
+void expect(const char* what, const Graph& g, const cpaa_opts& o, bool valid,
+            cpaa_status want_err = CPAA_OK) {
+  cpaa_csr csr;
+  std::memset(&csr, 0, sizeof(csr));
+  csr.n = g.n;
+  csr.nnz = static_cast<int64_t>(g.ci.size());
+  csr.row_ptr = g.rp.data();
+  csr.col_idx = g.ci.data();
+  cpaa_plan_t p = nullptr;
+  const cpaa_status s = cpaa_plan(&csr, 0.85, &o, &p);
+  bool ok;
+  if (valid) {
+    ok = s == CPAA_OK || s == CPAA_ENOMEM || s == CPAA_EDEVICE;
+    if (s == CPAA_OK) {
+      cpaa_plan_info info;
+      ok = cpaa_plan_info_get(p, &info) == CPAA_OK && info.n == g.n;
+      cpaa_plan_destroy(p);
+    }
+  } else {
+    ok = s == want_err;
+  }
+  std::printf("%-40s status %d %s\n", what, static_cast<int>(s), ok ? "ok" : "UNEXPECTED");
+  if (!ok) ++failures;
+}
+
+}  // namespace
+
+int main() {
+  cpaa_opts base;
+  cpaa_default_opts(&base);
+  base.validate = 1;
+  auto with = [&](auto f) {
+    cpaa_opts o = base;
+    f(o);
+    return o;
+  };
+  const cpaa_opts slices = with([](cpaa_opts& o) { o.column_slices = 8; });
+  const cpaa_opts rcm = with([](cpaa_opts& o) { o.locality_order = 2; });
+  const cpaa_opts interval = with([](cpaa_opts& o) { o.spectral_interval = 1; });
+  const cpaa_opts small_items = with([](cpaa_opts& o) { o.nnz_per_thread = 4; });
+  const cpaa_opts tuned = with([](cpaa_opts& o) { o.autotune = 1; });
+
+  const Graph graphs[] = {star(7), star(30000), cycles(9, 14), lattice(40), power_law(20000, 7),
+                          from_edges(2, {{0, 1}})};
+  const char* names[] = {"star7", "star30000", "two_cycles", "lattice40", "power_law20000", "edge"};
+  for (int i = 0; i < 6; ++i) {
+    char buf[64];
+    const cpaa_opts* os[] = {&base, &slices, &rcm, &interval, &small_items, &tuned};
+    const char* on[] = {"default", "column_slices=8", "locality_order=2", "spectral_interval=1",
+                        "nnz_per_thread=4", "autotune=1"};
+    for (int k = 0; k < 6; ++k) {
+      std::snprintf(buf, sizeof(buf), "%s %s", names[i], on[k]);
+      expect(buf, graphs[i], *os[k], true);
+    }
+  }
+  // invalid patterns are rejected before any device work
+  Graph asym = from_edges(4, {{0, 1}, {1, 2}, {2, 3}});
+  asym.ci[0] = 2;               // row 0 now lists 2 but row 2 does not list 0
+  std::sort(asym.ci.begin() + asym.rp[0], asym.ci.begin() + asym.rp[1]);
+  expect("asymmetric", asym, base, false, CPAA_ENOTSYM);
+  Graph loop;                   // 0-1-2 path plus a loop at 0 (still symmetric)
+  loop.n = 3;
+  loop.rp = {0, 2, 4, 5};
+  loop.ci = {0, 1, 0, 2, 1};
+  expect("self loop", loop, base, false, CPAA_ESELFLOOP);
+  Graph range = from_edges(3, {{0, 1}, {1, 2}});
+  range.ci.back() = 7;
+  expect("column out of range", range, base, false, CPAA_EPATTERN);
+  Graph iso = from_edges(4, {{0, 1}, {1, 2}});
+  expect("isolated vertex", iso, base, false, CPAA_EISOLATED);
+  std::printf("%s\n", failures ? "FAILED" : "ALL OK");
+  return failures ? 1 : 0;
+}
