@@ -37,7 +37,7 @@ def _dev(torch, a):
     return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
 
 
-@settings(max_examples=60, deadline=None, derandomize=True, database=None,
+@settings(max_examples=200, deadline=None, derandomize=True, database=None,
           suppress_health_check=[HealthCheck.too_slow, HealthCheck.function_scoped_fixture])
 @given(g=graphs(), c=st.floats(0.05, 0.9), opt=st.sampled_from(OPTIONS),
        pseed=st.integers(0, 2**31 - 1), method=st.sampled_from(["solve", "solve_power"]))
