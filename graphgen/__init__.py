@@ -283,6 +283,30 @@ def delaunay(n: int, seed) -> CSR:
     return g
 
 
+def directed_random(n: int, avg_deg: float, dangling_frac: float, seed) -> CSR:
+    """Random directed graph: each vertex, except a random dangling_frac of them,
+    sends edges to ~avg_deg/(1 - dangling_frac) random other vertices (the
+    out-degree of a non-dangling vertex is at least 1).  Returned by targets:
+    row u lists the sources v of the edges v -> u, sorted; no self loops, no
+    duplicates.  Rows may be empty (vertices without in-edges)."""
+    rng = philox(seed)
+    dangling = rng.random(n) < dangling_frac
+    src_ids = np.nonzero(~dangling)[0]
+    k = 1 + rng.poisson(max(avg_deg / max(1.0 - dangling_frac, 1e-9) - 1.0, 0.0), src_ids.size)
+    v = np.repeat(src_ids, k).astype(np.int64)
+    u = rng.integers(0, n, v.size)
+    keep = u != v
+    u, v = u[keep], v[keep]
+    key = np.unique(u * n + v)
+    u, v = key // n, key - (key // n) * n
+    counts = np.bincount(u, minlength=n)
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=row_ptr[1:])
+    g = CSR(n=n, row_ptr=row_ptr.astype(np.int32), col_idx=v.astype(np.int32))
+    g.meta.update(model="directed_random", directed=True, dangling=int(dangling.sum()))
+    return g
+
+
 def uneven_batch(num_graphs: int, seed, n_lo: int = 100, n_hi: int = 5000,
                  deg_lo: float = 4.0, deg_hi: float = 32.0, gamma_lo: float = 2.1,
                  gamma_hi: float = 3.0) -> CSR:

@@ -41,7 +41,8 @@ __all__ = [
     "chebyshev_interval_coefficient_integral", "convergence_rate", "mass_error", "accumulated_mass", "total_mass",
     "series_tail", "terms_for_mass_error", "apriori_error_bound", "terms_for_apriori",
     "adjacency", "transition_matrix", "transition_dense", "pagerank_exact",
-    "pagerank_power", "power_method", "cpaa", "cpaa_interval", "cpaa_alg1_global", "residual", "residual_l1_bound",
+    "pagerank_power", "power_method", "transition_directed", "pagerank_directed_exact",
+    "power_method_directed", "cpaa", "cpaa_interval", "cpaa_alg1_global", "residual", "residual_l1_bound",
     "series_residual", "l1_error", "max_error", "max_relative_error",
 ]
 
@@ -215,6 +216,42 @@ def power_method(g, p: np.ndarray, c: float, t: int, return_all: bool = False):
     seq = [x]
     for _ in range(t):
         x = c * (P @ x) + (1.0 - c) * p * x.sum(axis=0)
+        seq.append(x)
+    return seq if return_all else x
+
+
+def transition_directed(g):
+    """For a directed graph (row u of the pattern lists the v with v -> u, so
+    a_uv = 1 iff v -> u as in Sec. 2.1): P = A D^{-1} on the columns of vertices
+    with out-edges (D the out-degrees, column sums of A), zero columns at
+    dangling vertices, and the dangling indicator d of Sec. 2.1.  Dense."""
+    A = adjacency(g).toarray()
+    dout = A.sum(axis=0)
+    P = np.zeros_like(A)
+    nz = dout > 0
+    P[:, nz] = A[:, nz] / dout[nz]
+    return P, (~nz).astype(np.float64)
+
+
+def pagerank_directed_exact(g, p: np.ndarray, c: float) -> np.ndarray:
+    """PageRank of a directed graph by a dense FP64 solve: with P' = P + p d^T
+    (Sec. 2.1), pi = P''pi, P'' = cP' + (1-c) p e^T, sum pi = 1 (eq. 2.1) is
+    (I - cP') pi = (1-c) p."""
+    P, d = transition_directed(g)
+    p = np.asarray(p, dtype=np.float64)
+    Pp = P + np.outer(p, d)
+    return np.linalg.solve(np.eye(g.n) - c * Pp, (1.0 - c) * p)
+
+
+def power_method_directed(g, p: np.ndarray, c: float, t: int, return_all: bool = False):
+    """The power method on a directed graph: x_{k+1} = P'' x_k from x_0 = p with
+    P'' = c(P + p d^T) + (1-c) p e^T applied as written (eq. 2.1, Sec. 2.1)."""
+    P, d = transition_directed(g)
+    p = np.asarray(p, dtype=np.float64)
+    x = p.copy()
+    seq = [x]
+    for _ in range(t):
+        x = c * (P @ x + p * (d @ x)) + (1.0 - c) * p * x.sum()
         seq.append(x)
     return seq if return_all else x
 
