@@ -125,6 +125,16 @@ typedef struct {
                              fewer terms when the spectrum stays away from -1.  Results are
                              certified as always; a wrong a only slows convergence.  Single-graph
                              plans only (else CPAA_EINVAL); the power method ignores it. */
+  int32_t directed;       /* 1: a directed graph (Sec. 2.1: a_uv = 1 iff v -> u): row u lists the
+                             vertices v with an edge v -> u, columns sorted, no duplicates or
+                             self loops; symmetry is not required and rows may be empty.  The
+                             out-degree of v is the number of rows listing v; a vertex without
+                             out-edges is dangling, and P' = P + p d^T sends its mass along p
+                             (Sec. 2.1).  CPAA's expansion needs the real spectrum of an
+                             undirected graph (Sec. 3), so such a plan is solved by
+                             cpaa_solve_power only (single vector, x0 = NULL); every other solve
+                             call returns CPAA_EINVAL.  Needs one graph; column slices, RCM
+                             and the spectral interval are not used. */
 } cpaa_opts;
 
 /* Per-solve report (one per right-hand side in batched calls, one per graph in

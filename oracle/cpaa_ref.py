@@ -224,13 +224,13 @@ def transition_directed(g):
     """For a directed graph (row u of the pattern lists the v with v -> u, so
     a_uv = 1 iff v -> u as in Sec. 2.1): P = A D^{-1} on the columns of vertices
     with out-edges (D the out-degrees, column sums of A), zero columns at
-    dangling vertices, and the dangling indicator d of Sec. 2.1.  Dense."""
-    A = adjacency(g).toarray()
-    dout = A.sum(axis=0)
-    P = np.zeros_like(A)
+    dangling vertices (sparse), and the dangling indicator d of Sec. 2.1."""
+    A = adjacency(g)
+    dout = np.asarray(A.sum(axis=0)).ravel()
+    inv = np.zeros(g.n)
     nz = dout > 0
-    P[:, nz] = A[:, nz] / dout[nz]
-    return P, (~nz).astype(np.float64)
+    inv[nz] = 1.0 / dout[nz]
+    return (A @ sp.diags(inv)).tocsr(), (~nz).astype(np.float64)
 
 
 def pagerank_directed_exact(g, p: np.ndarray, c: float) -> np.ndarray:
@@ -239,7 +239,7 @@ def pagerank_directed_exact(g, p: np.ndarray, c: float) -> np.ndarray:
     (I - cP') pi = (1-c) p."""
     P, d = transition_directed(g)
     p = np.asarray(p, dtype=np.float64)
-    Pp = P + np.outer(p, d)
+    Pp = P.toarray() + np.outer(p, d)
     return np.linalg.solve(np.eye(g.n) - c * Pp, (1.0 - c) * p)
 
 

@@ -38,7 +38,7 @@ class cpaa_opts(ctypes.Structure):
                 ("io_device", ctypes.c_int32), ("time_kernels", ctypes.c_int32),
                 ("xcd_remap", ctypes.c_int32), ("autotune", ctypes.c_int32),
                 ("column_slices", ctypes.c_int32), ("locality_order", ctypes.c_int32),
-                ("spectral_interval", ctypes.c_int32)]
+                ("spectral_interval", ctypes.c_int32), ("directed", ctypes.c_int32)]
 
 
 class cpaa_report(ctypes.Structure):

@@ -120,6 +120,11 @@ struct Workspace {
   int* terms = nullptr;          // [tiles]
   double* series_cert = nullptr; // [cols]
   float* part = nullptr;         // column-sliced term: [kSlices][n] FP32 partial row sums
+  double* dang = nullptr;        // directed plans: [5][kSlots] dangling mass of the increment
+                                 // in z[0..2], then of x and |x| for the residual
+  double* wdir = nullptr;        // directed plans: [n] FP64 D_out^+ x for the residual
+  const double* dir_x0 = nullptr;  // directed power method: start of the series in progress
+  double dir_x0_scale = 1.0;       //   x_0 = dir_x0_scale * dir_x0
   float* split_f = nullptr;      // [split slots * W] FP32 partial sums
   double* split_d = nullptr;     // [split slots * W] FP64 partial sums (residual)
   int* split_count = nullptr;    // [split slots] arrivals
@@ -156,6 +161,8 @@ struct cpaa_plan_s {
   int32_t* d_ci_w1 = nullptr;
   int32_t* d_perm = nullptr;         // [n] single-vector label -> caller's label, or null
   int reordered = 0;                 // 0 caller's labels, 1 column slices, 2 reverse Cuthill-McKee
+  bool directed = false;             // rows list in-neighbours; solved by the power method only
+  int32_t* d_dout = nullptr;         // directed plans: [n] out-degrees
   bool sliced = false;
   cpaa::SlicedMap slc;
 
@@ -261,6 +268,18 @@ hipError_t check_series(const cpaa_plan_s* pl, Workspace& ws, const double* cert
 hipError_t residual_w1(const cpaa_plan_s* pl, Workspace& ws, hipStream_t st);
 hipError_t finalize_w1(const cpaa_plan_s* pl, Workspace& ws, double* x, double scale,
                        hipStream_t st);
+
+// ---- directed graphs: the power method in x-space (kernels_w1.hip) ----
+// acc (+)= x_0 = scale * src, z_0 = D_out^+ x_0, dangling mass of x_0 into
+// dang[0]; b = (1-c) src when store_b.  Statistics as init_w1's ([0], [4], [5]).
+hipError_t init_dir(const cpaa_plan_s* pl, Workspace& ws, const double* src, double scale,
+                    bool add, bool store_b, hipStream_t st);
+hipError_t term_dir(const cpaa_plan_s* pl, Workspace& ws, int cur, int prev, int next,
+                    bool first, const AccUpdate& au, double* cert_slot, const int* done,
+                    hipStream_t st);
+hipError_t residual_dir(const cpaa_plan_s* pl, Workspace& ws, hipStream_t st);
+hipError_t finalize_dir(const cpaa_plan_s* pl, Workspace& ws, double* x, double scale,
+                        hipStream_t st);
 
 // ---- tiled path (W right-hand sides per tile) ----
 hipError_t init_tile(const cpaa_plan_s* pl, Workspace& ws, const double* P, int64_t ldp, int B,

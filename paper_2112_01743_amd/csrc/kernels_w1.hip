@@ -494,6 +494,219 @@ int elem_grid(int64_t n) {
   return static_cast<int>(g < 8192 ? (g < 1 ? 1 : g) : 8192);
 }
 
+// ---------------------------------------------------------------------------
+// Directed graphs (Sec. 2.1): row u lists the v with v -> u, P = A D_out^+ on
+// the columns with out-edges and P' = P + p d^T sends a dangling vertex's mass
+// along p.  The power method x_{t+1} = cP'x_t + (1-c)p runs in x-space as x_0
+// plus its increments delta_t = (cP')^t delta_0, delta_0 = c(P' - I)x_0:
+//     delta_{t+1}(u) = c sum_{v -> u} delta_t(v)/dout_v + c m_t p_u,
+// m_t the dangling mass of delta_t.  The SpMV gathers z_t = D_out^+ delta_t
+// (FP32, zero at dangling vertices); m_t is reduced into dang[buffer of z_t]
+// by the launch that forms delta_t and read by the next one.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double slot_sum(const double* __restrict__ slots) {
+  double m = 0.0;
+  for (int k = 0; k < kSlots; ++k) m += slots[k];
+  return m;
+}
+
+// acc (+)= x_0 = scale * src; z_0 = D_out^+ x_0; dangling mass of x_0 -> dang0.
+__global__ __launch_bounds__(kWG) void k_init_dir(int n, const int* __restrict__ dout,
+                                                  const double* __restrict__ src, double scale,
+                                                  double one_minus_c, int add, int store_b,
+                                                  double* __restrict__ b, float* __restrict__ z0,
+                                                  double* __restrict__ acc,
+                                                  double* __restrict__ dang0,
+                                                  double* __restrict__ stat_slots) {
+  double f_sum = 0, f_neg = 0, f_bad = 0, f_dang = 0;
+  for (int u = blockIdx.x * kWG + threadIdx.x; u < n; u += gridDim.x * kWG) {
+    const double p = src[u];
+    const double x = scale * p;
+    const int d = dout[u];
+    if (store_b) b[u] = one_minus_c * p;
+    z0[u] = d > 0 ? static_cast<float>(x / d) : 0.f;
+    acc[u] = add ? acc[u] + x : x;
+    if (d == 0) f_dang += x;
+    f_sum += p;
+    f_neg += (p < 0.0) ? 1.0 : 0.0;
+    f_bad += isfinite(p) ? 0.0 : 1.0;
+  }
+  const double s0 = block_sum256(f_sum), s4 = block_sum256(f_neg);
+  const double s5 = block_sum256(f_bad), sd = block_sum256(f_dang);
+  if (threadIdx.x == 0) {
+    double* o = stat_slots + (size_t)(blockIdx.x % kSlots) * kStat;
+    atomic_add(&o[0], s0);
+    if (s4 != 0.0) atomic_add(&o[4], s4);
+    if (s5 != 0.0) atomic_add(&o[5], s5);
+    if (sd != 0.0) atomic_add(&dang0[blockIdx.x % kSlots], sd);
+  }
+}
+
+struct DirTermEpi {
+  const double* __restrict__ b;      // (1-c) p
+  const double* __restrict__ x0;     // first launch only: x_0 = x0_scale * x0
+  const int* __restrict__ dout;
+  float* __restrict__ zn;
+  double* __restrict__ acc;
+  double c, m, p_scale, x0_scale;
+  int want_cert;
+  double cert, mnext;
+  __device__ __forceinline__ void row(int r, int, float s, float) {
+    double y = c * static_cast<double>(s) + c * m * (p_scale * b[r]);
+    if (x0 != nullptr) y -= c * x0_scale * x0[r];
+    const int d = dout[r];
+    zn[r] = d > 0 ? static_cast<float>(y / d) : 0.f;
+    acc[r] += y;
+    if (d == 0) mnext += y;
+    // (1-c)|delta|, the scale of the undirected power method's certificate
+    if (want_cert) cert += (1.0 - c) * fabs(y);
+  }
+};
+
+struct DirArgs {
+  const int* rp;
+  const int* ci;
+  const WorkItem* items;
+  const int* dout;
+  const double* b;
+  const double* x0;
+  double x0_scale;
+  const float* zc;
+  float* zn;
+  double* acc;
+  const double* dang_cur;   // [kSlots] dangling mass of the increment in zc
+  double* dang_next;        // [kSlots] of the increment this launch forms (zero on entry)
+  double* dang_clear;       // [kSlots] cleared here for the launch after next
+  double c;
+  double* cert;
+  const int* done;
+  float* split_part;
+  int* split_count;
+  const int* split_nchunks;
+  int xcd;
+};
+
+template <int NPT>
+__global__ __launch_bounds__(kWG) void k_term_dir(DirArgs a) {
+  if (a.done != nullptr && *a.done) return;
+  __shared__ double m_sh;
+  if (threadIdx.x == 0) m_sh = slot_sum(a.dang_cur);
+  if (blockIdx.x == 0 && threadIdx.x < kSlots) a.dang_clear[threadIdx.x] = 0.0;
+  __syncthreads();
+  const int lb = xcd_logical(blockIdx.x, gridDim.x, a.xcd);
+  DirTermEpi epi{a.b, a.x0, a.dout, a.zn, a.acc, a.c, m_sh, 1.0 / (1.0 - a.c), a.x0_scale,
+                 a.cert != nullptr, 0.0, 0.0};
+  spmv_item<float, NPT, false>(a.items[lb], a.rp, a.ci, a.zc, a.split_part, a.split_count,
+                               a.split_nchunks, epi);
+  const double cs = block_sum256(epi.cert);
+  const double ms = block_sum256(epi.mnext);
+  if (threadIdx.x == 0) {
+    if (a.cert != nullptr && cs != 0.0) atomic_add(&a.cert[lb % kSlots], cs);
+    if (ms != 0.0) atomic_add(&a.dang_next[lb % kSlots], ms);
+  }
+}
+
+// w = D_out^+ x for the residual; dangling mass of x and of |x| -> dx, dxa.
+__global__ __launch_bounds__(kWG) void k_dir_w(int n, const int* __restrict__ dout,
+                                               const double* __restrict__ acc,
+                                               double* __restrict__ w, double* __restrict__ dx,
+                                               double* __restrict__ dxa) {
+  double f = 0, fa = 0;
+  for (int u = blockIdx.x * kWG + threadIdx.x; u < n; u += gridDim.x * kWG) {
+    const int d = dout[u];
+    const double x = acc[u];
+    w[u] = d > 0 ? x / d : 0.0;
+    if (d == 0) {
+      f += x;
+      fa += fabs(x);
+    }
+  }
+  const double s = block_sum256(f), sa = block_sum256(fa);
+  if (threadIdx.x == 0) {
+    if (s != 0.0) atomic_add(&dx[blockIdx.x % kSlots], s);
+    if (sa != 0.0) atomic_add(&dxa[blockIdx.x % kSlots], sa);
+  }
+}
+
+// r = b - x + c (A w) + c m_x p, with an upper bound on the FP64 rounding of
+// its evaluation: (k + 5) u (|b| + |x| + c sum|w_v| + c |m_x| p) for a row of
+// k entries (w_v = x_v/dout_v adds one rounding each), plus the rounding of the
+// n-term sum m_x: c p n u sum|x_dangling|.
+struct DirResidEpi {
+  const double* __restrict__ acc;
+  const double* __restrict__ b;
+  double* __restrict__ r_out;
+  double c, mx, mxa, p_scale, nu;
+  double f_abs, f_max, f_mass, f_round, f_bad;
+  __device__ __forceinline__ void row(int r, int k, double s, double sa) {
+    const double x = acc[r];
+    const double bb = b[r];
+    const double p = p_scale * bb;
+    const double res = bb - x + c * s + c * mx * p;
+    r_out[r] = res;
+    const double ar = fabs(res);
+    if (!isfinite(res)) f_bad += 1.0;
+    f_abs += ar;
+    f_max = fmax(f_max, ar);
+    f_mass += x;
+    f_round += (static_cast<double>(k) + 5.0) * 0x1p-53 *
+                   (fabs(bb) + fabs(x) + c * sa + c * fabs(mx) * p) +
+               c * p * nu * mxa;
+  }
+};
+
+struct DirResidArgs {
+  const int* rp;
+  const int* ci;
+  const WorkItem* items;
+  const double* w;
+  const double* acc;
+  const double* b;
+  double* r;
+  const double* dx;
+  const double* dxa;
+  double c, nu;
+  double* stat_slots;
+  double* split_part;
+  int* split_count;
+  const int* split_nchunks;
+  int xcd;
+};
+
+template <int NPT>
+__global__ __launch_bounds__(kWG) void k_resid_dir(DirResidArgs a) {
+  __shared__ double m_sh[2];
+  if (threadIdx.x == 0) {
+    m_sh[0] = slot_sum(a.dx);
+    m_sh[1] = slot_sum(a.dxa);
+  }
+  __syncthreads();
+  const int lb = xcd_logical(blockIdx.x, gridDim.x, a.xcd);
+  DirResidEpi epi{a.acc, a.b, a.r, a.c, m_sh[0], m_sh[1], 1.0 / (1.0 - a.c), a.nu,
+                  0.0, 0.0, 0.0, 0.0, 0.0};
+  spmv_item<double, NPT, true>(a.items[lb], a.rp, a.ci, a.w, a.split_part, a.split_count,
+                               a.split_nchunks, epi);
+  const double s_abs = block_sum256(epi.f_abs);
+  const double s_max = block_max256(epi.f_max);
+  const double s_mass = block_sum256(epi.f_mass);
+  const double s_round = block_sum256(epi.f_round);
+  const double s_bad = block_sum256(epi.f_bad);
+  if (threadIdx.x == 0) {
+    double* o = a.stat_slots + (size_t)(lb % kSlots) * kStat;
+    atomic_add(&o[0], s_abs);
+    atomic_max_nonneg(&o[1], s_max);
+    atomic_add(&o[3], s_mass);
+    atomic_add(&o[4], s_round);
+    if (s_bad != 0.0) atomic_add(&o[5], s_bad);
+  }
+}
+
+__global__ __launch_bounds__(kWG) void k_finalize_dir(int n, const double* __restrict__ acc,
+                                                      double scale, double* __restrict__ x) {
+  for (int u = blockIdx.x * kWG + threadIdx.x; u < n; u += gridDim.x * kWG) x[u] = scale * acc[u];
+}
+
 }  // namespace
 
 hipError_t init_w1(const cpaa_plan_s* pl, Workspace& ws, const double* src, double scale,
@@ -609,6 +822,90 @@ hipError_t finalize_w1(const cpaa_plan_s* pl, Workspace& ws, double* x, double s
                        hipStream_t st) {
   hipLaunchKernelGGL(k_finalize_w1, dim3(elem_grid(pl->n)), dim3(kWG), 0, st, pl->n,
                      pl->d_rp_w1, pl->d_perm, ws.acc, scale, x);
+  return hipGetLastError();
+}
+
+hipError_t init_dir(const cpaa_plan_s* pl, Workspace& ws, const double* src, double scale,
+                    bool add, bool store_b, hipStream_t st) {
+  hipLaunchKernelGGL(k_init_dir, dim3(elem_grid(pl->n)), dim3(kWG), 0, st, pl->n, pl->d_dout, src,
+                     scale, 1.0 - pl->c, add ? 1 : 0, store_b ? 1 : 0, ws.b, ws.z[0], ws.acc,
+                     ws.dang, ws.stat_slots);
+  return hipGetLastError();
+}
+
+hipError_t term_dir(const cpaa_plan_s* pl, Workspace& ws, int cur, int prev, int next, bool first,
+                    const AccUpdate&, double* cert_slot, const int* done, hipStream_t st) {
+  // every launch adds its increment to acc (x-space), so any stop leaves
+  // acc = x_{k+1}; grouped updates do not apply here
+  DirArgs a;
+  a.rp = pl->d_row_ptr;
+  a.ci = pl->d_col_idx;
+  a.items = pl->d_items;
+  a.dout = pl->d_dout;
+  a.b = ws.b;
+  a.x0 = first ? ws.dir_x0 : nullptr;
+  a.x0_scale = ws.dir_x0_scale;
+  a.zc = ws.z[cur];
+  a.zn = ws.z[next];
+  a.acc = ws.acc;
+  a.dang_cur = ws.dang + (size_t)cur * kSlots;
+  a.dang_next = ws.dang + (size_t)next * kSlots;
+  a.dang_clear = ws.dang + (size_t)prev * kSlots;
+  a.c = pl->c;
+  a.cert = cert_slot;
+  a.done = done;
+  a.split_part = ws.split_f;
+  a.split_count = ws.split_count;
+  a.split_nchunks = pl->d_split_nchunks;
+  a.xcd = pl->xcd_remap;
+  const dim3 grid(pl->n_items);
+  switch (pl->npt) {
+    case 4: hipLaunchKernelGGL(k_term_dir<4>, grid, dim3(kWG), 0, st, a); break;
+    case 16: hipLaunchKernelGGL(k_term_dir<16>, grid, dim3(kWG), 0, st, a); break;
+    case 32: hipLaunchKernelGGL(k_term_dir<32>, grid, dim3(kWG), 0, st, a); break;
+    default: hipLaunchKernelGGL(k_term_dir<8>, grid, dim3(kWG), 0, st, a); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t residual_dir(const cpaa_plan_s* pl, Workspace& ws, hipStream_t st) {
+  double* dx = ws.dang + 3 * kSlots;
+  double* dxa = ws.dang + 4 * kSlots;
+  hipError_t e = fill_f64(dx, 0.0, 2 * kSlots, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_dir_w, dim3(elem_grid(pl->n)), dim3(kWG), 0, st, pl->n, pl->d_dout, ws.acc,
+                     ws.wdir, dx, dxa);
+  DirResidArgs a;
+  a.rp = pl->d_row_ptr;
+  a.ci = pl->d_col_idx;
+  a.items = pl->d_items;
+  a.w = ws.wdir;
+  a.acc = ws.acc;
+  a.b = ws.b;
+  a.r = ws.r;
+  a.dx = dx;
+  a.dxa = dxa;
+  a.c = pl->c;
+  a.nu = (static_cast<double>(pl->n) + 2.0) * 0x1p-53;
+  a.stat_slots = ws.stat_slots + (size_t)kSlots * ws.cols * kStat;   // residual phase
+  a.split_part = ws.split_d;
+  a.split_count = ws.split_count;
+  a.split_nchunks = pl->d_split_nchunks;
+  a.xcd = pl->xcd_remap;
+  const dim3 grid(pl->n_items);
+  switch (pl->npt) {
+    case 4: hipLaunchKernelGGL(k_resid_dir<4>, grid, dim3(kWG), 0, st, a); break;
+    case 16: hipLaunchKernelGGL(k_resid_dir<16>, grid, dim3(kWG), 0, st, a); break;
+    case 32: hipLaunchKernelGGL(k_resid_dir<32>, grid, dim3(kWG), 0, st, a); break;
+    default: hipLaunchKernelGGL(k_resid_dir<8>, grid, dim3(kWG), 0, st, a); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t finalize_dir(const cpaa_plan_s* pl, Workspace& ws, double* x, double scale,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_finalize_dir, dim3(elem_grid(pl->n)), dim3(kWG), 0, st, pl->n, ws.acc,
+                     scale, x);
   return hipGetLastError();
 }
 

@@ -26,7 +26,8 @@
 namespace cpaa {
 
 void free_workspace(Workspace& ws) {
-  void* ptrs[] = {ws.z[0], ws.z[1], ws.z[2], ws.acc, ws.part, ws.b, ws.r, ws.slots, ws.stat_slots,
+  void* ptrs[] = {ws.z[0], ws.z[1], ws.z[2], ws.acc, ws.part, ws.dang, ws.wdir, ws.b, ws.r,
+                  ws.slots, ws.stat_slots,
                   ws.stat, ws.done, ws.terms, ws.series_cert, ws.split_f, ws.split_d,
                   ws.split_count, ws.active, ws.plain, ws.col_scale};
   for (void* p : ptrs)
@@ -67,6 +68,10 @@ cpaa_status ensure_workspace(cpaa_plan_s* pl, Workspace& ws, int W, int tiles) {
   ok = ok && alloc((void**)&ws.acc, ws.vec_elems * sizeof(double));
   if (W == 1 && pl->sliced)
     ok = ok && alloc((void**)&ws.part, (size_t)kSlices * pl->n * sizeof(float));
+  if (W == 1 && pl->directed) {
+    ok = ok && alloc((void**)&ws.dang, (size_t)5 * kSlots * sizeof(double));
+    ok = ok && alloc((void**)&ws.wdir, (size_t)pl->n * sizeof(double));
+  }
   ok = ok && alloc((void**)&ws.b, ws.vec_elems * sizeof(double));
   ok = ok && alloc((void**)&ws.r, ws.vec_elems * sizeof(double));
   ok = ok && alloc((void**)&ws.slots, (size_t)(kMaxTerms + 2) * kSlots * ws.cols * sizeof(double));
@@ -358,9 +363,19 @@ using namespace cpaa;
 
 namespace {
 
+cpaa_status solve_directed(cpaa_plan_t pl, const double* p, double tol, double* x,
+                           cpaa_report* rep, void* stream);
+
 cpaa_status solve_single(cpaa_plan_t pl, const double* p, double tol, const double* x0, double* x,
                          cpaa_report* rep, void* stream, Method method) {
   set_error("");
+  if (pl && pl->directed) {
+    if (method != Method::kPower || x0) {
+      set_error("a directed plan is solved by cpaa_solve_power without x0");
+      return CPAA_EINVAL;
+    }
+    return solve_directed(pl, p, tol, x, rep, stream);
+  }
   if (!pl || !p || !x) {
     set_error("cpaa_solve: null argument");
     return CPAA_EINVAL;
@@ -534,6 +549,10 @@ cpaa_status solve_batched(cpaa_plan_t pl, int32_t B, const double* P, int64_t ld
                           const double* X0, int64_t ldx0, double* X, int64_t ldx,
                           cpaa_report* reps, void* stream, Method method) {
   set_error("");
+  if (pl && pl->directed) {
+    set_error("a directed plan is solved by cpaa_solve_power (single vector)");
+    return CPAA_EINVAL;
+  }
   if (!pl || !P || !X || B <= 0) {
     set_error("cpaa_solve_batched: null argument or B <= 0");
     return CPAA_EINVAL;
@@ -773,6 +792,108 @@ cpaa_status solve_batched(cpaa_plan_t pl, int32_t B, const double* P, int64_t ld
   }
   if (!all_ok) {
     set_error("tolerance not certified for every column");
+    return CPAA_ENOCONV;
+  }
+  return CPAA_OK;
+}
+
+// The power method on a directed plan (kernels_w1.hip, x-space): the series
+// runs from x_0 = p; a correction runs the same iteration on b = r from
+// x_0 = r/(1-c); certification as for the other solves (FP64 residual of P'').
+cpaa_status solve_directed(cpaa_plan_t pl, const double* p, double tol, double* x,
+                           cpaa_report* rep, void* stream) {
+  if (!p || !x) {
+    set_error("cpaa_solve_power: null argument");
+    return CPAA_EINVAL;
+  }
+  if (!(tol > 0.0) || !std::isfinite(tol)) {
+    set_error("tol must be positive and finite");
+    return CPAA_EINVAL;
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  cpaa_status s = ensure_workspace(pl, pl->ws1, 1, 1);
+  if (s != CPAA_OK) return s;
+  Workspace& ws = pl->ws1;
+  ws.method = Method::kPower;
+  const int n = pl->n;
+  const double c = pl->c;
+  TempDev tp, tx;
+  const double* dp = p;
+  double* dx = x;
+  if (!pl->opts.io_device) {
+    if (hipMalloc(&tp.p, n * sizeof(double)) != hipSuccess ||
+        hipMalloc(&tx.p, n * sizeof(double)) != hipSuccess) {
+      (void)hipGetLastError();
+      set_error("device allocation for host I/O failed");
+      return CPAA_ENOMEM;
+    }
+    CPAA_HIP(hipMemcpyAsync(tp.p, p, n * sizeof(double), hipMemcpyHostToDevice, st));
+    dp = static_cast<const double*>(tp.p);
+    dx = static_cast<double*>(tx.p);
+  }
+  TermTimer timer{pl, pl->opts.time_kernels != 0};
+  std::vector<int> series_terms;
+  cpaa_report R;
+  std::memset(&R, 0, sizeof(R));
+  CPAA_HIP(hipEventRecord(pl->ev_begin, st));
+  CPAA_HIP(fill_f64(ws.stat_slots, 0.0, (size_t)2 * kSlots * ws.cols * kStat, st));
+  CPAA_HIP(fill_f64(ws.dang, 0.0, 3 * kSlots, st));
+  CPAA_HIP(init_dir(pl, ws, dp, 1.0, false, true, st));
+  if ((s = read_back(ws, st)) != CPAA_OK) return s;
+  if ((s = check_p_stats(ws, 0)) != CPAA_OK) return s;
+  const double target_main = 0.5 * tol;
+  ws.dir_x0 = dp;
+  ws.dir_x0_scale = 1.0;
+  int k_cap = series_cap(pl, ws, 0.0, (1.0 - c) * stat_at(ws, 0, 0, 0), target_main);
+  if ((s = run_series(pl, ws, term_dir, 0, k_cap, 0, target_main, timer, st)) != CPAA_OK) return s;
+  series_terms.push_back(k_cap);
+  double bound = 0.0;
+  for (;;) {
+    CPAA_HIP(fill_f64(ws.stat_slots + (size_t)kSlots * ws.cols * kStat, 0.0,
+                      (size_t)kSlots * ws.cols * kStat, st));
+    CPAA_HIP(residual_dir(pl, ws, st));
+    if ((s = read_back(ws, st)) != CPAA_OK) return s;
+    HostView hv = host_view(ws);
+    const int ran = hv.done[0] ? hv.terms[0] : series_terms.back();
+    series_terms.back() = ran;
+    if (series_terms.size() == 1) R.terms = ran;
+    else R.refine_terms += ran;
+    R.series_cert = hv.series_cert[0];
+    R.resid_l1 = stat_at(ws, 1, 0, 0);
+    R.resid_max = stat_at(ws, 1, 0, 1);
+    R.mass = stat_at(ws, 1, 0, 3);
+    bound = rigorous_bound(pl, R.resid_l1, stat_at(ws, 1, 0, 4), R.mass);
+    if (bound <= tol || !std::isfinite(bound) || R.refinements >= pl->opts.max_refine) break;
+    // correction: the same iteration on b' = r from x_0 = r/(1-c), added to acc
+    const double target_ref = 0.25 * tol;
+    const int kr = series_cap(pl, ws, 0.0, R.resid_l1, target_ref);
+    CPAA_HIP(fill_f64(ws.dang, 0.0, 3 * kSlots, st));
+    CPAA_HIP(init_dir(pl, ws, ws.r, 1.0 / (1.0 - c), true, false, st));
+    ws.dir_x0 = ws.r;
+    ws.dir_x0_scale = 1.0 / (1.0 - c);
+    R.refinements++;
+    series_terms.push_back(kr);
+    if ((s = run_series(pl, ws, term_dir, (int)series_terms.size() - 1, kr, 0, target_ref, timer,
+                        st)) != CPAA_OK)
+      return s;
+  }
+  R.cert_bound = bound;
+  R.certified = (bound <= tol) ? 1 : 0;
+  const double scale = pl->opts.normalize ? 1.0 / R.mass : 1.0;
+  CPAA_HIP(finalize_dir(pl, ws, dx, scale, st));
+  CPAA_HIP(hipEventRecord(pl->ev_end, st));
+  if (!pl->opts.io_device)
+    CPAA_HIP(hipMemcpyAsync(x, dx, n * sizeof(double), hipMemcpyDeviceToHost, st));
+  CPAA_HIP(hipStreamSynchronize(st));
+  float ms = 0.f;
+  CPAA_HIP(hipEventElapsedTime(&ms, pl->ev_begin, pl->ev_end));
+  R.ms_total = ms;
+  timer.total(series_terms, &R.ms_terms, &R.term_launches);
+  if (pl->opts.normalize) R.mass = 1.0;
+  R.edges = pl->nnz * static_cast<int64_t>(R.terms + R.refine_terms);
+  if (rep) *rep = R;
+  if (!R.certified) {
+    set_error("tolerance not certified: bound " + std::to_string(bound));
     return CPAA_ENOCONV;
   }
   return CPAA_OK;

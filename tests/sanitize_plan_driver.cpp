@@ -136,6 +136,15 @@ int main() {
       expect(buf, graphs[i], *os[k], true);
     }
   }
+  // a directed graph: asymmetric, with an empty row and a dangling vertex
+  {
+    Graph d;
+    d.n = 4;
+    d.rp = {0, 0, 1, 3, 4};          // edges 0->1, 0->2, 1->2, 2->3; vertex 3 dangling
+    d.ci = {0, 0, 1, 2};
+    const cpaa_opts dir = with([](cpaa_opts& o) { o.directed = 1; });
+    expect("directed", d, dir, true);
+  }
   // invalid patterns are rejected before any device work
   Graph asym = from_edges(4, {{0, 1}, {1, 2}, {2, 3}});
   asym.ci[0] = 2;               // row 0 now lists 2 but row 2 does not list 0

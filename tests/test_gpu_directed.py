@@ -1,0 +1,124 @@
+"""GPU parity of the power method on directed graphs with dangling vertices
+(cpaa_solve_power on a plan with directed = 1) against the oracle's P''
+iteration (eq. 2.1 from p) and its dense solve (Sec. 2.1's P' = P + p d^T).
+
+Bar: pinned steps match the oracle's FP64 iterates to the FP32 rounding level
+(2e-6 in L1); certified solves are within tol and below the library's bound."""
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+
+pytestmark = pytest.mark.gpu
+C = 0.85
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2112_01743_amd import binding
+    binding.lib()
+    return torch
+
+
+def _dev(torch, a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _by_targets(n, edges):
+    rows = [[] for _ in range(n)]
+    for v, u in edges:
+        rows[u].append(v)
+    rp = np.zeros(n + 1, dtype=np.int32)
+    for u in range(n):
+        rp[u + 1] = rp[u] + len(set(rows[u]))
+    ci = np.concatenate([np.asarray(sorted(set(r)), dtype=np.int32) for r in rows])
+    return gg.CSR(n=n, row_ptr=rp, col_idx=ci)
+
+
+def _hubs(n):
+    """Most vertices point at 0 (an in-hub row longer than a work item), 0 points
+    at every odd vertex, odd vertices at one more; vertices 2 mod 4 are dangling."""
+    edges = [(v, 0) for v in range(1, n) if v % 4 != 2] + [(0, u) for u in range(1, n, 2)]
+    edges += [(u, (u * 7 + 3) % n) for u in range(1, n, 2) if (u * 7 + 3) % n != u]
+    return _by_targets(n, edges)
+
+
+GRAPHS = {
+    "three": lambda: _by_targets(3, [(0, 1), (0, 2), (1, 2)]),
+    "random5000": lambda: gg.directed_random(5000, 6, 0.1, seed=4),
+    "hubs20000": lambda: _hubs(20000),
+}
+
+
+def _plan(g, **opts):
+    from paper_2112_01743_amd import Plan
+    return Plan.from_graph(g, C, directed=1, **opts)
+
+
+@pytest.mark.parametrize("name", list(GRAPHS))
+def test_directed_steps_match_oracle(torch_cuda, name):
+    g = GRAPHS[name]()
+    for p in (gg.uniform_personalization(g.n), gg.source_personalization(g.n, [g.n - 1])[0]):
+        ref = oracle.power_method_directed(g, p, C, 30, return_all=True)
+        for t in (1, 2, 7, 30):
+            _note(f"case {name} n={g.n} nnz={g.nnz} t={t}")
+            x, rep = _plan(g, k_max=t, max_refine=0).solve_power(_dev(torch_cuda, p), 1e-15)
+            err = np.abs(x.cpu().numpy() - ref[t]).sum()
+            assert rep["terms"] == t and err <= 2e-6, (name, t, err)
+
+
+@pytest.mark.parametrize("name", list(GRAPHS))
+@pytest.mark.parametrize("tol", [1e-6, 1e-9])
+def test_directed_certified_solve(torch_cuda, name, tol):
+    g = GRAPHS[name]()
+    for p in (gg.uniform_personalization(g.n), gg.source_personalization(g.n, [g.n // 2])[0]):
+        pi = (oracle.pagerank_directed_exact(g, p, C) if g.n <= 5000 else
+              oracle.power_method_directed(g, p, C, int(np.log(1e-15) / np.log(C)) + 1))
+        x, rep = _plan(g).solve_power(_dev(torch_cuda, p), tol)
+        err = np.abs(x.cpu().numpy() - pi).sum()
+        _note(f"{name} tol={tol}: steps {rep['terms']}+{rep['refine_terms']} err {err:.2e} "
+              f"bound {rep['cert_bound']:.2e}")
+        assert rep["status"] == "CPAA_OK" and rep["certified"] == 1, rep
+        assert err <= tol and err <= rep["cert_bound"] * (1 + 1e-9) + 2e-13
+
+
+def test_directed_large_and_host_io(torch_cuda):
+    from paper_2112_01743_amd import Plan
+    from paper_2112_01743_amd import binding as B
+    g = gg.directed_random(400000, 8, 0.2, seed=9)
+    p = gg.uniform_personalization(g.n)
+    pi = oracle.power_method_directed(g, p, C, 230)
+    x, rep = _plan(g).solve_power(_dev(torch_cuda, p), 1e-8)
+    err = np.abs(x.cpu().numpy() - pi).sum()
+    _note(f"n={g.n} nnz={g.nnz}: steps {rep['terms']}+{rep['refine_terms']} err {err:.2e}")
+    assert rep["certified"] == 1 and err <= 1e-8
+    plan = Plan.from_graph(g, C, directed=1, io_device=0)
+    xh = np.zeros(g.n)
+    ph = np.ascontiguousarray(p)
+    st, reph = B.cpaa_solve_power(plan.handle, ph.ctypes.data, 1e-8, None, xh.ctypes.data)
+    assert st == B.CPAA_OK, B.cpaa_last_error()
+    assert np.abs(xh - pi).sum() <= 1e-8
+
+
+def test_directed_plan_rejects_other_solves(torch_cuda):
+    from paper_2112_01743_amd import CpaaError
+    g = GRAPHS["random5000"]()
+    plan = _plan(g)
+    p = _dev(torch_cuda, gg.uniform_personalization(g.n))
+    for call in (lambda: plan.solve(p, 1e-6),
+                 lambda: plan.solve_power(p, 1e-6, x0=p),
+                 lambda: plan.solve_batched(p[None, :].contiguous(), 1e-6),
+                 lambda: plan.solve_power_batched(p[None, :].contiguous(), 1e-6)):
+        with pytest.raises(CpaaError):
+            call()

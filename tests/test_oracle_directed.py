@@ -48,7 +48,7 @@ def test_iterates_are_distributions_and_reach_the_dense_solve():
     pi = oracle.pagerank_directed_exact(g, p, C)
     P, d = oracle.transition_directed(g)
     # eq. 2.1: pi = P'' pi with sum 1
-    Ppp = C * (P + np.outer(p, d)) + (1 - C) * np.outer(p, np.ones(g.n))
+    Ppp = C * (P.toarray() + np.outer(p, d)) + (1 - C) * np.outer(p, np.ones(g.n))
     assert np.abs(Ppp @ pi - pi).max() < 1e-15 and abs(pi.sum() - 1) < 1e-13
     e0 = np.abs(p - pi).sum()
     seq = oracle.power_method_directed(g, p, C, 250, return_all=True)
