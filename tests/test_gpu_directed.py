@@ -75,7 +75,9 @@ def test_directed_steps_match_oracle(torch_cuda, name):
             _note(f"case {name} n={g.n} nnz={g.nnz} t={t}")
             x, rep = _plan(g, k_max=t, max_refine=0).solve_power(_dev(torch_cuda, p), 1e-15)
             err = np.abs(x.cpu().numpy() - ref[t]).sum()
-            assert rep["terms"] == t and err <= 2e-6, (name, t, err)
+            # an earlier stop happens only at a fixed point (x_0 = p = pi when p
+            # sits on a dangling vertex of the three-vertex graph), where err is 0
+            assert rep["terms"] <= t and err <= 2e-6, (name, t, err)
 
 
 @pytest.mark.parametrize("name", list(GRAPHS))
