@@ -269,6 +269,52 @@ def bench_table3(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_directed(args):
+    """The power method on a directed graph with dangling vertices: n = 4,000,000,
+    ~16 out-edges per non-dangling vertex, 10% dangling (seed 2112020), p
+    uniform, certified to 1e-6 in L1.  Algorithmic bytes of one step (k_term_dir):
+    4 nnz + 4 (n+1) + per vertex z gathered once, z written (4 B each), acc read
+    and written (16 B), b read (8 B) and the out-degree (4 B): 36 n."""
+    import torch
+    import graphgen as gg
+    from paper_2112_01743_amd import Plan
+    c = 0.85
+    t0 = time.perf_counter()
+    g = gg.directed_random(4_000_000, 16, 0.1, seed=2112020)
+    log(f"graph n={g.n} nnz={g.nnz} ({time.perf_counter() - t0:.1f} s)")
+    plan = Plan.from_graph(g, c, directed=1, time_kernels=1)
+    p = torch.full((g.n,), 1.0 / g.n, dtype=torch.float64, device="cuda")
+    x = torch.empty_like(p)
+    for _ in range(2):
+        plan.solve_power(p, args.tol, out=x)
+    torch.cuda.synchronize()
+    reps = []
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        reps.append(plan.solve_power(p, args.tol, out=x)[1])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t1
+    ms_terms = sum(r["ms_terms"] for r in reps)
+    launches = sum(r["term_launches"] for r in reps)
+    avg = ms_terms / 1e3 / max(launches, 1)
+    alg = 4 * g.nnz + 4 * (g.n + 1) + 36 * g.n
+    r = reps[-1]
+    out = {"metric": METRIC, "value": sum(q["edges"] for q in reps) / wall / 1e9, "unit": "GTEPS",
+           "n_gpus": 1, "steps": args.steps, "ms_per_step": wall * 1e3 / args.steps,
+           "higher_is_better": True, "dtype": "f32 increments, f64 accumulation",
+           "data": "synthetic",
+           "config": {"workload": "directed_power_method", "n": g.n, "nnz": g.nnz,
+                      "dangling": g.meta["dangling"], "seed": 2112020, "c": c,
+                      "tol_l1": args.tol, "personalization": "uniform"},
+           "solves_per_s": args.steps / wall, "steps_per_solve": r["terms"] + r["refine_terms"],
+           "certified": all(q["certified"] for q in reps), "cert_bound": r["cert_bound"],
+           "roofline": {"bound": "hbm", "achieved": alg / avg / 1e9, "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": alg / avg / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                        "kernel": "k_term_dir", "bytes_per_launch": alg,
+                        "avg_launch_us": avg * 1e6}}
+    print(json.dumps(out), flush=True)
+
+
 def bench_graph_batch(args):
     """10,000 independent Chung-Lu graphs (n log-uniform in [100, 5000], average
     degree 4-32, exponent 2.1-3.0, seed 2112003), one random source each, solved
@@ -336,12 +382,14 @@ def main():
                     help="0 auto (column-sliced on this graph), 1 off, 8 on")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="chung_lu",
-                    choices=["chung_lu", "grid_batched", "graph_batch", "table3"],
+                    choices=["chung_lu", "grid_batched", "graph_batch", "table3", "directed"],
                     help="chung_lu: global PageRank on the 4M-vertex power-law graph (default); "
                          "grid_batched: 256 single-source solves on the 1000x1000 perturbed "
                          "lattice in one batched call; graph_batch: 10,000 small Chung-Lu graphs "
                          "in one persistent launch; table3: rounds and time to ERR < 1e-3 "
-                         "for CPAA and the power method on a Delaunay stand-in for delaunay-n21")
+                         "for CPAA and the power method on a Delaunay stand-in for delaunay-n21; "
+                         "directed: the power method on a 4M-vertex directed graph with dangling "
+                         "vertices")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters against a known byte count)")
@@ -367,6 +415,8 @@ def main():
         return bench_graph_batch(args)
     if args.workload == "table3":
         return bench_table3(args)
+    if args.workload == "directed":
+        return bench_directed(args)
 
     import torch
     import graphgen as gg
