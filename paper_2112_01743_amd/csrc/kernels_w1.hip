@@ -505,10 +505,11 @@ int elem_grid(int64_t n) {
 // by the launch that forms delta_t and read by the next one.
 // ---------------------------------------------------------------------------
 
+// Sum of kSlots (= 64) reduction slots by the first wavefront, one per lane;
+// the result is valid in every lane of that wavefront.
+static_assert(kSlots == 64, "one slot per lane");
 __device__ __forceinline__ double slot_sum(const double* __restrict__ slots) {
-  double m = 0.0;
-  for (int k = 0; k < kSlots; ++k) m += slots[k];
-  return m;
+  return wave_sum(slots[threadIdx.x & 63]);
 }
 
 // acc (+)= x_0 = scale * src; z_0 = D_out^+ x_0; dangling mass of x_0 -> dang0.
@@ -591,7 +592,10 @@ template <int NPT>
 __global__ __launch_bounds__(kWG) void k_term_dir(DirArgs a) {
   if (a.done != nullptr && *a.done) return;
   __shared__ double m_sh;
-  if (threadIdx.x == 0) m_sh = slot_sum(a.dang_cur);
+  if (threadIdx.x < 64) {
+    const double m = slot_sum(a.dang_cur);
+    if (threadIdx.x == 0) m_sh = m;
+  }
   if (blockIdx.x == 0 && threadIdx.x < kSlots) a.dang_clear[threadIdx.x] = 0.0;
   __syncthreads();
   const int lb = xcd_logical(blockIdx.x, gridDim.x, a.xcd);
@@ -677,9 +681,12 @@ struct DirResidArgs {
 template <int NPT>
 __global__ __launch_bounds__(kWG) void k_resid_dir(DirResidArgs a) {
   __shared__ double m_sh[2];
-  if (threadIdx.x == 0) {
-    m_sh[0] = slot_sum(a.dx);
-    m_sh[1] = slot_sum(a.dxa);
+  if (threadIdx.x < 64) {
+    const double m = slot_sum(a.dx), ma = slot_sum(a.dxa);
+    if (threadIdx.x == 0) {
+      m_sh[0] = m;
+      m_sh[1] = ma;
+    }
   }
   __syncthreads();
   const int lb = xcd_logical(blockIdx.x, gridDim.x, a.xcd);
