@@ -25,3 +25,20 @@ def graphs(draw):
     u = np.concatenate([np.asarray(u, dtype=np.int64), rng.integers(0, n, extra)])
     v = np.concatenate([np.asarray(v, dtype=np.int64), rng.integers(0, n, extra)])
     return gg.csr_from_edges(n, u, v)
+
+
+@st.composite
+def directed_graphs(draw):
+    """n in [1, 40]; every vertex gets 0-4 random out-edges (so some are dangling,
+    some rows empty); returned by targets (row u lists the sources of v -> u)."""
+    n = draw(st.integers(1, 40))
+    rng = np.random.default_rng(draw(st.integers(0, 2**31 - 1)))
+    deg = rng.integers(0, 5, n)
+    src = np.repeat(np.arange(n), deg)
+    dst = rng.integers(0, n, src.size)
+    keep = src != dst
+    key = np.unique(dst[keep].astype(np.int64) * n + src[keep])
+    u, v = key // n, key % n
+    rp = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(u, minlength=n), out=rp[1:])
+    return gg.CSR(n=n, row_ptr=rp.astype(np.int32), col_idx=v.astype(np.int32))

@@ -14,7 +14,7 @@ from hypothesis import strategies as st  # noqa: E402
 
 import graphgen as gg  # noqa: E402
 import oracle  # noqa: E402
-from strategies import graphs  # noqa: E402
+from strategies import directed_graphs, graphs  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -62,3 +62,21 @@ def test_random_graphs_match_dense_solve(torch_cuda, g, c, opt, pseed, method):
     ref = oracle.pagerank_exact(g, P.T, c)
     errs = np.abs(X.cpu().numpy().T - ref).sum(axis=0)
     assert np.all(reps["certified"] == 1) and errs.max() <= tol, errs
+
+
+@settings(max_examples=100, deadline=None, derandomize=True, database=None,
+          suppress_health_check=[HealthCheck.too_slow, HealthCheck.function_scoped_fixture])
+@given(g=directed_graphs(), c=st.floats(0.05, 0.9), pseed=st.integers(0, 2**31 - 1))
+def test_random_directed_graphs_match_dense_solve(torch_cuda, g, c, pseed):
+    """Directed plans (dangling vertices, empty rows) through the power method."""
+    from paper_2112_01743_amd import Plan
+    rng = np.random.default_rng(pseed)
+    p = rng.random(g.n) ** 3 + 1e-3
+    p /= p.sum()
+    print(f"directed n={g.n} nnz={g.nnz} c={c:.3f}", flush=True)
+    plan = Plan.from_graph(g, c, directed=1)
+    x, rep = plan.solve_power(_dev(torch_cuda, p), 1e-9)
+    pi = oracle.pagerank_directed_exact(g, p, c)
+    err = np.abs(x.cpu().numpy() - pi).sum()
+    assert rep["certified"] == 1 and err <= 1e-9, (err, rep)
+    assert err <= rep["cert_bound"] * (1 + 1e-9) + 1e-14
