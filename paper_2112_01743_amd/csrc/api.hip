@@ -515,6 +515,8 @@ void cpaa_plan_destroy(cpaa_plan_t pl) {
     if (p) (void)hipFree(p);
   if (pl->ev_begin) (void)hipEventDestroy(pl->ev_begin);
   if (pl->ev_end) (void)hipEventDestroy(pl->ev_end);
+  for (hipEvent_t e : pl->ev_poll)
+    if (e) (void)hipEventDestroy(e);
   for (hipEvent_t e : pl->ev_terms) (void)hipEventDestroy(e);
   delete pl;
 }
@@ -830,7 +832,9 @@ cpaa_status cpaa_plan(const cpaa_csr* g, double c, const cpaa_opts* opts, cpaa_p
     if (s == CPAA_OK) s = build_graph_state(pl, rp, ci, gp);
   }
   if (s == CPAA_OK) {
-    if (hipEventCreate(&pl->ev_begin) != hipSuccess || hipEventCreate(&pl->ev_end) != hipSuccess) {
+    if (hipEventCreate(&pl->ev_begin) != hipSuccess || hipEventCreate(&pl->ev_end) != hipSuccess ||
+        hipEventCreateWithFlags(&pl->ev_poll[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&pl->ev_poll[1], hipEventDisableTiming) != hipSuccess) {
       set_error("hipEventCreate failed");
       s = CPAA_EDEVICE;
     }

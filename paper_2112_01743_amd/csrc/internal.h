@@ -132,6 +132,7 @@ struct Workspace {
   int* plain = nullptr;          // [cols] columns restarted as plain solves
   double* col_scale = nullptr;   // [cols] output scale per column
   double* host = nullptr;        // pinned host mirror
+  int* poll_host = nullptr;      // pinned [2][tiles] stop flags of a series read while it runs
   size_t host_bytes = 0;
 };
 
@@ -206,6 +207,7 @@ struct cpaa_plan_s {
   cpaa::Workspace wsg;               // multi-graph
 
   hipEvent_t ev_begin = nullptr, ev_end = nullptr;
+  hipEvent_t ev_poll[2] = {nullptr, nullptr};   // chunked power-method series
   std::vector<hipEvent_t> ev_terms;  // pairs around term launches
 };
 

@@ -33,6 +33,7 @@ void free_workspace(Workspace& ws) {
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (ws.host) (void)hipHostFree(ws.host);
+  if (ws.poll_host) (void)hipHostFree(ws.poll_host);
   ws = Workspace();
 }
 
@@ -90,6 +91,12 @@ cpaa_status ensure_workspace(cpaa_plan_s* pl, Workspace& ws, int W, int tiles) {
   if (ok && hipHostMalloc((void**)&ws.host, ws.host_bytes, hipHostMallocDefault) != hipSuccess) {
     (void)hipGetLastError();
     ws.host = nullptr;
+    ok = false;
+  }
+  if (ok && hipHostMalloc((void**)&ws.poll_host, (size_t)2 * tiles * sizeof(int),
+                          hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    ws.poll_host = nullptr;
     ok = false;
   }
   if (ok) {
@@ -247,6 +254,14 @@ cpaa_status run_series(cpaa_plan_s* pl, Workspace& ws, TermFn term, int series_i
   CPAA_HIP(fill_i32(ws.terms, k_cap, ws.tiles, st));
   CPAA_HIP(fill_f64(ws.series_cert, -1.0, cols, st));
   const std::vector<AccUpdate> acc_plan = acc_schedule(series_coef(pl, ws), k_cap, k_min);
+  // The power method's a-priori cap (from c^k alone) can run far past the stop,
+  // so its launches are enqueued in chunks and the stop flags are read one chunk
+  // behind (the GPU always has the next chunk queued); at most one chunk of
+  // launches that return at once is left.
+  constexpr int kChunk = 8;
+  const bool poll = ws.method == Method::kPower && ws.poll_host != nullptr &&
+                    pl->ev_poll[0] != nullptr && k_cap > 2 * kChunk;
+  int chunk = 0;
   for (int k = 0; k < k_cap; ++k) {
     // this launch produces z_{k+1}; its certificate is that of x_k
     double* cert = (k >= k_min) ? ws.slots + (size_t)k * kSlots * cols : nullptr;
@@ -259,6 +274,19 @@ cpaa_status run_series(cpaa_plan_s* pl, Workspace& ws, TermFn term, int series_i
                                ? 1.0 / ((1.0 - pl->c) * (1.0 - pl->c))
                                : (1.0 + pl->s) / pl->s * std::pow(pl->beta, k + 1) / (1.0 - pl->c);
       CPAA_HIP(check_series(pl, ws, cert, scale, target, k + 1, st));
+    }
+    if (poll && (k + 1) % kChunk == 0 && k + 1 < k_cap) {
+      int* flags = ws.poll_host + (size_t)(chunk % 2) * ws.tiles;
+      CPAA_HIP(hipMemcpyAsync(flags, ws.done, ws.tiles * sizeof(int), hipMemcpyDeviceToHost, st));
+      CPAA_HIP(hipEventRecord(pl->ev_poll[chunk % 2], st));
+      if (chunk > 0) {
+        CPAA_HIP(hipEventSynchronize(pl->ev_poll[(chunk - 1) % 2]));
+        const int* prev = ws.poll_host + (size_t)((chunk - 1) % 2) * ws.tiles;
+        bool all = true;
+        for (int t = 0; t < ws.tiles && all; ++t) all = prev[t] != 0;
+        if (all) break;
+      }
+      ++chunk;
     }
   }
   return CPAA_OK;
