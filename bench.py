@@ -272,9 +272,12 @@ def bench_table3(args):
 def bench_directed(args):
     """The power method on a directed graph with dangling vertices: n = 4,000,000,
     ~16 out-edges per non-dangling vertex, 10% dangling (seed 2112020), p
-    uniform, certified to 1e-6 in L1.  Algorithmic bytes of one step (k_term_dir):
-    4 nnz + 4 (n+1) + per vertex z gathered once, z written (4 B each), acc read
-    and written (16 B), b read (8 B) and the out-degree (4 B): 36 n."""
+    uniform, certified to 1e-6 in L1.  Column slices are on by default here (the
+    edges are scattered over all labels), so a step is k_term_sliced plus
+    k_combine_dir; with --column-slices 1 it is the fused k_term_dir.
+    Algorithmic bytes of one step: 4 nnz + 4 (n+1) + per vertex z gathered
+    once, z written (4 B each), acc read and written (16 B), b read (8 B) and
+    the out-degree (4 B): 36 n."""
     import torch
     import graphgen as gg
     from paper_2112_01743_amd import Plan
@@ -282,7 +285,9 @@ def bench_directed(args):
     t0 = time.perf_counter()
     g = gg.directed_random(4_000_000, 16, 0.1, seed=2112020)
     log(f"graph n={g.n} nnz={g.nnz} ({time.perf_counter() - t0:.1f} s)")
-    plan = Plan.from_graph(g, c, directed=1, time_kernels=1)
+    plan = Plan.from_graph(g, c, directed=1, time_kernels=1,
+                           column_slices=args.column_slices)
+    info = plan.info()
     p = torch.full((g.n,), 1.0 / g.n, dtype=torch.float64, device="cuda")
     x = torch.empty_like(p)
     for _ in range(2):
@@ -305,12 +310,15 @@ def bench_directed(args):
            "data": "synthetic",
            "config": {"workload": "directed_power_method", "n": g.n, "nnz": g.nnz,
                       "dangling": g.meta["dangling"], "seed": 2112020, "c": c,
-                      "tol_l1": args.tol, "personalization": "uniform"},
+                      "tol_l1": args.tol, "personalization": "uniform",
+                      "column_slices": info["column_slices"]},
            "solves_per_s": args.steps / wall, "steps_per_solve": r["terms"] + r["refine_terms"],
            "certified": all(q["certified"] for q in reps), "cert_bound": r["cert_bound"],
            "roofline": {"bound": "hbm", "achieved": alg / avg / 1e9, "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": alg / avg / 1e9 / HBM_PEAK_GBS, "traffic": None,
-                        "kernel": "k_term_dir", "bytes_per_launch": alg,
+                        "kernel": ("step = k_term_sliced<32> + k_combine_dir"
+                                   if info["column_slices"] == 8 else "step = k_term_dir"),
+                        "bytes_per_launch": alg,
                         "avg_launch_us": avg * 1e6}}
     print(json.dumps(out), flush=True)
 

@@ -106,7 +106,9 @@ typedef struct {
                              s, so every XCD gathers from one eighth of the vector, which stays
                              in its L2, and a combine pass adds the 8 partial row sums and
                              applies the term update.  Auto: on for one graph with n >= 3 * 2^18
-                             and max degree >= 16 x average degree.  Needs one graph and
+                             and max degree >= 16 x average degree (for a directed plan also
+                             when its entries span more than 2^14 labels on average).  Needs
+                             one graph and
                              n < 8 (2^21 - 16) (else CPAA_EINVAL).  Inputs and outputs keep the caller's
                              labels. */
   int32_t locality_order; /* single-vector path without column slices: 0 auto, 1 off (caller's
@@ -133,8 +135,9 @@ typedef struct {
                              (Sec. 2.1).  CPAA's expansion needs the real spectrum of an
                              undirected graph (Sec. 3), so such a plan is solved by
                              cpaa_solve_power only (single vector, x0 = NULL); every other solve
-                             call returns CPAA_EINVAL.  Needs one graph; column slices, RCM
-                             and the spectral interval are not used. */
+                             call returns CPAA_EINVAL.  Needs one graph; RCM and the spectral
+                             interval are not used (CPAA_EINVAL when asked for); column slices
+                             are. */
 } cpaa_opts;
 
 /* Per-solve report (one per right-hand side in batched calls, one per graph in

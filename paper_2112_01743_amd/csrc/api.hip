@@ -569,9 +569,9 @@ cpaa_status cpaa_plan(const cpaa_csr* g, double c, const cpaa_opts* opts, cpaa_p
     set_error("directed must be 0 or 1");
     return CPAA_EINVAL;
   }
-  if (o.directed == 1 && (g->num_graphs > 1 || o.column_slices == kSlices ||
-                          o.locality_order == 2 || o.spectral_interval == 1)) {
-    set_error("directed plans need one graph and no column slices, RCM or spectral interval");
+  if (o.directed == 1 &&
+      (g->num_graphs > 1 || o.locality_order == 2 || o.spectral_interval == 1)) {
+    set_error("directed plans need one graph and no RCM or spectral interval");
     return CPAA_EINVAL;
   }
   if (o.locality_order < 0 || o.locality_order > 2) {
@@ -702,10 +702,14 @@ cpaa_status cpaa_plan(const cpaa_csr* g, double c, const cpaa_opts* opts, cpaa_p
   // Column slices keep each XCD's gathers inside one eighth of the vector
   // (its L2); they pay off once the FP32 vector (4n bytes) passes ~3 MB and
   // the degrees are skewed (a lattice's natural order is already local):
-  // measured on power-law graphs, 6 % faster at n = 1M, even at 500k.
+  // measured on power-law graphs, 6 % faster at n = 1M, even at 500k.  A
+  // directed plan has no RCM alternative, so there a scattered pattern
+  // (entries spanning more than 2^14 labels on average) also qualifies.
+  const bool big = n >= 3 * (1 << 18) && n < kSliceMaxN;
   pl->sliced = o.column_slices == kSlices ||
-               (o.column_slices == 0 && num_graphs == 1 && !pl->directed && n >= 3 * (1 << 18) &&
-                n < kSliceMaxN && static_cast<double>(maxd) >= 16.0 * vol / n);
+               (o.column_slices == 0 && num_graphs == 1 && big &&
+                (static_cast<double>(maxd) >= 16.0 * vol / n ||
+                 (pl->directed && mean_span(n, rp, ci) > 16384.0)));
   std::vector<int32_t> rp2, ci2, perm;
   if (pl->sliced) {
     slice_relabel(n, rp, ci, rp2, ci2, perm, pl->slc.slice_off);
@@ -748,8 +752,10 @@ cpaa_status cpaa_plan(const cpaa_csr* g, double c, const cpaa_opts* opts, cpaa_p
   cpaa_status s = CPAA_OK;
   if (s == CPAA_OK) s = dev_upload(&pl->d_row_ptr, rp, n + 1);
   if (s == CPAA_OK && pl->directed) {
-    std::vector<int32_t> dout(n, 0);     // out-degree of v = rows that list v
-    for (int64_t j = 0; j < nnz; ++j) ++dout[ci[j]];
+    // out-degree of v = rows that list v, in the single-vector labelling
+    const int32_t* ci1 = pl->reordered ? ci2.data() : ci;
+    std::vector<int32_t> dout(n, 0);
+    for (int64_t j = 0; j < nnz; ++j) ++dout[ci1[j]];
     s = dev_upload(&pl->d_dout, dout.data(), dout.size());
   }
   if (s == CPAA_OK) s = dev_upload(&pl->d_col_idx, ci, static_cast<size_t>(nnz));

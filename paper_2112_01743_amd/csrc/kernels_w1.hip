@@ -514,6 +514,7 @@ __device__ __forceinline__ double slot_sum(const double* __restrict__ slots) {
 
 // acc (+)= x_0 = scale * src; z_0 = D_out^+ x_0; dangling mass of x_0 -> dang0.
 __global__ __launch_bounds__(kWG) void k_init_dir(int n, const int* __restrict__ dout,
+                                                  const int* __restrict__ perm,
                                                   const double* __restrict__ src, double scale,
                                                   double one_minus_c, int add, int store_b,
                                                   double* __restrict__ b, float* __restrict__ z0,
@@ -522,7 +523,7 @@ __global__ __launch_bounds__(kWG) void k_init_dir(int n, const int* __restrict__
                                                   double* __restrict__ stat_slots) {
   double f_sum = 0, f_neg = 0, f_bad = 0, f_dang = 0;
   for (int u = blockIdx.x * kWG + threadIdx.x; u < n; u += gridDim.x * kWG) {
-    const double p = src[u];
+    const double p = src[perm ? perm[u] : u];
     const double x = scale * p;
     const int d = dout[u];
     if (store_b) b[u] = one_minus_c * p;
@@ -709,9 +710,57 @@ __global__ __launch_bounds__(kWG) void k_resid_dir(DirResidArgs a) {
   }
 }
 
-__global__ __launch_bounds__(kWG) void k_finalize_dir(int n, const double* __restrict__ acc,
+__global__ __launch_bounds__(kWG) void k_finalize_dir(int n, const int* __restrict__ perm,
+                                                      const double* __restrict__ acc,
                                                       double scale, double* __restrict__ x) {
-  for (int u = blockIdx.x * kWG + threadIdx.x; u < n; u += gridDim.x * kWG) x[u] = scale * acc[u];
+  for (int u = blockIdx.x * kWG + threadIdx.x; u < n; u += gridDim.x * kWG)
+    x[perm ? perm[u] : u] = scale * acc[u];
+}
+
+// Column-sliced step on a directed plan: k_term_sliced left the partial sums
+// of z over each column slice in part[s][row]; add them in a fixed order and
+// run the directed epilogue.
+struct DirCombineArgs {
+  const float* part;
+  const int* dout;
+  const double* b;
+  const double* x0;
+  double x0_scale;
+  float* zn;
+  double* acc;
+  const double* dang_cur;
+  double* dang_next;
+  double* dang_clear;
+  double c;
+  double* cert;
+  const int* done;
+  int n;
+};
+
+__global__ __launch_bounds__(kWG) void k_combine_dir(DirCombineArgs a) {
+  if (a.done != nullptr && *a.done) return;
+  __shared__ double m_sh;
+  if (threadIdx.x < 64) {
+    const double m = slot_sum(a.dang_cur);
+    if (threadIdx.x == 0) m_sh = m;
+  }
+  if (blockIdx.x == 0 && threadIdx.x < kSlots) a.dang_clear[threadIdx.x] = 0.0;
+  __syncthreads();
+  DirTermEpi epi{a.b, a.x0, a.dout, a.zn, a.acc, a.c, m_sh, 1.0 / (1.0 - a.c), a.x0_scale,
+                 a.cert != nullptr, 0.0, 0.0};
+  const size_t n = static_cast<size_t>(a.n);
+  for (int u = blockIdx.x * kWG + threadIdx.x; u < a.n; u += gridDim.x * kWG) {
+    float s = 0.f;
+#pragma unroll
+    for (int k = 0; k < kSlices; ++k) s += a.part[k * n + u];
+    epi.row(u, 0, s, 0.f);
+  }
+  const double cs = block_sum256(epi.cert);
+  const double ms = block_sum256(epi.mnext);
+  if (threadIdx.x == 0) {
+    if (a.cert != nullptr && cs != 0.0) atomic_add(&a.cert[blockIdx.x % kSlots], cs);
+    if (ms != 0.0) atomic_add(&a.dang_next[blockIdx.x % kSlots], ms);
+  }
 }
 
 }  // namespace
@@ -730,30 +779,39 @@ hipError_t load_x0_w1(const cpaa_plan_s* pl, Workspace& ws, const double* x0, hi
   return hipGetLastError();
 }
 
+namespace {
+
+// Pass 1 of a column-sliced term: partial sums of z_cur per column slice into ws.part.
+void sliced_pass(const cpaa_plan_s* pl, Workspace& ws, int cur, const int* done, hipStream_t st) {
+  SlicedArgs s;
+  s.entries = pl->slc.d_entries;
+  s.items = pl->slc.d_items;
+  s.rp = pl->d_rp_w1;
+  s.zc = ws.z[cur];
+  s.part = ws.part;
+  s.done = done;
+  s.split_part = ws.split_f;
+  s.split_count = ws.split_count;
+  s.split_nchunks = pl->slc.d_split_nchunks;
+  s.n = pl->n;
+  for (int i = 0; i <= kSlices; ++i) {
+    s.item_off[i] = pl->slc.item_off[i];
+    s.slice_off[i] = pl->slc.slice_off[i];
+  }
+  const dim3 grid(kSlices * pl->slc.max_items);
+  if (pl->slc.row_bits == kSliceRowBitsMax)
+    hipLaunchKernelGGL((k_term_sliced<kSliceNpt, kSliceRowBitsMax>), grid, dim3(kWG), 0, st, s);
+  else
+    hipLaunchKernelGGL((k_term_sliced<kSliceNpt, 11>), grid, dim3(kWG), 0, st, s);
+}
+
+}  // namespace
+
 hipError_t term_w1(const cpaa_plan_s* pl, Workspace& ws, int cur, int prev, int next, bool first,
                    const AccUpdate& au, double* cert_slot, const int* done, hipStream_t st) {
   const TermShape sh = term_shape(pl, ws, first);
   if (pl->sliced) {
-    SlicedArgs s;
-    s.entries = pl->slc.d_entries;
-    s.items = pl->slc.d_items;
-    s.rp = pl->d_rp_w1;
-    s.zc = ws.z[cur];
-    s.part = ws.part;
-    s.done = done;
-    s.split_part = ws.split_f;
-    s.split_count = ws.split_count;
-    s.split_nchunks = pl->slc.d_split_nchunks;
-    s.n = pl->n;
-    for (int i = 0; i <= kSlices; ++i) {
-      s.item_off[i] = pl->slc.item_off[i];
-      s.slice_off[i] = pl->slc.slice_off[i];
-    }
-    const dim3 grid(kSlices * pl->slc.max_items);
-    if (pl->slc.row_bits == kSliceRowBitsMax)
-      hipLaunchKernelGGL((k_term_sliced<kSliceNpt, kSliceRowBitsMax>), grid, dim3(kWG), 0, st, s);
-    else
-      hipLaunchKernelGGL((k_term_sliced<kSliceNpt, 11>), grid, dim3(kWG), 0, st, s);
+    sliced_pass(pl, ws, cur, done, st);
     CombineArgs c;
     c.rp = pl->d_rp_w1;
     c.part = ws.part;
@@ -834,9 +892,9 @@ hipError_t finalize_w1(const cpaa_plan_s* pl, Workspace& ws, double* x, double s
 
 hipError_t init_dir(const cpaa_plan_s* pl, Workspace& ws, const double* src, double scale,
                     bool add, bool store_b, hipStream_t st) {
-  hipLaunchKernelGGL(k_init_dir, dim3(elem_grid(pl->n)), dim3(kWG), 0, st, pl->n, pl->d_dout, src,
-                     scale, 1.0 - pl->c, add ? 1 : 0, store_b ? 1 : 0, ws.b, ws.z[0], ws.acc,
-                     ws.dang, ws.stat_slots);
+  hipLaunchKernelGGL(k_init_dir, dim3(elem_grid(pl->n)), dim3(kWG), 0, st, pl->n, pl->d_dout,
+                     src == ws.r ? nullptr : pl->d_perm, src, scale, 1.0 - pl->c, add ? 1 : 0,
+                     store_b ? 1 : 0, ws.b, ws.z[0], ws.acc, ws.dang, ws.stat_slots);
   return hipGetLastError();
 }
 
@@ -844,9 +902,29 @@ hipError_t term_dir(const cpaa_plan_s* pl, Workspace& ws, int cur, int prev, int
                     const AccUpdate&, double* cert_slot, const int* done, hipStream_t st) {
   // every launch adds its increment to acc (x-space), so any stop leaves
   // acc = x_{k+1}; grouped updates do not apply here
+  if (pl->sliced) {
+    sliced_pass(pl, ws, cur, done, st);
+    DirCombineArgs c;
+    c.part = ws.part;
+    c.dout = pl->d_dout;
+    c.b = ws.b;
+    c.x0 = first ? ws.dir_x0 : nullptr;
+    c.x0_scale = ws.dir_x0_scale;
+    c.zn = ws.z[next];
+    c.acc = ws.acc;
+    c.dang_cur = ws.dang + (size_t)cur * kSlots;
+    c.dang_next = ws.dang + (size_t)next * kSlots;
+    c.dang_clear = ws.dang + (size_t)prev * kSlots;
+    c.c = pl->c;
+    c.cert = cert_slot;
+    c.done = done;
+    c.n = pl->n;
+    hipLaunchKernelGGL(k_combine_dir, dim3(elem_grid(pl->n)), dim3(kWG), 0, st, c);
+    return hipGetLastError();
+  }
   DirArgs a;
-  a.rp = pl->d_row_ptr;
-  a.ci = pl->d_col_idx;
+  a.rp = pl->d_rp_w1;
+  a.ci = pl->d_ci_w1;
   a.items = pl->d_items;
   a.dout = pl->d_dout;
   a.b = ws.b;
@@ -883,8 +961,8 @@ hipError_t residual_dir(const cpaa_plan_s* pl, Workspace& ws, hipStream_t st) {
   hipLaunchKernelGGL(k_dir_w, dim3(elem_grid(pl->n)), dim3(kWG), 0, st, pl->n, pl->d_dout, ws.acc,
                      ws.wdir, dx, dxa);
   DirResidArgs a;
-  a.rp = pl->d_row_ptr;
-  a.ci = pl->d_col_idx;
+  a.rp = pl->d_rp_w1;
+  a.ci = pl->d_ci_w1;
   a.items = pl->d_items;
   a.w = ws.wdir;
   a.acc = ws.acc;
@@ -911,8 +989,8 @@ hipError_t residual_dir(const cpaa_plan_s* pl, Workspace& ws, hipStream_t st) {
 
 hipError_t finalize_dir(const cpaa_plan_s* pl, Workspace& ws, double* x, double scale,
                         hipStream_t st) {
-  hipLaunchKernelGGL(k_finalize_dir, dim3(elem_grid(pl->n)), dim3(kWG), 0, st, pl->n, ws.acc,
-                     scale, x);
+  hipLaunchKernelGGL(k_finalize_dir, dim3(elem_grid(pl->n)), dim3(kWG), 0, st, pl->n, pl->d_perm,
+                     ws.acc, scale, x);
   return hipGetLastError();
 }
 

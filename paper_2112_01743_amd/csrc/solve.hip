@@ -870,8 +870,8 @@ cpaa_status solve_directed(cpaa_plan_t pl, const double* p, double tol, double* 
   if ((s = read_back(ws, st)) != CPAA_OK) return s;
   if ((s = check_p_stats(ws, 0)) != CPAA_OK) return s;
   const double target_main = 0.5 * tol;
-  ws.dir_x0 = dp;
-  ws.dir_x0_scale = 1.0;
+  ws.dir_x0 = ws.b;    // x_0 = p = b/(1-c), in the plan's labels
+  ws.dir_x0_scale = 1.0 / (1.0 - c);
   int k_cap = series_cap(pl, ws, 0.0, (1.0 - c) * stat_at(ws, 0, 0, 0), target_main);
   if ((s = run_series(pl, ws, term_dir, 0, k_cap, 0, target_main, timer, st)) != CPAA_OK) return s;
   series_terms.push_back(k_cap);

@@ -190,3 +190,31 @@ def test_warm_start_network_at_1m(torch_cuda):
     assert np.all(rw["certified"] == 1) and np.all(rp["certified"] == 1)
     diff = (Xw - Xp).abs().sum(dim=1).cpu().numpy()
     assert np.all(diff <= rw["cert_bound"] + rp["cert_bound"])
+
+
+@pytest.mark.timeout(600)
+def test_directed_4m_sliced(torch_cuda):
+    """The directed workload at its full size (the bench's graph and seed): the
+    plan picks column slices by itself; the result is certified by the oracle's
+    FP64 residual of (I - cP') x = (1-c) p (Sec. 2.1, ||(I - cP')^{-1}||_1 <=
+    1/(1-c) for the column-stochastic P') and agrees with the row-order plan."""
+    from paper_2112_01743_amd import Plan
+    torch = torch_cuda
+    g = gg.directed_random(4_000_000, 16, 0.1, seed=2112020)
+    _note(f"directed n={g.n} nnz={g.nnz}")
+    plan = Plan.from_graph(g, C, directed=1, time_kernels=1)
+    assert plan.info()["column_slices"] == 8
+    p = np.full(g.n, 1.0 / g.n)
+    dp = torch.as_tensor(p, device="cuda")
+    xs, rs = plan.solve_power(dp, TOL)
+    xs = xs.cpu().numpy()
+    del plan
+    xr, rr = Plan.from_graph(g, C, directed=1, column_slices=1).solve_power(dp, TOL)
+    xr = xr.cpu().numpy()
+    P, d = oracle.transition_directed(g)
+    r = (1 - C) * p - xs + C * (P @ xs + p * (d @ xs))
+    bound = np.abs(r).sum() / (1 - C)
+    _note(f"sliced: steps {rs['terms']}+{rs['refine_terms']} gpu bound {rs['cert_bound']:.3e} "
+          f"oracle bound {bound:.3e}; row order steps {rr['terms']}")
+    assert rs["certified"] == 1 and bound <= TOL
+    assert np.abs(xs - xr).sum() <= 2 * TOL

@@ -66,15 +66,17 @@ def test_random_graphs_match_dense_solve(torch_cuda, g, c, opt, pseed, method):
 
 @settings(max_examples=100, deadline=None, derandomize=True, database=None,
           suppress_health_check=[HealthCheck.too_slow, HealthCheck.function_scoped_fixture])
-@given(g=directed_graphs(), c=st.floats(0.05, 0.9), pseed=st.integers(0, 2**31 - 1))
-def test_random_directed_graphs_match_dense_solve(torch_cuda, g, c, pseed):
-    """Directed plans (dangling vertices, empty rows) through the power method."""
+@given(g=directed_graphs(), c=st.floats(0.05, 0.9), pseed=st.integers(0, 2**31 - 1),
+       slices=st.sampled_from([1, 8]))
+def test_random_directed_graphs_match_dense_solve(torch_cuda, g, c, pseed, slices):
+    """Directed plans (dangling vertices, empty rows) through the power method,
+    in row order or column-sliced."""
     from paper_2112_01743_amd import Plan
     rng = np.random.default_rng(pseed)
     p = rng.random(g.n) ** 3 + 1e-3
     p /= p.sum()
-    print(f"directed n={g.n} nnz={g.nnz} c={c:.3f}", flush=True)
-    plan = Plan.from_graph(g, c, directed=1)
+    print(f"directed n={g.n} nnz={g.nnz} c={c:.3f} slices={slices}", flush=True)
+    plan = Plan.from_graph(g, c, directed=1, column_slices=slices)
     x, rep = plan.solve_power(_dev(torch_cuda, p), 1e-9)
     pi = oracle.pagerank_directed_exact(g, p, c)
     err = np.abs(x.cpu().numpy() - pi).sum()

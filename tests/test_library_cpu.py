@@ -113,14 +113,16 @@ def test_plan_rejects_bad_damping_and_options():
 
 def test_directed_plan_options():
     """directed = 1 accepts asymmetric patterns and empty rows (the plan then
-    fails only at its first device allocation when there is no GPU) and
-    rejects the options that need an undirected graph."""
+    fails only at its first device allocation when there is no GPU), also
+    with column slices, and rejects the options that need an undirected graph."""
     rp = np.array([0, 0, 1, 3], dtype=np.int32)     # edges 0->1, 0->2, 1->2; row 0 empty
     ci = np.array([0, 0, 1], dtype=np.int32)
     assert _plan_status(rp, ci) in (B.CPAA_ENOTSYM, B.CPAA_EISOLATED)
     assert _plan_status(rp, ci, directed=1) in (B.CPAA_OK, B.CPAA_ENOMEM, B.CPAA_EDEVICE)
-    for bad in ({"directed": 2}, {"directed": 1, "column_slices": 8},
-                {"directed": 1, "locality_order": 2}, {"directed": 1, "spectral_interval": 1}):
+    assert _plan_status(rp, ci, directed=1, column_slices=8) in (B.CPAA_OK, B.CPAA_ENOMEM,
+                                                                 B.CPAA_EDEVICE)
+    for bad in ({"directed": 2}, {"directed": 1, "locality_order": 2},
+                {"directed": 1, "spectral_interval": 1}):
         assert _plan_status(rp, ci, **bad) == B.CPAA_EINVAL, bad
 
 
