@@ -256,8 +256,9 @@ cpaa_status run_series(cpaa_plan_s* pl, Workspace& ws, TermFn term, int series_i
   const std::vector<AccUpdate> acc_plan = acc_schedule(series_coef(pl, ws), k_cap, k_min);
   // The power method's a-priori cap (from c^k alone) can run far past the stop,
   // so its launches are enqueued in chunks and the stop flags are read one chunk
-  // behind (the GPU always has the next chunk queued); at most one chunk of
-  // launches that return at once is left.
+  // behind (the GPU always has the next chunk queued).  A stop inside chunk j
+  // is seen after chunk j + 1 is enqueued, so up to 2 kChunk - 1 launches past
+  // the stop are issued; they return at once.
   constexpr int kChunk = 8;
   const bool poll = ws.method == Method::kPower && ws.poll_host != nullptr &&
                     pl->ev_poll[0] != nullptr && k_cap > 2 * kChunk;
