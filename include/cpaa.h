@@ -133,11 +133,16 @@ typedef struct {
                              out-degree of v is the number of rows listing v; a vertex without
                              out-edges is dangling, and P' = P + p d^T sends its mass along p
                              (Sec. 2.1).  CPAA's expansion needs the real spectrum of an
-                             undirected graph (Sec. 3), so such a plan is solved by
-                             cpaa_solve_power only (single vector, x0 = NULL); every other solve
-                             call returns CPAA_EINVAL.  Needs one graph; RCM and the spectral
-                             interval are not used (CPAA_EINVAL when asked for); column slices
-                             are. */
+                             undirected graph (Sec. 3), so every solve of such a plan runs the
+                             power method: cpaa_solve falls back to it (report.method = 1), and
+                             the batched calls solve their columns one after another through
+                             the single-vector path.  No warm start (x0 / X0 must be NULL, else
+                             CPAA_EINVAL).  Needs one graph; RCM and the spectral interval are
+                             not used (CPAA_EINVAL when asked for); column slices are.
+                             2: detect.  The plan is directed if the pattern is not symmetric or
+                             has an empty row (a vertex without edges, dangling), else
+                             undirected; the other pattern rules are checked as for 1.
+                             cpaa_plan_info_get reports which. */
 } cpaa_opts;
 
 /* Per-solve report (one per right-hand side in batched calls, one per graph in
@@ -148,7 +153,8 @@ typedef struct {
   int32_t refinements;    /* correction series run */
   int32_t certified;      /* 1 if cert_bound <= tol */
   int32_t fallback_used;  /* warm start rejected and a plain solve done instead */
-  int32_t pad_;
+  int32_t method;         /* 0 CPAA (Chebyshev series), 1 the power method (cpaa_solve_power*,
+                             and every solve of a directed plan) */
   double cert_bound;      /* ||r||_1/(1-c) in FP64: upper bound on ||x - pi||_1 (before normalize) */
   double resid_l1;        /* ||r||_1, r = b - (I - cP)x */
   double resid_max;       /* ||r||_inf */
@@ -178,6 +184,7 @@ typedef struct {
   double vol;               /* sum of degrees */
   int32_t column_slices;    /* single-vector term: 1 (row order) or 8 (column-sliced) */
   double spectrum_lo;       /* a of the expansion interval [a, 1] (-1: the paper's) */
+  int32_t directed;         /* 1 for a directed plan (opts.directed = 1, or 2 and detected) */
 } cpaa_plan_info;
 
 /* Fill *o with defaults.  Never fails. */
@@ -216,6 +223,8 @@ CPAA_API cpaa_status cpaa_plan_info_get(cpaa_plan_t plan, cpaa_plan_info* info);
  * Pointers are device pointers if opts.io_device = 1, host pointers otherwise.
  * With opts.normalize = 1 the result is divided by its sum after
  * certification; the bound in the report refers to the unnormalized x.
+ * On a directed plan (opts.directed) the call runs the power method instead
+ * (as cpaa_solve_power; x0 must be NULL) and sets report.method = 1.
  * Returns CPAA_OK when certified, CPAA_ENOCONV when not (x still written). */
 CPAA_API cpaa_status cpaa_solve(cpaa_plan_t plan, const double* p, double tol, const double* x0,
                        double* x, cpaa_report* rep, void* stream);
@@ -224,7 +233,9 @@ CPAA_API cpaa_status cpaa_solve(cpaa_plan_t plan, const double* p, double tol, c
  * likewise X0 (may be NULL) and X.  The right-hand sides are processed in
  * tiles of opts.tile_w columns by one SpMM kernel per term; each tile stops
  * when all its columns are certified (per-column in-loop certificate), and
- * each column gets its own FP64 residual and report.
+ * each column gets its own FP64 residual and report.  On a directed plan the
+ * columns are solved one after another by the single-vector power method
+ * (X0 must be NULL).
  * reps: [B] or NULL.  ldp, ldx0, ldx >= n.  Other rules as cpaa_solve. */
 CPAA_API cpaa_status cpaa_solve_batched(cpaa_plan_t plan, int32_t B, const double* P, int64_t ldp,
                                double tol, const double* X0, int64_t ldx0, double* X,

@@ -44,7 +44,7 @@ class cpaa_opts(ctypes.Structure):
 class cpaa_report(ctypes.Structure):
     _fields_ = [("terms", ctypes.c_int32), ("refine_terms", ctypes.c_int32),
                 ("refinements", ctypes.c_int32), ("certified", ctypes.c_int32),
-                ("fallback_used", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("fallback_used", ctypes.c_int32), ("method", ctypes.c_int32),
                 ("cert_bound", ctypes.c_double), ("resid_l1", ctypes.c_double),
                 ("resid_max", ctypes.c_double), ("mass", ctypes.c_double),
                 ("series_cert", ctypes.c_double), ("ms_total", ctypes.c_double),
@@ -52,7 +52,7 @@ class cpaa_report(ctypes.Structure):
                 ("edges", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad_"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class cpaa_plan_info(ctypes.Structure):
@@ -62,7 +62,8 @@ class cpaa_plan_info(ctypes.Structure):
                 ("work_items", ctypes.c_int32), ("tile_w", ctypes.c_int32),
                 ("k_cap_global", ctypes.c_int32), ("c", ctypes.c_double),
                 ("beta", ctypes.c_double), ("vol", ctypes.c_double),
-                ("column_slices", ctypes.c_int32), ("spectrum_lo", ctypes.c_double)]
+                ("column_slices", ctypes.c_int32), ("spectrum_lo", ctypes.c_double),
+                ("directed", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

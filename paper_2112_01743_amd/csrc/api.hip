@@ -565,8 +565,8 @@ cpaa_status cpaa_plan(const cpaa_csr* g, double c, const cpaa_opts* opts, cpaa_p
     set_error("spectral_interval needs a single-graph plan");
     return CPAA_EINVAL;
   }
-  if (o.directed != 0 && o.directed != 1) {
-    set_error("directed must be 0 or 1");
+  if (o.directed < 0 || o.directed > 2) {
+    set_error("directed must be 0, 1 or 2");
     return CPAA_EINVAL;
   }
   if (o.directed == 1 &&
@@ -609,8 +609,21 @@ cpaa_status cpaa_plan(const cpaa_csr* g, double c, const cpaa_opts* opts, cpaa_p
       gp = h_gp.data();
     }
   }
-  if (o.validate) {
-    cpaa_status s = validate_pattern(n, nnz, rp, ci, o.directed == 0, o.directed == 1);
+  bool directed = o.directed == 1;
+  if (o.directed == 2) {
+    // detect: a pattern that is not symmetric, or has an empty row (a dangling
+    // vertex), makes a directed plan
+    cpaa_status s = validate_pattern(n, nnz, rp, ci, false, true);
+    if (s != CPAA_OK) return s;
+    directed = validate_pattern(n, nnz, rp, ci, true, false) != CPAA_OK;
+    set_error("");
+    if (directed && (g->num_graphs > 1 || o.locality_order == 2 || o.spectral_interval == 1)) {
+      set_error("the pattern is directed (not symmetric, or with an empty row); directed plans "
+                "need one graph and no RCM or spectral interval");
+      return CPAA_EINVAL;
+    }
+  } else if (o.validate) {
+    cpaa_status s = validate_pattern(n, nnz, rp, ci, !directed, directed);
     if (s != CPAA_OK) return s;
   } else if (rp[0] != 0 || rp[n] != nnz) {
     set_error("row_ptr[0] must be 0 and row_ptr[n] must equal nnz");
@@ -658,7 +671,7 @@ cpaa_status cpaa_plan(const cpaa_csr* g, double c, const cpaa_opts* opts, cpaa_p
     mind = std::min(mind, d);
     vol += d;
   }
-  pl->directed = o.directed == 1;
+  pl->directed = directed;
   if (mind <= 0 && !pl->directed) {
     cpaa_plan_destroy(pl);
     set_error("isolated vertex (degree 0)");
@@ -874,6 +887,7 @@ cpaa_status cpaa_plan_info_get(cpaa_plan_t pl, cpaa_plan_info* info) {
   info->k_cap_global = mass_rule_terms(pl, 1e-6);
   info->column_slices = pl->sliced ? kSlices : 1;
   info->spectrum_lo = pl->lam_lo;
+  info->directed = pl->directed ? 1 : 0;
   return CPAA_OK;
 }
 

@@ -395,12 +395,37 @@ namespace {
 cpaa_status solve_directed(cpaa_plan_t pl, const double* p, double tol, double* x,
                            cpaa_report* rep, void* stream);
 
+// Batched solves of a directed plan: the power method, one column after
+// another through the single-vector path (no tiled directed kernel).
+cpaa_status solve_directed_columns(cpaa_plan_t pl, int32_t B, const double* P, int64_t ldp,
+                                   double tol, double* X, int64_t ldx, cpaa_report* reps,
+                                   void* stream) {
+  bool all_ok = true;
+  for (int32_t j = 0; j < B; ++j) {
+    cpaa_report R;
+    std::memset(&R, 0, sizeof(R));
+    const cpaa_status s = solve_directed(pl, P + (size_t)j * ldp, tol, X + (size_t)j * ldx, &R,
+                                         stream);
+    if (s != CPAA_OK && s != CPAA_ENOCONV) return s;
+    all_ok = all_ok && s == CPAA_OK;
+    if (reps) reps[j] = R;
+  }
+  if (!all_ok) {
+    set_error("tolerance not certified for every column");
+    return CPAA_ENOCONV;
+  }
+  set_error("");
+  return CPAA_OK;
+}
+
 cpaa_status solve_single(cpaa_plan_t pl, const double* p, double tol, const double* x0, double* x,
                          cpaa_report* rep, void* stream, Method method) {
   set_error("");
   if (pl && pl->directed) {
-    if (method != Method::kPower || x0) {
-      set_error("a directed plan is solved by cpaa_solve_power without x0");
+    // CPAA's expansion needs the real spectrum of an undirected graph, so every
+    // solve of a directed plan runs the power method (report.method = 1)
+    if (x0) {
+      set_error("a directed plan has no warm start (x0 must be NULL)");
       return CPAA_EINVAL;
     }
     return solve_directed(pl, p, tol, x, rep, stream);
@@ -448,6 +473,7 @@ cpaa_status solve_single(cpaa_plan_t pl, const double* p, double tol, const doub
   std::vector<int> series_terms;
   cpaa_report R;
   std::memset(&R, 0, sizeof(R));
+  R.method = method == Method::kPower ? 1 : 0;
   CPAA_HIP(hipEventRecord(pl->ev_begin, st));
   CPAA_HIP(fill_f64(ws.stat_slots, 0.0, (size_t)2 * kSlots * ws.cols * kStat, st));
 
@@ -579,8 +605,19 @@ cpaa_status solve_batched(cpaa_plan_t pl, int32_t B, const double* P, int64_t ld
                           cpaa_report* reps, void* stream, Method method) {
   set_error("");
   if (pl && pl->directed) {
-    set_error("a directed plan is solved by cpaa_solve_power (single vector)");
-    return CPAA_EINVAL;
+    if (!P || !X || B <= 0) {
+      set_error("cpaa_solve_batched: null argument or B <= 0");
+      return CPAA_EINVAL;
+    }
+    if (X0) {
+      set_error("a directed plan has no warm start (X0 must be NULL)");
+      return CPAA_EINVAL;
+    }
+    if (ldp < pl->n || ldx < pl->n) {
+      set_error("leading dimensions must be >= n");
+      return CPAA_EINVAL;
+    }
+    return solve_directed_columns(pl, B, P, ldp, tol, X, ldx, reps, stream);
   }
   if (!pl || !P || !X || B <= 0) {
     set_error("cpaa_solve_batched: null argument or B <= 0");
@@ -802,6 +839,7 @@ cpaa_status solve_batched(cpaa_plan_t pl, int32_t B, const double* P, int64_t ld
     const int t = j / W;
     cpaa_report R;
     std::memset(&R, 0, sizeof(R));
+    R.method = method == Method::kPower ? 1 : 0;
     R.terms = terms_main[t];
     R.refine_terms = refine_terms[t];
     R.refinements = refinements[t];
@@ -864,6 +902,7 @@ cpaa_status solve_directed(cpaa_plan_t pl, const double* p, double tol, double* 
   std::vector<int> series_terms;
   cpaa_report R;
   std::memset(&R, 0, sizeof(R));
+  R.method = 1;
   CPAA_HIP(hipEventRecord(pl->ev_begin, st));
   CPAA_HIP(fill_f64(ws.stat_slots, 0.0, (size_t)2 * kSlots * ws.cols * kStat, st));
   CPAA_HIP(fill_f64(ws.dang, 0.0, 3 * kSlots, st));

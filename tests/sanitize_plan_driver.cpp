@@ -144,6 +144,14 @@ int main() {
     d.ci = {0, 0, 1, 2};
     const cpaa_opts dir = with([](cpaa_opts& o) { o.directed = 1; });
     expect("directed", d, dir, true);
+    const cpaa_opts dir_sl = with([](cpaa_opts& o) {
+      o.directed = 1;
+      o.column_slices = 8;
+    });
+    expect("directed column_slices=8", d, dir_sl, true);
+    const cpaa_opts detect = with([](cpaa_opts& o) { o.directed = 2; });
+    expect("directed=2 (detect)", d, detect, true);
+    expect("directed=2 on an undirected graph", lattice(40), detect, true);
   }
   // invalid patterns are rejected before any device work
   Graph asym = from_edges(4, {{0, 1}, {1, 2}, {2, 3}});
@@ -160,6 +168,19 @@ int main() {
   expect("column out of range", range, base, false, CPAA_EPATTERN);
   Graph iso = from_edges(4, {{0, 1}, {1, 2}});
   expect("isolated vertex", iso, base, false, CPAA_EISOLATED);
+  // detection makes directed plans of the asymmetric and the isolated-vertex
+  // patterns, but still rejects what no plan accepts
+  const cpaa_opts detect = with([](cpaa_opts& o) { o.directed = 2; });
+  expect("directed=2 asymmetric", asym, detect, true);
+  expect("directed=2 isolated vertex", iso, detect, true);
+  expect("directed=2 self loop", loop, detect, false, CPAA_ESELFLOOP);
+  expect("directed=2 column out of range", range, detect, false, CPAA_EPATTERN);
+  const cpaa_opts detect_rcm = with([](cpaa_opts& o) {
+    o.directed = 2;
+    o.locality_order = 2;
+  });
+  expect("directed=2 asymmetric with RCM", asym, detect_rcm, false, CPAA_EINVAL);
+  expect("directed=2 undirected with RCM", lattice(40), detect_rcm, true);
   std::printf("%s\n", failures ? "FAILED" : "ALL OK");
   return failures ? 1 : 0;
 }

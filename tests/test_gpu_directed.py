@@ -137,14 +137,77 @@ def test_directed_large_and_host_io(torch_cuda, slices):
     assert np.abs(xh - pi).sum() <= 1e-8
 
 
-def test_directed_plan_rejects_other_solves(torch_cuda):
+@pytest.mark.parametrize("slices", [1, 8])
+def test_every_solve_of_a_directed_plan_runs_the_power_method(torch_cuda, slices):
+    """cpaa_solve falls back to the power method (report.method = 1); the
+    batched calls solve column by column; a warm start is refused."""
     from paper_2112_01743_amd import CpaaError
     g = GRAPHS["random5000"]()
-    plan = _plan(g)
-    p = _dev(torch_cuda, gg.uniform_personalization(g.n))
-    for call in (lambda: plan.solve(p, 1e-6),
-                 lambda: plan.solve_power(p, 1e-6, x0=p),
-                 lambda: plan.solve_batched(p[None, :].contiguous(), 1e-6),
-                 lambda: plan.solve_power_batched(p[None, :].contiguous(), 1e-6)):
+    plan = _plan(g, column_slices=slices)
+    assert plan.info()["directed"] == 1
+    ps = [gg.uniform_personalization(g.n), gg.source_personalization(g.n, [7])[0],
+          gg.source_personalization(g.n, [g.n - 2])[0]]
+    pis = [oracle.pagerank_directed_exact(g, p, C) for p in ps]
+    tol = 1e-9
+    for name in ("solve", "solve_power"):
+        x, rep = getattr(plan, name)(_dev(torch_cuda, ps[0]), tol)
+        err = np.abs(x.cpu().numpy() - pis[0]).sum()
+        _note(f"{name} slices={slices}: method {rep['method']} err {err:.2e}")
+        assert rep["method"] == 1 and rep["certified"] == 1 and err <= tol
+    P = _dev(torch_cuda, np.stack(ps))
+    for name in ("solve_batched", "solve_power_batched"):
+        X, reps = getattr(plan, name)(P, tol)
+        errs = [np.abs(X[j].cpu().numpy() - pis[j]).sum() for j in range(3)]
+        _note(f"{name} slices={slices}: errs {max(errs):.2e}")
+        assert np.all(reps["method"] == 1) and np.all(reps["certified"] == 1)
+        assert max(errs) <= tol
+    p0 = _dev(torch_cuda, ps[0])
+    for call in (lambda: plan.solve(p0, 1e-6, x0=p0),
+                 lambda: plan.solve_power(p0, 1e-6, x0=p0),
+                 lambda: plan.solve_batched(P, 1e-6, X0=P),
+                 lambda: plan.solve_power_batched(P, 1e-6, X0=P)):
         with pytest.raises(CpaaError):
             call()
+
+
+def test_directed_batched_host_io_with_padding(torch_cuda):
+    """Host buffers with leading dimensions above n through the column loop."""
+    from paper_2112_01743_amd import Plan
+    from paper_2112_01743_amd import binding as B
+    g = GRAPHS["hubs20000"]()
+    plan = Plan.from_graph(g, C, directed=1, io_device=0)
+    n, ldp, ldx = g.n, g.n + 3, g.n + 5
+    srcs = [0, 1, 2, 17]
+    P = np.zeros((len(srcs), ldp))
+    for j, s in enumerate(srcs):
+        P[j, :n] = gg.source_personalization(n, [s])[0]
+    X = np.full((len(srcs), ldx), -7.0)
+    st, reps = B.cpaa_solve_batched(plan.handle, len(srcs), P.ctypes.data, ldp, 1e-9, None, n,
+                                    X.ctypes.data, ldx)
+    assert st == B.CPAA_OK, B.cpaa_last_error()
+    for j in range(len(srcs)):
+        pi = oracle.power_method_directed(g, P[j, :n], C, 200)
+        assert reps[j].method == 1 and reps[j].certified == 1
+        assert np.abs(X[j, :n] - pi).sum() <= 1e-9
+        assert np.all(X[j, n:] == -7.0)          # padding untouched
+
+
+def test_detection_picks_the_plan(torch_cuda):
+    """directed = 2: an asymmetric pattern, or a symmetric one with an isolated
+    vertex (dangling: its mass goes along p, Sec. 2.1), makes a directed plan;
+    a symmetric pattern without empty rows stays undirected (CPAA)."""
+    from paper_2112_01743_amd import Plan
+    tol = 1e-10
+    asym = GRAPHS["random5000"]()
+    sym = gg.random_connected(3000, 6, seed=5)
+    rp = np.concatenate([sym.row_ptr, sym.row_ptr[-1:]]).astype(np.int32)   # vertex n isolated
+    iso = gg.CSR(n=sym.n + 1, row_ptr=rp, col_idx=sym.col_idx.copy())
+    for g, want in ((asym, 1), (sym, 0), (iso, 1)):
+        plan = Plan.from_graph(g, C, directed=2)
+        p = gg.uniform_personalization(g.n)
+        x, rep = plan.solve(_dev(torch_cuda, p), tol)
+        pi = oracle.pagerank_directed_exact(g, p, C)
+        err = np.abs(x.cpu().numpy() - pi).sum()
+        _note(f"n={g.n}: directed {plan.info()['directed']} method {rep['method']} err {err:.2e}")
+        assert plan.info()["directed"] == want and rep["method"] == want
+        assert rep["certified"] == 1 and err <= tol

@@ -121,8 +121,10 @@ def test_directed_plan_options():
     assert _plan_status(rp, ci, directed=1) in (B.CPAA_OK, B.CPAA_ENOMEM, B.CPAA_EDEVICE)
     assert _plan_status(rp, ci, directed=1, column_slices=8) in (B.CPAA_OK, B.CPAA_ENOMEM,
                                                                  B.CPAA_EDEVICE)
-    for bad in ({"directed": 2}, {"directed": 1, "locality_order": 2},
-                {"directed": 1, "spectral_interval": 1}):
+    # detection (directed = 2) takes the asymmetric pattern with its empty row
+    assert _plan_status(rp, ci, directed=2) in (B.CPAA_OK, B.CPAA_ENOMEM, B.CPAA_EDEVICE)
+    for bad in ({"directed": 3}, {"directed": -1}, {"directed": 1, "locality_order": 2},
+                {"directed": 1, "spectral_interval": 1}, {"directed": 2, "locality_order": 2}):
         assert _plan_status(rp, ci, **bad) == B.CPAA_EINVAL, bad
 
 
