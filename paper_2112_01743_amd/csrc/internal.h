@@ -123,6 +123,8 @@ struct Workspace {
   double* dang = nullptr;        // directed plans: [5][kSlots] dangling mass of the increment
                                  // in z[0..2], then of x and |x| for the residual
   double* wdir = nullptr;        // directed plans: [n] FP64 D_out^+ x for the residual
+  double* part_d = nullptr;      // column-sliced directed plans: [kSlices][n][2] FP64 partial
+                                 // sums of w and |w| (residual)
   const double* dir_x0 = nullptr;  // directed power method: start of the series in progress
   double dir_x0_scale = 1.0;       //   x_0 = dir_x0_scale * dir_x0
   float* split_f = nullptr;      // [split slots * W] FP32 partial sums

@@ -219,58 +219,80 @@ __global__ __launch_bounds__(kWG) void k_term_w1(TermArgs a) {
 // XCD's gathers stay inside one eighth of z_k, which its L2 holds.  Each item
 // writes the partial row sums of its rows into part[slice][row] (zeros for
 // rows without entries in the slice).  Pass 2 (k_combine_w1) adds the eight
-// partials in a fixed order and runs the term epilogue.
-struct SlicedArgs {
+// partials in a fixed order and runs the term epilogue.  The FP64 residual of
+// a directed plan runs the same pass over w = D_out^+ x (k_resid_sliced), with
+// a second partial per row, the sum of magnitudes its rounding bound needs.
+template <typename V>
+struct SlicedArgsT {
   const uint32_t* entries;
   const WorkItem* items;
   const int* rp;
-  const float* zc;
-  float* part;
+  const V* zc;
+  V* part;                // [kSlices][n], or [kSlices][n][2] (sum, sum of magnitudes)
   const int* done;
-  float* split_part;
+  V* split_part;
   int* split_count;
   const int* split_nchunks;
   int n;
   int item_off[kSlices + 1];
   int slice_off[kSlices + 1];
 };
+using SlicedArgs = SlicedArgsT<float>;
 
+template <typename V, bool ABS>
 struct PartEpi {
-  float* __restrict__ out;
-  __device__ __forceinline__ void row(int r, int, float s, float) { out[r] = s; }
+  V* __restrict__ out;
+  __device__ __forceinline__ void row(int r, int, V s, V sa) {
+    if constexpr (ABS) {
+      static_assert(sizeof(V) == sizeof(double), "pairs are stored as double2");
+      reinterpret_cast<double2*>(out)[r] = make_double2(s, sa);
+    } else {
+      out[r] = s;
+    }
+  }
 };
 
-template <int NPT, int RB>
-__global__ __launch_bounds__(kWG) void k_term_sliced(SlicedArgs a) {
-  if (a.done != nullptr && *a.done) return;
+template <typename V, bool ABS, int NPT, int RB>
+__device__ __forceinline__ void gather_sliced(const SlicedArgsT<V>& a) {
   const int sl = blockIdx.x % kSlices;
   const int k = a.item_off[sl] + static_cast<int>(blockIdx.x / kSlices);
   if (k >= a.item_off[sl + 1]) return;
   const WorkItem it = a.items[k];
-  const float* __restrict__ xs = a.zc + a.slice_off[sl];
-  PartEpi epi{a.part + static_cast<size_t>(sl) * a.n};
+  const V* __restrict__ xs = a.zc + a.slice_off[sl];
+  PartEpi<V, ABS> epi{a.part + static_cast<size_t>(sl) * a.n * (ABS ? 2 : 1)};
   constexpr uint32_t kNone = kSliceNone;
   const int t = threadIdx.x;
   if (it.row1 < 0) {
     // chunk of a split row: plain local columns
-    float sum = 0.f;
+    V sum = V(0), suma = V(0);
 #pragma unroll
     for (int i = 0; i < NPT; ++i) {
       const int j = it.nnz0 + t + i * kWG;
-      if (j < it.nnz1) sum += xs[__builtin_nontemporal_load(a.entries + j)];
+      if (j < it.nnz1) {
+        const V x = xs[__builtin_nontemporal_load(a.entries + j)];
+        sum += x;
+        if (ABS) suma += fabs(x);
+      }
     }
-    split_chunk_finish<float, false>(it, a.rp, sum, 0.f, a.split_part, a.split_count,
-                                     a.split_nchunks, epi);
+    split_chunk_finish<V, ABS>(it, a.rp, sum, suma, a.split_part, a.split_count,
+                               a.split_nchunks, epi);
     return;
   }
-  __shared__ float rsum[kSliceRowsMax];
-  __shared__ float hub[kSliceHub];
+  __shared__ V rsum[kSliceRowsMax];
+  __shared__ V rabs[ABS ? kSliceRowsMax : 1];
+  __shared__ V hub[ABS ? 1 : kSliceHub];
   const int lane = t & 63;
   const int nrows = it.row1 - it.row0;
-  for (int r = t; r < nrows; r += kWG) rsum[r] = 0.f;
+  for (int r = t; r < nrows; r += kWG) {
+    rsum[r] = V(0);
+    if (ABS) rabs[r] = V(0);
+  }
   // The slice's first kSliceHub vertices (its highest degrees, the targets of
-  // a large share of all gathers) are copied to LDS with coalesced loads.
-  const int nhub = min(kSliceHub, a.slice_off[sl + 1] - a.slice_off[sl]);
+  // a large share of all gathers) are copied to LDS with coalesced loads.  Not
+  // in the FP64 pass with magnitudes: there the LDS copy and its registers
+  // would halve the waves per CU (80 KB of LDS, over 256 registers).
+  constexpr bool kHub = !ABS;
+  const int nhub = kHub ? min(kSliceHub, a.slice_off[sl + 1] - a.slice_off[sl]) : 0;
   for (int c = t; c < nhub; c += kWG) hub[c] = xs[c];
   // Wavefront w owns the logical entries [q0, q0 + Lw); lane l owns the
   // contiguous run [l*RL, (l+1)*RL) of them, stored transposed (element i of
@@ -284,13 +306,13 @@ __global__ __launch_bounds__(kWG) void k_term_sliced(SlicedArgs a) {
 #pragma unroll
   for (int i = 0; i < NPT; ++i) e[i] = (i < RL) ? __builtin_nontemporal_load(pe + i * 64) : kNone;
   __syncthreads();
-  float v[NPT];
+  V v[NPT];
 #pragma unroll
   for (int i = 0; i < NPT; ++i) {
-    float h = 0.f, g = 0.f;
+    V h = V(0), g = V(0);
     const uint32_t c = e[i] >> RB;
-    if (e[i] != kNone && c < static_cast<uint32_t>(kSliceHub)) h = hub[c];
-    if (e[i] != kNone && c >= static_cast<uint32_t>(kSliceHub)) g = xs[c];
+    if (kHub && e[i] != kNone && c < static_cast<uint32_t>(kSliceHub)) h = hub[c];
+    if (e[i] != kNone && (!kHub || c >= static_cast<uint32_t>(kSliceHub))) g = xs[c];
     v[i] = h + g;
   }
   // Row sums of the run in a register.  A row that starts and ends strictly
@@ -298,7 +320,7 @@ __global__ __launch_bounds__(kWG) void k_term_sliced(SlicedArgs a) {
   // last row of a run may be shared with neighbouring runs: LDS atomic.
   constexpr uint32_t row_mask = (1u << RB) - 1u;
   int row = -1;
-  float sum = 0.f;
+  V sum = V(0), suma = V(0);
   bool first = true;
 #pragma unroll
   for (int i = 0; i < NPT; ++i) {
@@ -306,29 +328,51 @@ __global__ __launch_bounds__(kWG) void k_term_sliced(SlicedArgs a) {
       const int r = static_cast<int>(e[i] & row_mask);
       if (r != row) {
         if (row >= 0) {
-          if (first)
+          if (first) {
             atomicAdd(&rsum[row], sum);
-          else
+            if (ABS) atomicAdd(&rabs[row], suma);
+          } else {
             rsum[row] = sum;
+            if (ABS) rabs[row] = suma;
+          }
           first = false;
         }
         row = r;
         sum = v[i];
+        if (ABS) suma = fabs(v[i]);
       } else {
         sum += v[i];
+        if (ABS) suma += fabs(v[i]);
       }
     }
   }
   // a row that covers every run of the wavefront: one wavefront sum
   const int row_l0 = __builtin_amdgcn_readfirstlane(row);
   if (__all(row == row_l0) && row_l0 >= 0) {
-    const float ws = wave_sum(sum);
-    if (lane == 0) atomicAdd(&rsum[row_l0], ws);
+    const V ws = wave_sum(sum);
+    V wa = V(0);
+    if (ABS) wa = wave_sum(suma);
+    if (lane == 0) {
+      atomicAdd(&rsum[row_l0], ws);
+      if (ABS) atomicAdd(&rabs[row_l0], wa);
+    }
   } else if (row >= 0) {
     atomicAdd(&rsum[row], sum);
+    if (ABS) atomicAdd(&rabs[row], suma);
   }
   __syncthreads();
-  for (int r = t; r < nrows; r += kWG) epi.out[it.row0 + r] = rsum[r];
+  for (int r = t; r < nrows; r += kWG) epi.row(it.row0 + r, 0, rsum[r], ABS ? rabs[r] : V(0));
+}
+
+template <int NPT, int RB>
+__global__ __launch_bounds__(kWG) void k_term_sliced(SlicedArgs a) {
+  if (a.done != nullptr && *a.done) return;
+  gather_sliced<float, false, NPT, RB>(a);
+}
+
+template <int NPT, int RB>
+__global__ __launch_bounds__(kWG) void k_resid_sliced(SlicedArgsT<double> a) {
+  gather_sliced<double, true, NPT, RB>(a);
 }
 
 struct CombineArgs {
@@ -710,6 +754,61 @@ __global__ __launch_bounds__(kWG) void k_resid_dir(DirResidArgs a) {
   }
 }
 
+// Residual of a column-sliced directed plan: k_resid_sliced left per slice
+// the partial sums of w and of |w| over each row's in-neighbours; add the
+// eight pairs and run k_resid_dir's epilogue (same rounding allowance: the
+// partial sums and this addition are one summation of the row's k terms).
+struct DirResidCombineArgs {
+  const double2* part;
+  const int* rp;
+  const double* acc;
+  const double* b;
+  double* r;
+  const double* dx;
+  const double* dxa;
+  double c, nu;
+  double* stat_slots;
+  int n;
+};
+
+__global__ __launch_bounds__(kWG) void k_resid_combine_dir(DirResidCombineArgs a) {
+  __shared__ double m_sh[2];
+  if (threadIdx.x < 64) {
+    const double m = slot_sum(a.dx), ma = slot_sum(a.dxa);
+    if (threadIdx.x == 0) {
+      m_sh[0] = m;
+      m_sh[1] = ma;
+    }
+  }
+  __syncthreads();
+  DirResidEpi epi{a.acc, a.b, a.r, a.c, m_sh[0], m_sh[1], 1.0 / (1.0 - a.c), a.nu,
+                  0.0, 0.0, 0.0, 0.0, 0.0};
+  const size_t n = static_cast<size_t>(a.n);
+  for (int u = blockIdx.x * kWG + threadIdx.x; u < a.n; u += gridDim.x * kWG) {
+    double s = 0.0, sa = 0.0;
+#pragma unroll
+    for (int k = 0; k < kSlices; ++k) {
+      const double2 q = a.part[k * n + u];
+      s += q.x;
+      sa += q.y;
+    }
+    epi.row(u, a.rp[u + 1] - a.rp[u], s, sa);
+  }
+  const double s_abs = block_sum256(epi.f_abs);
+  const double s_max = block_max256(epi.f_max);
+  const double s_mass = block_sum256(epi.f_mass);
+  const double s_round = block_sum256(epi.f_round);
+  const double s_bad = block_sum256(epi.f_bad);
+  if (threadIdx.x == 0) {
+    double* o = a.stat_slots + (size_t)(blockIdx.x % kSlots) * kStat;
+    atomic_add(&o[0], s_abs);
+    atomic_max_nonneg(&o[1], s_max);
+    atomic_add(&o[3], s_mass);
+    atomic_add(&o[4], s_round);
+    if (s_bad != 0.0) atomic_add(&o[5], s_bad);
+  }
+}
+
 __global__ __launch_bounds__(kWG) void k_finalize_dir(int n, const int* __restrict__ perm,
                                                       const double* __restrict__ acc,
                                                       double scale, double* __restrict__ x) {
@@ -781,23 +880,31 @@ hipError_t load_x0_w1(const cpaa_plan_s* pl, Workspace& ws, const double* x0, hi
 
 namespace {
 
-// Pass 1 of a column-sliced term: partial sums of z_cur per column slice into ws.part.
-void sliced_pass(const cpaa_plan_s* pl, Workspace& ws, int cur, const int* done, hipStream_t st) {
-  SlicedArgs s;
+template <typename V>
+SlicedArgsT<V> sliced_args(const cpaa_plan_s* pl, const V* x, V* part, V* split_part,
+                           int* split_count, const int* done) {
+  SlicedArgsT<V> s;
   s.entries = pl->slc.d_entries;
   s.items = pl->slc.d_items;
   s.rp = pl->d_rp_w1;
-  s.zc = ws.z[cur];
-  s.part = ws.part;
+  s.zc = x;
+  s.part = part;
   s.done = done;
-  s.split_part = ws.split_f;
-  s.split_count = ws.split_count;
+  s.split_part = split_part;
+  s.split_count = split_count;
   s.split_nchunks = pl->slc.d_split_nchunks;
   s.n = pl->n;
   for (int i = 0; i <= kSlices; ++i) {
     s.item_off[i] = pl->slc.item_off[i];
     s.slice_off[i] = pl->slc.slice_off[i];
   }
+  return s;
+}
+
+// Pass 1 of a column-sliced term: partial sums of z_cur per column slice into ws.part.
+void sliced_pass(const cpaa_plan_s* pl, Workspace& ws, int cur, const int* done, hipStream_t st) {
+  const SlicedArgs s = sliced_args<float>(pl, ws.z[cur], ws.part, ws.split_f, ws.split_count,
+                                          done);
   const dim3 grid(kSlices * pl->slc.max_items);
   if (pl->slc.row_bits == kSliceRowBitsMax)
     hipLaunchKernelGGL((k_term_sliced<kSliceNpt, kSliceRowBitsMax>), grid, dim3(kWG), 0, st, s);
@@ -960,6 +1067,32 @@ hipError_t residual_dir(const cpaa_plan_s* pl, Workspace& ws, hipStream_t st) {
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_dir_w, dim3(elem_grid(pl->n)), dim3(kWG), 0, st, pl->n, pl->d_dout, ws.acc,
                      ws.wdir, dx, dxa);
+  const double nu = (static_cast<double>(pl->n) + 2.0) * 0x1p-53;
+  double* stat = ws.stat_slots + (size_t)kSlots * ws.cols * kStat;   // residual phase
+  if (pl->sliced) {
+    // FP64 gathers per column slice (pairs of partials), then the combine pass
+    const SlicedArgsT<double> s = sliced_args<double>(pl, ws.wdir, ws.part_d, ws.split_d,
+                                                      ws.split_count, nullptr);
+    const dim3 grid(kSlices * pl->slc.max_items);
+    if (pl->slc.row_bits == kSliceRowBitsMax)
+      hipLaunchKernelGGL((k_resid_sliced<kSliceNpt, kSliceRowBitsMax>), grid, dim3(kWG), 0, st, s);
+    else
+      hipLaunchKernelGGL((k_resid_sliced<kSliceNpt, 11>), grid, dim3(kWG), 0, st, s);
+    DirResidCombineArgs c;
+    c.part = reinterpret_cast<const double2*>(ws.part_d);
+    c.rp = pl->d_rp_w1;
+    c.acc = ws.acc;
+    c.b = ws.b;
+    c.r = ws.r;
+    c.dx = dx;
+    c.dxa = dxa;
+    c.c = pl->c;
+    c.nu = nu;
+    c.stat_slots = stat;
+    c.n = pl->n;
+    hipLaunchKernelGGL(k_resid_combine_dir, dim3(elem_grid(pl->n)), dim3(kWG), 0, st, c);
+    return hipGetLastError();
+  }
   DirResidArgs a;
   a.rp = pl->d_rp_w1;
   a.ci = pl->d_ci_w1;
@@ -971,8 +1104,8 @@ hipError_t residual_dir(const cpaa_plan_s* pl, Workspace& ws, hipStream_t st) {
   a.dx = dx;
   a.dxa = dxa;
   a.c = pl->c;
-  a.nu = (static_cast<double>(pl->n) + 2.0) * 0x1p-53;
-  a.stat_slots = ws.stat_slots + (size_t)kSlots * ws.cols * kStat;   // residual phase
+  a.nu = nu;
+  a.stat_slots = stat;
   a.split_part = ws.split_d;
   a.split_count = ws.split_count;
   a.split_nchunks = pl->d_split_nchunks;

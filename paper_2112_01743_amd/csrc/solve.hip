@@ -26,7 +26,8 @@
 namespace cpaa {
 
 void free_workspace(Workspace& ws) {
-  void* ptrs[] = {ws.z[0], ws.z[1], ws.z[2], ws.acc, ws.part, ws.dang, ws.wdir, ws.b, ws.r,
+  void* ptrs[] = {ws.z[0], ws.z[1], ws.z[2], ws.acc, ws.part, ws.dang, ws.wdir, ws.part_d,
+                  ws.b, ws.r,
                   ws.slots, ws.stat_slots,
                   ws.stat, ws.done, ws.terms, ws.series_cert, ws.split_f, ws.split_d,
                   ws.split_count, ws.active, ws.plain, ws.col_scale};
@@ -72,6 +73,8 @@ cpaa_status ensure_workspace(cpaa_plan_s* pl, Workspace& ws, int W, int tiles) {
   if (W == 1 && pl->directed) {
     ok = ok && alloc((void**)&ws.dang, (size_t)5 * kSlots * sizeof(double));
     ok = ok && alloc((void**)&ws.wdir, (size_t)pl->n * sizeof(double));
+    if (pl->sliced)
+      ok = ok && alloc((void**)&ws.part_d, (size_t)kSlices * pl->n * 2 * sizeof(double));
   }
   ok = ok && alloc((void**)&ws.b, ws.vec_elems * sizeof(double));
   ok = ok && alloc((void**)&ws.r, ws.vec_elems * sizeof(double));

@@ -115,6 +115,18 @@ def test_directed_certified_solve(torch_cuda, name, tol, slices):
               f"bound {rep['cert_bound']:.2e}")
         assert rep["status"] == "CPAA_OK" and rep["certified"] == 1, rep
         assert err <= tol and err <= rep["cert_bound"] * (1 + 1e-9) + 2e-13
+        # the library's FP64 residual of x (row order, or the column-sliced
+        # gather and combine) against the oracle's: r = (1-c)p - (I - cP')x.
+        # Both round; the library's rounding allowance (the part of cert_bound
+        # beyond ||r||_1) bounds its error, and the oracle's is of the same size.
+        Pm, d = oracle.transition_directed(g)
+        xs = x.cpu().numpy()
+        rl1 = np.abs((1 - C) * p - xs + C * (Pm @ xs + p * (d @ xs))).sum()
+        u = 2.0**-53
+        allowance = ((rep["cert_bound"] - u * abs(rep["mass"])) * (1 - C)
+                     - rep["resid_l1"] * (1 + 2 * u * g.n))
+        assert 0 <= allowance and abs(rep["resid_l1"] - rl1) <= 2 * allowance + 1e-15, \
+            (rep["resid_l1"], rl1, allowance)
 
 
 @pytest.mark.parametrize("slices", [1, 8])
