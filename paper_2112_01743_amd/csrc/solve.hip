@@ -262,7 +262,7 @@ cpaa_status run_series(cpaa_plan_s* pl, Workspace& ws, TermFn term, int series_i
   // behind (the GPU always has the next chunk queued).  A stop inside chunk j
   // is seen after chunk j + 1 is enqueued, so up to 2 kChunk - 1 launches past
   // the stop are issued; they return at once.
-  constexpr int kChunk = 8;
+  constexpr int kChunk = 4;
   const bool poll = ws.method == Method::kPower && ws.poll_host != nullptr &&
                     pl->ev_poll[0] != nullptr && k_cap > 2 * kChunk;
   int chunk = 0;
