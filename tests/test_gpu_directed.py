@@ -61,6 +61,9 @@ GRAPHS = {
     "three": lambda: _by_targets(3, [(0, 1), (0, 2), (1, 2)]),
     "random5000": lambda: gg.directed_random(5000, 6, 0.1, seed=4),
     "hubs20000": lambda: _hubs(20000),
+    # in-hub of 75,000 entries: more per column slice than a sliced work item
+    # holds, so the sliced term and residual passes split it too
+    "hubs100000": lambda: _hubs(100000),
 }
 
 
