@@ -108,9 +108,8 @@ typedef struct {
                              applies the term update.  Auto: on for one graph with n >= 3 * 2^18
                              and max degree >= 16 x average degree (for a directed plan also
                              when its entries span more than 2^14 labels on average).  Needs
-                             one graph and
-                             n < 8 (2^21 - 16) (else CPAA_EINVAL).  Inputs and outputs keep the caller's
-                             labels. */
+                             one graph and n < 8 (2^21 - 16) (else CPAA_EINVAL).  Inputs and
+                             outputs keep the caller's labels. */
   int32_t locality_order; /* single-vector path without column slices: 0 auto, 1 off (caller's
                              labels), 2 reverse Cuthill-McKee.  RCM relabels the vertices by a
                              breadth-first order from a pseudo-peripheral vertex, so that on

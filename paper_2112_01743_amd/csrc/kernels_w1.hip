@@ -867,7 +867,8 @@ __global__ __launch_bounds__(kWG) void k_combine_dir(DirCombineArgs a) {
 hipError_t init_w1(const cpaa_plan_s* pl, Workspace& ws, const double* src, double scale,
                    bool add, bool store_b, bool series, hipStream_t st) {
   hipLaunchKernelGGL(k_init_w1, dim3(elem_grid(pl->n)), dim3(kWG), 0, st, pl->n, pl->d_rp_w1,
-                     src == ws.r ? nullptr : pl->d_perm, src, scale, add ? 1 : 0, store_b ? 1 : 0, series ? 1 : 0, series_a0(pl, ws),
+                     src == ws.r ? nullptr : pl->d_perm, src, scale, add ? 1 : 0,
+                     store_b ? 1 : 0, series ? 1 : 0, series_a0(pl, ws),
                      ws.b, ws.z[0], ws.acc, ws.stat_slots);
   return hipGetLastError();
 }

@@ -584,7 +584,8 @@ cpaa_status solve_single(cpaa_plan_t pl, const double* p, double tol, const doub
   const double scale = pl->opts.normalize ? 1.0 / R.mass : 1.0;
   CPAA_HIP(finalize_w1(pl, ws, dx, scale, st));
   CPAA_HIP(hipEventRecord(pl->ev_end, st));
-  if (!pl->opts.io_device) CPAA_HIP(hipMemcpyAsync(x, dx, n * sizeof(double), hipMemcpyDeviceToHost, st));
+  if (!pl->opts.io_device)
+    CPAA_HIP(hipMemcpyAsync(x, dx, n * sizeof(double), hipMemcpyDeviceToHost, st));
   CPAA_HIP(hipStreamSynchronize(st));
   float ms = 0.f;
   CPAA_HIP(hipEventElapsedTime(&ms, pl->ev_begin, pl->ev_end));

@@ -114,8 +114,8 @@ def test_directed_certified_solve(torch_cuda, name, tol, slices):
               oracle.power_method_directed(g, p, C, int(np.log(1e-15) / np.log(C)) + 1))
         x, rep = _plan(g, column_slices=slices).solve_power(_dev(torch_cuda, p), tol)
         err = np.abs(x.cpu().numpy() - pi).sum()
-        _note(f"{name} tol={tol} slices={slices}: steps {rep['terms']}+{rep['refine_terms']} err {err:.2e} "
-              f"bound {rep['cert_bound']:.2e}")
+        _note(f"{name} tol={tol} slices={slices}: steps {rep['terms']}+{rep['refine_terms']} "
+              f"err {err:.2e} bound {rep['cert_bound']:.2e}")
         assert rep["status"] == "CPAA_OK" and rep["certified"] == 1, rep
         assert err <= tol and err <= rep["cert_bound"] * (1 + 1e-9) + 2e-13
         # the library's FP64 residual of x (row order, or the column-sliced
