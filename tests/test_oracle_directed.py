@@ -81,3 +81,26 @@ def test_mutation_dropped_dangling_mass_is_caught():
     except AssertionError:
         return
     raise AssertionError("mutation not caught")
+
+
+def test_directed_cycle_closed_form():
+    """Directed cycle 0 -> 1 -> ... -> n-1 -> 0 (every out-degree 1, nothing
+    dangling), p = e_0: the walk restarts at 0 with probability 1-c per step,
+    so vertex k (k steps ahead) has pi_k = (1-c) c^k / (1 - c^n)."""
+    n = 7
+    g = _graph(n, [(v, (v + 1) % n) for v in range(n)])
+    p = np.zeros(n)
+    p[0] = 1.0
+    want = (1 - C) * C ** np.arange(n) / (1 - C ** n)
+    assert np.abs(oracle.pagerank_directed_exact(g, p, C) - want).max() < 1e-15
+    x = oracle.power_method_directed(g, p, C, 400)
+    assert np.abs(x - want).max() < 1e-15
+
+
+def test_graph_without_edges_returns_p():
+    """Every vertex dangling: P' = p e^T, so (I - cP')pi = (1-c)p gives pi = p."""
+    n = 5
+    g = _graph(n, [])
+    p = np.array([0.1, 0.4, 0.2, 0.0, 0.3])
+    assert np.abs(oracle.pagerank_directed_exact(g, p, C) - p).max() < 1e-15
+    assert np.abs(oracle.power_method_directed(g, p, C, 3) - p).max() < 1e-15
