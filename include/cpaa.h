@@ -234,7 +234,8 @@ CPAA_API cpaa_status cpaa_solve(cpaa_plan_t plan, const double* p, double tol, c
  * when all its columns are certified (per-column in-loop certificate), and
  * each column gets its own FP64 residual and report.  On a directed plan the
  * columns are solved one after another by the single-vector power method
- * (X0 must be NULL).
+ * (X0 must be NULL); a column that fails validation stops the call with its
+ * error, and the columns before it are already written.
  * reps: [B] or NULL.  ldp, ldx0, ldx >= n.  Other rules as cpaa_solve. */
 CPAA_API cpaa_status cpaa_solve_batched(cpaa_plan_t plan, int32_t B, const double* P, int64_t ldp,
                                double tol, const double* X0, int64_t ldx0, double* X,
