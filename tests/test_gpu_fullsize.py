@@ -218,3 +218,33 @@ def test_directed_4m_sliced(torch_cuda):
           f"oracle bound {bound:.3e}; row order steps {rr['terms']}")
     assert rs["certified"] == 1 and bound <= TOL
     assert np.abs(xs - xr).sum() <= 2 * TOL
+
+
+@pytest.mark.timeout(600)
+def test_column_slices_at_the_maximum_size(torch_cuda):
+    """n = 8 (2^21 - 16) - 1, the largest plan the column-sliced path takes:
+    a slice holds 2,097,135 vertices, so the packed entries need 21 bits of
+    local column and work items hold 2^11 rows (the sliced pass's 11-row-bit
+    variant, which smaller graphs never reach).  A path through all vertices
+    plus n/4 random chords (42M entries); certified by the oracle's residual."""
+    from paper_2112_01743_amd import Plan
+    torch = torch_cuda
+    n = 8 * (2**21 - 16) - 1
+    rng = gg.philox(2112040)
+    u = np.arange(n - 1, dtype=np.int64)
+    a, b = rng.integers(0, n, n // 4), rng.integers(0, n, n // 4)
+    g = gg.csr_from_edges(n, np.concatenate([u, a]), np.concatenate([u + 1, b]))
+    _note(f"n={g.n} nnz={g.nnz}")
+    plan = Plan.from_graph(g, C, column_slices=8)
+    assert plan.info()["column_slices"] == 8 and plan.info()["reordered"] == 1
+    P = np.stack([np.full(n, 1.0 / n), gg.source_personalization(n, [n // 3])[0]])
+    X = []
+    for p in P:
+        x, rep = plan.solve(torch.as_tensor(p, device="cuda"), TOL)
+        _note(f"terms {rep['terms']}+{rep['refine_terms']} bound {rep['cert_bound']:.3e}")
+        assert rep["certified"] == 1
+        X.append(x.cpu().numpy())
+    del plan
+    bounds = _oracle_bound(g, (1 - C) * P, np.stack(X))
+    _note(f"oracle bounds {bounds}")
+    assert np.all(bounds <= TOL)
