@@ -248,3 +248,28 @@ def test_column_slices_at_the_maximum_size(torch_cuda):
     bounds = _oracle_bound(g, (1 - C) * P, np.stack(X))
     _note(f"oracle bounds {bounds}")
     assert np.all(bounds <= TOL)
+
+
+@pytest.mark.timeout(600)
+def test_directed_column_slices_at_the_maximum_size(torch_cuda):
+    """The directed power method at the column-sliced path's largest n (11
+    row bits, 21-bit local columns) through the sliced step and the sliced
+    FP64 residual; certified by the oracle's residual of (I - cP')x = (1-c)p."""
+    from paper_2112_01743_amd import Plan
+    torch = torch_cuda
+    n = 8 * (2**21 - 16) - 1
+    g = gg.directed_random(n, 2.5, 0.1, seed=2112041)
+    _note(f"directed n={g.n} nnz={g.nnz}")
+    plan = Plan.from_graph(g, C, directed=1)
+    assert plan.info()["column_slices"] == 8
+    p = np.full(n, 1.0 / n)
+    x, rep = plan.solve(torch.as_tensor(p, device="cuda"), TOL)
+    _note(f"steps {rep['terms']}+{rep['refine_terms']} method {rep['method']} "
+          f"bound {rep['cert_bound']:.3e}")
+    assert rep["certified"] == 1 and rep["method"] == 1
+    x = x.cpu().numpy()
+    del plan
+    P, d = oracle.transition_directed(g)
+    bound = np.abs((1 - C) * p - x + C * (P @ x + p * (d @ x))).sum() / (1 - C)
+    _note(f"oracle bound {bound:.3e}")
+    assert bound <= TOL
