@@ -19,6 +19,7 @@ namespace {
 struct Graph {
   int32_t n = 0;
   std::vector<int32_t> rp, ci;
+  std::vector<int32_t> gp;   // graph_ptr of a block-diagonal batch (empty: one graph)
 };
 
 // symmetric pattern from an edge list (loops dropped, duplicates merged)
@@ -89,6 +90,10 @@ void expect(const char* what, const Graph& g, const cpaa_opts& o, bool valid,
   csr.nnz = static_cast<int64_t>(g.ci.size());
   csr.row_ptr = g.rp.data();
   csr.col_idx = g.ci.data();
+  if (!g.gp.empty()) {
+    csr.num_graphs = static_cast<int32_t>(g.gp.size()) - 1;
+    csr.graph_ptr = g.gp.data();
+  }
   cpaa_plan_t p = nullptr;
   const cpaa_status s = cpaa_plan(&csr, 0.85, &o, &p);
   bool ok;
@@ -181,6 +186,21 @@ int main() {
   });
   expect("directed=2 asymmetric with RCM", asym, detect_rcm, false, CPAA_EINVAL);
   expect("directed=2 undirected with RCM", lattice(40), detect_rcm, true);
+  // block-diagonal batches: two 5-cycles
+  Graph batch = from_edges(10, {{0, 1}, {1, 2}, {2, 3}, {3, 4}, {4, 0},
+                                {5, 6}, {6, 7}, {7, 8}, {8, 9}, {9, 5}});
+  batch.gp = {0, 5, 10};
+  expect("batch of two cycles", batch, base, true);
+  expect("batch, directed=2 (symmetric: undirected)", batch, detect, true);
+  const cpaa_opts dir1 = with([](cpaa_opts& o) { o.directed = 1; });
+  expect("batch, directed=1", batch, dir1, false, CPAA_EINVAL);
+  Graph crossing = batch;
+  crossing.gp = {0, 4, 10};     // vertex 4's edges to 0 and 3 cross into the second block
+  expect("batch with a crossing edge", crossing, base, false, CPAA_EINVAL);
+  Graph dir_batch = batch;      // first block made asymmetric: row 0 drops vertex 1
+  dir_batch.ci.erase(dir_batch.ci.begin());
+  for (size_t u = 1; u < dir_batch.rp.size(); ++u) --dir_batch.rp[u];
+  expect("batch, directed=2 asymmetric block", dir_batch, detect, false, CPAA_EINVAL);
   std::printf("%s\n", failures ? "FAILED" : "ALL OK");
   return failures ? 1 : 0;
 }
