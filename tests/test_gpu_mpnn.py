@@ -53,7 +53,9 @@ def test_forward_matches_bf16_oracle(torch_cuda, layers):
         rel = np.max(np.abs(X[j] - ref) / ref)
         _note(f"layers={layers} src={s} L1={l1:.3e} maxrel={rel:.3e}")
         assert abs(X[j].sum() - 1.0) < 1e-12
-        assert l1 < 5e-3 and rel < 5e-2, (l1, rel)
+        # measured: L1 3e-12 to 3e-9; a bf16 rounding flipped by the FP32 / FP64
+        # accumulation difference moves single entries by up to ~2^-8 relative
+        assert l1 <= 1e-7 and rel <= 1e-2, (l1, rel)
 
 
 def test_gradients_match_oracle(torch_cuda):
@@ -74,7 +76,7 @@ def test_gradients_match_oracle(torch_cuda):
         diff = np.linalg.norm(grads[k] - r)
         _note(f"grad {k}: |diff| {diff:.3e} norm {np.linalg.norm(r):.3e}")
         # b_out's gradient is exactly zero (a softmax is shift invariant): absolute floor
-        assert diff <= 5e-2 * np.linalg.norm(r) + 1e-6, (k, diff)
+        assert diff <= 1e-4 * np.linalg.norm(r) + 1e-6, (k, diff)
 
 
 def test_training_steps_match_oracle_along_trajectory(torch_cuda):
@@ -88,8 +90,9 @@ def test_training_steps_match_oracle_along_trajectory(torch_cuda):
     plan = Plan.from_graph(g, C)
     model = Model(plan, gg.mpnn_init(2))
     src = gg.random_sources(g.n, 16, seed=3)
-    T, _ = plan.solve_batched(_dev(torch, gg.source_personalization(g.n, src)), 1e-9)
-    Tn = T.cpu().numpy()
+    # targets from the oracle's dense solve (an input of both sides)
+    Tn = oracle.pagerank_exact(g, gg.source_personalization(g.n, src).T, C).T
+    T = _dev(torch, Tn)
     for step in range(4):
         idx = np.arange(4) + 4 * step
         w, m, v, k = model.get_state()
