@@ -76,7 +76,11 @@ typedef struct {
   int32_t num_graphs;        /* 0 or 1: one graph.  > 1: block-diagonal batch of independent
                                 graphs, solved with cpaa_solve_graphs */
   const int32_t* graph_ptr;  /* [num_graphs+1] first vertex of each graph (num_graphs > 1) */
-  int32_t on_device;         /* 1: row_ptr/col_idx/graph_ptr are device pointers, 0: host */
+  int32_t on_device;         /* 1: row_ptr/col_idx/graph_ptr/values are device pointers, 0: host */
+  const double* values;      /* [nnz] or NULL.  Optional entries of P = A D^-1 (Sec. 2.1): the
+                                entry in column v must be 1/deg(v) (1/out-degree of v in a
+                                directed plan) to within 4 ulps, else CPAA_EINVAL.  Checked,
+                                then not used (only the pattern is read). */
 } cpaa_csr;
 
 typedef struct {
@@ -142,6 +146,30 @@ typedef struct {
                              has an empty row (a vertex without edges, dangling), else
                              undirected; the other pattern rules are checked as for 1.
                              cpaa_plan_info_get reports which. */
+  int32_t slice_shape;    /* column-sliced term of an undirected plan: launch shape of its gather
+                             pass, 0 auto (the default shape; with autotune the first cpaa_solve
+                             times every shape and keeps the fastest), 1-4 a fixed shape:
+                             1 = 8 wavefronts per workgroup and the slice's first 30,720
+                             vertices in LDS, 2 = 16 and 22,528, 3 = 16 and 16,384 (one
+                             workgroup per CU each), 4 = 8 and 8,192 (two per CU). */
+  int32_t fp64_recurrence; /* 1: debug mode, the Chebyshev (and power-method) recurrence in FP64
+                             instead of FP32 (the accumulation, residual and certificate are FP64
+                             always): results then follow the FP64 oracle's x_M to rounding.
+                             Row order only (no column slices; CPAA_EINVAL with column_slices = 8),
+                             one undirected graph; batched calls solve their columns one after
+                             another through the single-vector path. */
+  int32_t deterministic;  /* 1: bitwise-reproducible results: every sum is formed in a fixed order
+                             (partial row sums by a fixed-order scan, per-block partials of every
+                             reduction added in block order, no floating-point atomics), so two
+                             solves of the same input on the same device return identical bits.
+                             Uses the column-sliced term (forced on, any n); one undirected graph;
+                             batched calls solve their columns one after another. */
+  int32_t drop_isolated;  /* 1: accept vertices without edges (undirected plans).  P = A D^-1 has a
+                             zero column there (Sec. 2.1 needs d_v > 0), so (I - cP) x = (1-c) p
+                             gives x_v = (1-c) p_v, and no other vertex depends on v: the plan
+                             solves the graph without them (relabelled internally) and writes
+                             x_v = (1-c) p_v (scaled like the rest under normalize) for each
+                             dropped v.  0 (default): such a vertex is CPAA_EISOLATED. */
 } cpaa_opts;
 
 /* Per-solve report (one per right-hand side in batched calls, one per graph in
@@ -184,6 +212,10 @@ typedef struct {
   int32_t column_slices;    /* single-vector term: 1 (row order) or 8 (column-sliced) */
   double spectrum_lo;       /* a of the expansion interval [a, 1] (-1: the paper's) */
   int32_t directed;         /* 1 for a directed plan (opts.directed = 1, or 2 and detected) */
+  int32_t slice_shape;      /* launch shape of the column-sliced gather pass in use (1-4), 0 when
+                               the plan has no such pass */
+  int64_t slice_partials;   /* partial row sums per term of the column-sliced term: rows with an
+                               entry in a slice, summed over the 8 slices */
 } cpaa_plan_info;
 
 /* Fill *o with defaults.  Never fails. */

@@ -28,7 +28,7 @@ class cpaa_csr(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int64),
                 ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p),
                 ("num_graphs", ctypes.c_int32), ("graph_ptr", ctypes.c_void_p),
-                ("on_device", ctypes.c_int32)]
+                ("on_device", ctypes.c_int32), ("values", ctypes.c_void_p)]
 
 
 class cpaa_opts(ctypes.Structure):
@@ -38,7 +38,9 @@ class cpaa_opts(ctypes.Structure):
                 ("io_device", ctypes.c_int32), ("time_kernels", ctypes.c_int32),
                 ("xcd_remap", ctypes.c_int32), ("autotune", ctypes.c_int32),
                 ("column_slices", ctypes.c_int32), ("locality_order", ctypes.c_int32),
-                ("spectral_interval", ctypes.c_int32), ("directed", ctypes.c_int32)]
+                ("spectral_interval", ctypes.c_int32), ("directed", ctypes.c_int32),
+                ("slice_shape", ctypes.c_int32), ("fp64_recurrence", ctypes.c_int32),
+                ("deterministic", ctypes.c_int32), ("drop_isolated", ctypes.c_int32)]
 
 
 class cpaa_report(ctypes.Structure):
@@ -63,7 +65,8 @@ class cpaa_plan_info(ctypes.Structure):
                 ("k_cap_global", ctypes.c_int32), ("c", ctypes.c_double),
                 ("beta", ctypes.c_double), ("vol", ctypes.c_double),
                 ("column_slices", ctypes.c_int32), ("spectrum_lo", ctypes.c_double),
-                ("directed", ctypes.c_int32)]
+                ("directed", ctypes.c_int32), ("slice_shape", ctypes.c_int32),
+                ("slice_partials", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -248,7 +251,7 @@ class Plan:
     Keyword options are the fields of cpaa_opts.
     """
 
-    def __init__(self, row_ptr, col_idx, c: float = 0.85, graph_ptr=None, **opts):
+    def __init__(self, row_ptr, col_idx, c: float = 0.85, graph_ptr=None, values=None, **opts):
         self._keep = []
         on_device = 0
         if hasattr(row_ptr, "is_cuda"):
@@ -267,8 +270,17 @@ class Plan:
         n = int(len(row_ptr) - 1)
         nnz = int(len(col_idx))
         ng = 0 if graph_ptr is None else int(len(graph_ptr) - 1)
+        vptr = None
+        if values is not None:
+            if hasattr(values, "data_ptr"):
+                self._keep.append(values)
+                vptr = values.data_ptr()
+            else:
+                va = np.ascontiguousarray(values, dtype=np.float64)
+                self._keep.append(va)
+                vptr = va.ctypes.data
         csr = cpaa_csr(n=n, nnz=nnz, row_ptr=ptr(row_ptr), col_idx=ptr(col_idx), num_graphs=ng,
-                       graph_ptr=ptr(graph_ptr), on_device=on_device)
+                       graph_ptr=ptr(graph_ptr), on_device=on_device, values=vptr)
         o = cpaa_default_opts()
         for k, v in opts.items():
             if not hasattr(o, k):

@@ -7,6 +7,7 @@
 // Chebyshev coefficients c_k = 2 beta^k / sqrt(1-c^2) (Prop. 1) and uploads
 // the pattern to the device.
 #include <algorithm>
+#include <cfloat>
 #include <thread>
 #include <cmath>
 #include <cstring>
@@ -374,7 +375,7 @@ void slice_relabel(int32_t n, const int32_t* rp, const int32_t* ci, std::vector<
 // transposed per-wavefront layout described below; nnz0 is the physical start
 // and nnz1 - nnz0 the number of entries (the layout pads each wavefront's
 // share to a multiple of 64 with kSliceNone).
-void build_sliced(int32_t n, const std::vector<int32_t>& rp2, const std::vector<int32_t>& ci2,
+bool build_sliced(int32_t n, const std::vector<int32_t>& rp2, const std::vector<int32_t>& ci2,
                   const int slice_off[kSlices + 1], int row_bits, std::vector<uint32_t>& entries,
                   std::vector<WorkItem>& items, std::vector<int>& split_nchunks,
                   int item_off[kSlices + 1]) {
@@ -435,6 +436,10 @@ void build_sliced(int32_t n, const std::vector<int32_t>& rp2, const std::vector<
       I.push_back({r0, r, e0, e0 + L});   // nnz1 - nnz0 = logical length
     }
   });
+  // int offsets below: the padded total must fit (every local offset is smaller)
+  int64_t etot = 0;
+  for (int sl = 0; sl < kSlices; ++sl) etot += static_cast<int64_t>(ent[sl].size());
+  if (etot > kSliceEntryLimit) return false;
   entries.clear();
   items.clear();
   split_nchunks.clear();
@@ -452,6 +457,222 @@ void build_sliced(int32_t n, const std::vector<int32_t>& rp2, const std::vector<
     split_nchunks.insert(split_nchunks.end(), nch[sl].begin(), nch[sl].end());
     item_off[sl + 1] = static_cast<int>(items.size());
   }
+  return true;
+}
+
+// Host image of a HubMap (internal.h).
+struct HubHost {
+  std::vector<uint32_t> entries;
+  std::vector<HubItem> items;
+  int item_off[kSlices + 1] = {};
+  int pofs[kSlices + 1] = {};
+  std::vector<uint8_t> mask;
+  std::vector<int32_t> base;
+  std::vector<int> chunk_long, long_first, long_nch, long_out;
+};
+
+// Packed entries, wave items, compact partial indices and long-row chunks of
+// the hub-sliced term (layout in internal.h), from the relabelled CSR
+// (columns sorted).  Returns false when the entry array (with its run
+// padding) or the partial array would outgrow int offsets; h is then unusable.
+bool build_hub_sliced(int32_t n, const std::vector<int32_t>& rp2, const std::vector<int32_t>& ci2,
+                      const int slice_off[kSlices + 1], HubHost& h) {
+  struct LocalItem {
+    int64_t j0, e0;
+    int len, rows;
+  };
+  struct SliceOut {
+    std::vector<uint32_t> E;
+    std::vector<LocalItem> I;
+    std::vector<uint8_t> present;
+    int64_t P = 0;
+    std::vector<int64_t> lj;      // long rows: compact row
+    std::vector<int> lfirst, lnch;
+  };
+  std::vector<SliceOut> so(kSlices);
+  const int64_t nblk = (static_cast<int64_t>(n) + 63) / 64;
+  h.base.assign(static_cast<size_t>(nblk) * kSlices, 0);
+  parallel_for(kSlices, [&](int64_t sl) {
+    SliceOut& o = so[sl];
+    const int32_t lo = slice_off[sl], hi = slice_off[sl + 1];
+    o.present.assign(n, 0);
+    std::vector<uint32_t> logical;
+    int cur_rows = 0, chunks = 0;
+    int64_t cur_j0 = 0, j = 0;
+    auto flush = [&]() {
+      if (cur_rows == 0) return;
+      const int L = static_cast<int>(logical.size());
+      const int RL = (L + 63) / 64;
+      const size_t pb = o.E.size();
+      o.E.resize(pb + static_cast<size_t>(64) * RL, kSliceNone);
+      for (int q = 0; q < L; ++q) o.E[pb + (q % RL) * 64 + q / RL] = logical[q];
+      o.I.push_back({cur_j0, static_cast<int64_t>(pb), L, cur_rows});
+      logical.clear();
+      cur_rows = 0;
+    };
+    for (int32_t u = 0; u < n; ++u) {
+      if ((u & 63) == 0) h.base[static_cast<size_t>(u >> 6) * kSlices + sl] = static_cast<int32_t>(j);
+      const int32_t* a = ci2.data() + rp2[u];
+      const int32_t* b = ci2.data() + rp2[u + 1];
+      const int32_t* x = std::lower_bound(a, b, lo);
+      const int32_t* y = std::lower_bound(x, b, hi);
+      const int len = static_cast<int>(y - x);
+      if (len == 0) continue;
+      o.present[u] = 1;
+      if (len > kHubItemCap) {
+        flush();
+        const int nch = (len + kHubItemCap - 1) / kHubItemCap;
+        o.lj.push_back(j);
+        o.lfirst.push_back(chunks);
+        o.lnch.push_back(nch);
+        for (int c = 0; c < nch; ++c) {
+          const int cl = std::min(kHubItemCap, len - c * kHubItemCap);
+          const size_t pb = o.E.size();
+          for (int t = 0; t < cl; ++t)
+            o.E.push_back(static_cast<uint32_t>(x[c * kHubItemCap + t] - lo));
+          o.I.push_back({j, static_cast<int64_t>(pb), cl, -(chunks + 1)});
+          ++chunks;
+        }
+        ++j;
+        continue;
+      }
+      if (cur_rows > 0 &&
+          (static_cast<int>(logical.size()) + len > kHubItemCap || cur_rows == kHubRows))
+        flush();
+      if (cur_rows == 0) cur_j0 = j;
+      for (const int32_t* q = x; q < y; ++q)
+        logical.push_back((static_cast<uint32_t>(*q - lo) << kHubRowBits) |
+                          static_cast<uint32_t>(cur_rows));
+      ++cur_rows;
+      ++j;
+    }
+    flush();
+    o.P = j;
+  });
+  int64_t etot = 0, ptot = 0, itot = 0;
+  for (const SliceOut& o : so) {
+    etot += static_cast<int64_t>(o.E.size());
+    ptot += o.P;
+    itot += static_cast<int64_t>(o.I.size());
+  }
+  if (etot > kSliceEntryLimit || ptot > INT32_MAX || itot > INT32_MAX) return false;
+  h.entries.clear();
+  h.entries.reserve(static_cast<size_t>(etot));
+  h.items.clear();
+  h.items.reserve(static_cast<size_t>(itot));
+  int64_t ebase = 0, pbase = 0;
+  int cbase = 0, lbase = 0;
+  for (int sl = 0; sl < kSlices; ++sl) {
+    const SliceOut& o = so[sl];
+    h.item_off[sl] = static_cast<int>(h.items.size());
+    h.pofs[sl] = static_cast<int>(pbase);
+    for (const LocalItem& it : o.I)
+      h.items.push_back({static_cast<int>(it.j0), static_cast<int>(it.e0 + ebase), it.len,
+                         it.rows < 0 ? it.rows - cbase : it.rows});
+    for (size_t q = 0; q < o.lj.size(); ++q) {
+      h.long_first.push_back(o.lfirst[q] + cbase);
+      h.long_nch.push_back(o.lnch[q]);
+      h.long_out.push_back(static_cast<int>(pbase + o.lj[q]));
+      for (int c = 0; c < o.lnch[q]; ++c) h.chunk_long.push_back(lbase + static_cast<int>(q));
+    }
+    cbase += o.lnch.empty() ? 0 : o.lfirst.back() + o.lnch.back();
+    lbase += static_cast<int>(o.lj.size());
+    h.entries.insert(h.entries.end(), o.E.begin(), o.E.end());
+    ebase += static_cast<int64_t>(o.E.size());
+    pbase += o.P;
+  }
+  h.item_off[kSlices] = static_cast<int>(h.items.size());
+  h.pofs[kSlices] = static_cast<int>(pbase);
+  h.mask.assign(n, 0);
+  for (int sl = 0; sl < kSlices; ++sl)
+    for (int32_t u = 0; u < n; ++u) h.mask[u] |= static_cast<uint8_t>(so[sl].present[u] << sl);
+  return true;
+}
+
+// Structural check of a hub map against what the kernels index: every item's
+// run layout inside the entry array, packed rows below the item's row count
+// and local columns inside the slice, partial indices inside the slice's
+// range, the block bases consistent with the masks.  Runs once per plan on
+// the host (linear in the entries).
+bool check_hub_map(int32_t n, const int slice_off[kSlices + 1], const HubHost& h,
+                   std::string& why) {
+  const size_t ne = h.entries.size();
+  for (int sl = 0; sl < kSlices; ++sl) {
+    const uint32_t nsl = static_cast<uint32_t>(slice_off[sl + 1] - slice_off[sl]);
+    const int64_t P = static_cast<int64_t>(h.pofs[sl + 1]) - h.pofs[sl];
+    for (int k = h.item_off[sl]; k < h.item_off[sl + 1]; ++k) {
+      const HubItem& it = h.items[k];
+      if (it.len <= 0 || it.len > kHubItemCap || it.e0 < 0 || it.j0 < 0) {
+        why = "item bounds";
+        return false;
+      }
+      if (it.rows < 0) {
+        const int slot = -(it.rows + 1);
+        if (slot >= static_cast<int>(h.chunk_long.size()) ||
+            static_cast<size_t>(it.e0) + it.len > ne || it.j0 >= P) {
+          why = "chunk item";
+          return false;
+        }
+        for (int t = 0; t < it.len; ++t)
+          if (h.entries[it.e0 + t] >= nsl) {
+            why = "chunk column";
+            return false;
+          }
+        continue;
+      }
+      const int RL = (it.len + 63) / 64;
+      if (it.rows > kHubRows || it.rows > it.len || it.j0 + static_cast<int64_t>(it.rows) > P ||
+          static_cast<size_t>(it.e0) + static_cast<size_t>(64) * RL > ne) {
+        why = "item rows or run layout";
+        return false;
+      }
+      // logical entry q is element q % RL of lane q / RL; rows ascend over q
+      // (the kernel's cross-lane scan relies on it) and every row appears
+      int prev = 0;
+      for (int q = 0; q < it.len; ++q) {
+        const uint32_t e = h.entries[it.e0 + (q % RL) * 64 + q / RL];
+        const int r = static_cast<int>(e & ((1u << kHubRowBits) - 1u));
+        if (e == kSliceNone || (e >> kHubRowBits) >= nsl || r >= it.rows || r < prev ||
+            r > prev + 1 || (q == 0 && r != 0)) {
+          why = "packed entry";
+          return false;
+        }
+        prev = r;
+      }
+      if (prev != it.rows - 1) {
+        why = "rows of an item";
+        return false;
+      }
+      for (int l = 0; l < 64; ++l)
+        for (int i = std::max(0, std::min(RL, it.len - l * RL)); i < RL; ++i)
+          if (h.entries[it.e0 + i * 64 + l] != kSliceNone) {
+            why = "padding";
+            return false;
+          }
+    }
+  }
+  for (size_t q = 0; q < h.long_out.size(); ++q)
+    if (h.long_out[q] < 0 || h.long_out[q] >= h.pofs[kSlices] || h.long_nch[q] < 2 ||
+        h.long_first[q] + h.long_nch[q] > static_cast<int>(h.chunk_long.size())) {
+      why = "long row";
+      return false;
+    }
+  std::vector<int64_t> cnt(kSlices, 0);
+  for (int32_t u = 0; u < n; ++u) {
+    for (int sl = 0; sl < kSlices; ++sl) {
+      if ((u & 63) == 0 && h.base[static_cast<size_t>(u >> 6) * kSlices + sl] != cnt[sl]) {
+        why = "block base";
+        return false;
+      }
+      cnt[sl] += (h.mask[u] >> sl) & 1;
+    }
+  }
+  for (int sl = 0; sl < kSlices; ++sl)
+    if (cnt[sl] != static_cast<int64_t>(h.pofs[sl + 1]) - h.pofs[sl]) {
+      why = "present rows";
+      return false;
+    }
+  return true;
 }
 
 }  // namespace
@@ -491,6 +712,10 @@ void cpaa_default_opts(cpaa_opts* o) {
   o->locality_order = 0;
   o->spectral_interval = 0;
   o->directed = 0;
+  o->slice_shape = 0;
+  o->fp64_recurrence = 0;
+  o->deterministic = 0;
+  o->drop_isolated = 0;
 }
 
 void cpaa_plan_destroy(cpaa_plan_t pl) {
@@ -503,10 +728,19 @@ void cpaa_plan_destroy(cpaa_plan_t pl) {
     if (m.d_items) (void)hipFree(m.d_items);
     if (m.d_split_nchunks) (void)hipFree(m.d_split_nchunks);
   }
-  if (pl->d_perm) {
-    void* sp[] = {pl->d_rp_w1, pl->d_ci_w1, pl->d_perm, pl->slc.d_entries, pl->slc.d_items,
+  if (pl->reordered) {
+    void* sp[] = {pl->d_rp_w1, pl->d_ci_w1, pl->slc.d_entries, pl->slc.d_items,
                   pl->slc.d_split_nchunks};
     for (void* p : sp)
+      if (p) (void)hipFree(p);
+  }
+  if (pl->d_perm) (void)hipFree(pl->d_perm);
+  if (pl->d_dropped) (void)hipFree(pl->d_dropped);
+  {
+    HubMap& hm = pl->hub;
+    void* hp[] = {hm.d_entries, hm.d_items, hm.d_mask, hm.d_base, hm.d_chunk_long,
+                  hm.d_long_first, hm.d_long_nch, hm.d_long_out};
+    for (void* p : hp)
       if (p) (void)hipFree(p);
   }
   void* ptrs[] = {pl->d_row_ptr, pl->d_col_idx, pl->d_dout, pl->d_titems, pl->d_tsplit_nchunks,
@@ -557,6 +791,38 @@ cpaa_status cpaa_plan(const cpaa_csr* g, double c, const cpaa_opts* opts, cpaa_p
     set_error("column slices need one graph with n < 8 (2^21 - 16)");
     return CPAA_EINVAL;
   }
+  if (o.slice_shape < 0 || o.slice_shape > kHubConfigs + 1) {
+    set_error("slice_shape must be 0 (auto) or 1-" + std::to_string(kHubConfigs + 1));
+    return CPAA_EINVAL;
+  }
+  if ((o.fp64_recurrence != 0 && o.fp64_recurrence != 1) ||
+      (o.deterministic != 0 && o.deterministic != 1) ||
+      (o.drop_isolated != 0 && o.drop_isolated != 1)) {
+    set_error("fp64_recurrence, deterministic and drop_isolated must be 0 or 1");
+    return CPAA_EINVAL;
+  }
+  if (o.drop_isolated == 1 && (g->num_graphs > 1 || o.directed != 0)) {
+    set_error("drop_isolated needs one undirected graph (directed = 0)");
+    return CPAA_EINVAL;
+  }
+  if (o.fp64_recurrence == 1 && o.column_slices == kSlices) {
+    set_error("fp64_recurrence runs in row order (column_slices must be 0 or 1)");
+    return CPAA_EINVAL;
+  }
+  if (o.fp64_recurrence == 1 && o.deterministic == 1) {
+    set_error("fp64_recurrence and deterministic cannot be combined");
+    return CPAA_EINVAL;
+  }
+  if (o.deterministic == 1 && (o.column_slices == 1 || o.slice_shape == kHubConfigs + 1)) {
+    set_error("deterministic needs the column-sliced term with compact partials "
+              "(column_slices 0 or 8, slice_shape 0-" + std::to_string(kHubConfigs) + ")");
+    return CPAA_EINVAL;
+  }
+  if ((o.fp64_recurrence == 1 || o.deterministic == 1) &&
+      (g->num_graphs > 1 || o.directed == 1)) {
+    set_error("fp64_recurrence and deterministic need one undirected graph");
+    return CPAA_EINVAL;
+  }
   if (o.spectral_interval != 0 && o.spectral_interval != 1) {
     set_error("spectral_interval must be 0 or 1");
     return CPAA_EINVAL;
@@ -583,7 +849,7 @@ cpaa_status cpaa_plan(const cpaa_csr* g, double c, const cpaa_opts* opts, cpaa_p
     return CPAA_EINVAL;
   }
 
-  const int32_t n = g->n;
+  int32_t n = g->n;
   const int64_t nnz = g->nnz;
   std::vector<int32_t> h_rp, h_ci, h_gp;
   const int32_t* rp = g->row_ptr;
@@ -617,13 +883,14 @@ cpaa_status cpaa_plan(const cpaa_csr* g, double c, const cpaa_opts* opts, cpaa_p
     if (s != CPAA_OK) return s;
     directed = validate_pattern(n, nnz, rp, ci, true, false) != CPAA_OK;
     set_error("");
-    if (directed && (g->num_graphs > 1 || o.locality_order == 2 || o.spectral_interval == 1)) {
+    if (directed && (g->num_graphs > 1 || o.locality_order == 2 || o.spectral_interval == 1 ||
+                     o.fp64_recurrence == 1 || o.deterministic == 1)) {
       set_error("the pattern is directed (not symmetric, or with an empty row); directed plans "
-                "need one graph and no RCM or spectral interval");
+                "need one graph and no RCM, spectral interval, fp64_recurrence or deterministic");
       return CPAA_EINVAL;
     }
   } else if (o.validate) {
-    cpaa_status s = validate_pattern(n, nnz, rp, ci, !directed, directed);
+    cpaa_status s = validate_pattern(n, nnz, rp, ci, !directed, directed || o.drop_isolated == 1);
     if (s != CPAA_OK) return s;
   } else if (rp[0] != 0 || rp[n] != nnz) {
     set_error("row_ptr[0] must be 0 and row_ptr[n] must equal nnz");
@@ -649,6 +916,61 @@ cpaa_status cpaa_plan(const cpaa_csr* g, double c, const cpaa_opts* opts, cpaa_p
       }
     }
   }
+  // Optional per-entry values: Alg. 1 only reads N(u) and the degrees, so a
+  // caller's values must be the entries of P = A D^{-1} (Sec. 2.1): the entry
+  // of column v is 1/d_v (1/out-degree of v in a directed plan).  They are
+  // checked to a few ulps and then not used.
+  if (g->values != nullptr && nnz > 0) {
+    std::vector<double> h_val;
+    const double* val = g->values;
+    if (g->on_device) {
+      h_val.resize(static_cast<size_t>(nnz));
+      CPAA_HIP(hipMemcpy(h_val.data(), g->values, nnz * sizeof(double), hipMemcpyDeviceToHost));
+      val = h_val.data();
+    }
+    std::vector<int32_t> deg_col(n, 0);
+    if (directed) {
+      for (int64_t j = 0; j < nnz; ++j) ++deg_col[ci[j]];
+    } else {
+      for (int32_t v = 0; v < n; ++v) deg_col[v] = rp[v + 1] - rp[v];
+    }
+    for (int64_t j = 0; j < nnz; ++j) {
+      const double d = static_cast<double>(deg_col[ci[j]]);
+      if (!(std::fabs(val[j] * d - 1.0) <= 4.0 * DBL_EPSILON)) {
+        set_error("values[" + std::to_string(static_cast<long long>(j)) +
+                  "] is not 1/deg of its column (the entries of P = A D^-1)");
+        return CPAA_EINVAL;
+      }
+    }
+  }
+
+  // drop_isolated: the graph without its edgeless vertices, relabelled in order
+  // (P has a zero column there and no other vertex depends on them, Sec. 2.1);
+  // the solves write x_v = (1-c) p_v for them.
+  const int32_t n_caller = n;
+  std::vector<int32_t> keep, dropped, red_rp, red_ci;
+  if (o.drop_isolated == 1) {
+    for (int32_t v = 0; v < n; ++v) (rp[v + 1] > rp[v] ? keep : dropped).push_back(v);
+    if (keep.empty()) {
+      set_error("drop_isolated: no vertex has an edge");
+      return CPAA_EISOLATED;
+    }
+    if (!dropped.empty()) {
+      std::vector<int32_t> nid(n, -1);
+      for (size_t i = 0; i < keep.size(); ++i) nid[keep[i]] = static_cast<int32_t>(i);
+      red_rp.assign(keep.size() + 1, 0);
+      red_ci.resize(static_cast<size_t>(nnz));
+      for (size_t i = 0; i < keep.size(); ++i) {
+        const int32_t v = keep[i];
+        int32_t w = red_rp[i];
+        for (int32_t j = rp[v]; j < rp[v + 1]; ++j) red_ci[w++] = nid[ci[j]];   // order kept
+        red_rp[i + 1] = w;
+      }
+      rp = red_rp.data();
+      ci = red_ci.data();
+      n = static_cast<int32_t>(keep.size());
+    }
+  }
 
   cpaa_plan_s* pl = new (std::nothrow) cpaa_plan_s();
   if (!pl) {
@@ -657,6 +979,8 @@ cpaa_status cpaa_plan(const cpaa_csr* g, double c, const cpaa_opts* opts, cpaa_p
   }
   pl->opts = o;
   pl->n = n;
+  pl->n_caller = n_caller;
+  pl->n_drop = static_cast<int32_t>(dropped.size());
   pl->nnz = nnz;
   pl->c = c;
   pl->s = std::sqrt(1.0 - c * c);
@@ -719,10 +1043,18 @@ cpaa_status cpaa_plan(const cpaa_csr* g, double c, const cpaa_opts* opts, cpaa_p
   // directed plan has no RCM alternative, so there a scattered pattern
   // (entries spanning more than 2^14 labels on average) also qualifies.
   const bool big = n >= 3 * (1 << 18) && n < kSliceMaxN;
-  pl->sliced = o.column_slices == kSlices ||
-               (o.column_slices == 0 && num_graphs == 1 && big &&
-                (static_cast<double>(maxd) >= 16.0 * vol / n ||
-                 (pl->directed && mean_span(n, rp, ci) > 16384.0)));
+  pl->fp64 = o.fp64_recurrence == 1;
+  pl->deterministic = o.deterministic == 1;
+  if (pl->deterministic && n >= kSliceMaxN) {
+    cpaa_plan_destroy(pl);
+    set_error("deterministic needs the column-sliced term: n < 8 (2^21 - 16)");
+    return CPAA_EINVAL;
+  }
+  pl->sliced = !pl->fp64 &&
+               (o.column_slices == kSlices || pl->deterministic ||
+                (o.column_slices == 0 && num_graphs == 1 && big &&
+                 (static_cast<double>(maxd) >= 16.0 * vol / n ||
+                  (pl->directed && mean_span(n, rp, ci) > 16384.0))));
   std::vector<int32_t> rp2, ci2, perm;
   if (pl->sliced) {
     slice_relabel(n, rp, ci, rp2, ci2, perm, pl->slc.slice_off);
@@ -763,19 +1095,16 @@ cpaa_status cpaa_plan(const cpaa_csr* g, double c, const cpaa_opts* opts, cpaa_p
   pl->tile_w = o.tile_w ? o.tile_w : 64;
 
   cpaa_status s = CPAA_OK;
-  if (s == CPAA_OK) s = dev_upload(&pl->d_row_ptr, rp, n + 1);
-  if (s == CPAA_OK && pl->directed) {
-    // out-degree of v = rows that list v, in the single-vector labelling
-    const int32_t* ci1 = pl->reordered ? ci2.data() : ci;
-    std::vector<int32_t> dout(n, 0);
-    for (int64_t j = 0; j < nnz; ++j) ++dout[ci1[j]];
-    s = dev_upload(&pl->d_dout, dout.data(), dout.size());
-  }
-  if (s == CPAA_OK) s = dev_upload(&pl->d_col_idx, ci, static_cast<size_t>(nnz));
-  if (s == CPAA_OK && pl->sliced) {
-    std::vector<uint32_t> entries;
-    std::vector<WorkItem> sitems;
-    std::vector<int> snch;
+  // Host side of the column-sliced layout first (before any device work):
+  // packed entry offsets are int, so a pattern whose packed entries (with
+  // their run padding) pass kSliceEntryLimit is refused by the sliced layout
+  // and keeps row order (the degree-rank labels stay), unless column slices
+  // were asked for explicitly.
+  HubHost hh;
+  std::vector<uint32_t> entries;
+  std::vector<WorkItem> sitems;
+  std::vector<int> snch;
+  if (pl->sliced) {
     int max_slice = 0;
     for (int sl = 0; sl < kSlices; ++sl)
       max_slice = std::max(max_slice, pl->slc.slice_off[sl + 1] - pl->slc.slice_off[sl]);
@@ -785,25 +1114,96 @@ cpaa_status cpaa_plan(const cpaa_csr* g, double c, const cpaa_opts* opts, cpaa_p
       set_error("column slice too large for the packed entries");
       s = CPAA_EINVAL;
     }
-    if (s == CPAA_OK)
-      build_sliced(n, rp2, ci2, pl->slc.slice_off, pl->slc.row_bits, entries, sitems, snch,
-                   pl->slc.item_off);
+    bool fits = true;
+    // the per-item layout (dense partials) serves directed plans and, unless a
+    // deterministic plan needs the compact one, the automatic choice
+    const int shape = o.slice_shape > 0 ? o.slice_shape
+                                        : (pl->deterministic ? kHubDeterministicShape
+                                                             : kSliceShapeAuto);
+    const bool per_item_layout = pl->directed || shape == kHubConfigs + 1;
+    if (s == CPAA_OK && !per_item_layout) {
+      fits = build_hub_sliced(n, rp2, ci2, pl->slc.slice_off, hh);
+      std::string why;
+      if (fits && !check_hub_map(n, pl->slc.slice_off, hh, why)) {
+        set_error("internal error: hub-sliced map check failed (" + why + ")");
+        s = CPAA_EINVAL;
+      }
+    } else if (s == CPAA_OK) {
+      fits = build_sliced(n, rp2, ci2, pl->slc.slice_off, pl->slc.row_bits, entries, sitems, snch,
+                          pl->slc.item_off);
+      for (int sl = 0; sl < kSlices; ++sl)
+        pl->slc.max_items =
+            std::max(pl->slc.max_items, pl->slc.item_off[sl + 1] - pl->slc.item_off[sl]);
+      pl->slc.n_split_rows = static_cast<int>(snch.size());
+    }
+    if (s == CPAA_OK && !fits) {
+      if (o.column_slices == kSlices) {
+        set_error("column slices: the packed entries exceed int32 offsets (" +
+                  std::to_string(static_cast<long long>(nnz)) + " stored entries)");
+        s = CPAA_EINVAL;
+      } else {
+        pl->sliced = false;
+        pl->slc = SlicedMap();
+      }
+    }
+  }
+  if (s == CPAA_OK) s = dev_upload(&pl->d_row_ptr, rp, n + 1);
+  if (s == CPAA_OK && pl->directed) {
+    // out-degree of v = rows that list v, in the single-vector labelling
+    const int32_t* ci1 = pl->reordered ? ci2.data() : ci;
+    std::vector<int32_t> dout(n, 0);
+    for (int64_t j = 0; j < nnz; ++j) ++dout[ci1[j]];
+    s = dev_upload(&pl->d_dout, dout.data(), dout.size());
+  }
+  if (s == CPAA_OK) s = dev_upload(&pl->d_col_idx, ci, static_cast<size_t>(nnz));
+  if (s == CPAA_OK && pl->sliced && !hh.items.empty()) {
+    HubMap& hm = pl->hub;
+    for (int sl = 0; sl <= kSlices; ++sl) {
+      hm.item_off[sl] = hh.item_off[sl];
+      hm.pofs[sl] = hh.pofs[sl];
+    }
+    hm.n_long = static_cast<int>(hh.long_out.size());
+    hm.n_chunks = static_cast<int>(hh.chunk_long.size());
+    int max_items = 0;
     for (int sl = 0; sl < kSlices; ++sl)
-      pl->slc.max_items =
-          std::max(pl->slc.max_items, pl->slc.item_off[sl + 1] - pl->slc.item_off[sl]);
-    pl->slc.n_split_rows = static_cast<int>(snch.size());
-    if (s == CPAA_OK) s = dev_upload(&pl->slc.d_entries, entries.data(), entries.size());
+      max_items = std::max(max_items, hh.item_off[sl + 1] - hh.item_off[sl]);
+    for (int k = 0; k < kHubConfigs; ++k)
+      hm.groups[k] = std::max(1, hub_groups_per_slice(k, max_items));
+    s = dev_upload(&hm.d_entries, hh.entries.data(), hh.entries.size());
+    if (s == CPAA_OK) s = dev_upload(&hm.d_items, hh.items.data(), hh.items.size());
+    if (s == CPAA_OK) s = dev_upload(&hm.d_mask, hh.mask.data(), hh.mask.size());
+    if (s == CPAA_OK) s = dev_upload(&hm.d_base, hh.base.data(), hh.base.size());
+    if (s == CPAA_OK) s = dev_upload(&hm.d_chunk_long, hh.chunk_long.data(), hh.chunk_long.size());
+    if (s == CPAA_OK) s = dev_upload(&hm.d_long_first, hh.long_first.data(), hh.long_first.size());
+    if (s == CPAA_OK) s = dev_upload(&hm.d_long_nch, hh.long_nch.data(), hh.long_nch.size());
+    if (s == CPAA_OK) s = dev_upload(&hm.d_long_out, hh.long_out.data(), hh.long_out.size());
+    hm.cfg = (o.slice_shape > 0 ? o.slice_shape
+                                : (pl->deterministic ? kHubDeterministicShape : kSliceShapeAuto)) - 1;
+    hm.built = s == CPAA_OK;
+    std::vector<uint32_t>().swap(hh.entries);
+  } else if (s == CPAA_OK && pl->sliced) {
+    s = dev_upload(&pl->slc.d_entries, entries.data(), entries.size());
     if (s == CPAA_OK) s = dev_upload(&pl->slc.d_items, sitems.data(), sitems.size());
     if (s == CPAA_OK) s = dev_upload(&pl->slc.d_split_nchunks, snch.data(), snch.size());
+  }
+  if (pl->n_drop > 0) {
+    // single-vector labels -> the caller's: through the relabelling, then the
+    // vertices that were kept
+    if (pl->reordered)
+      for (int32_t& v : perm) v = keep[v];
+    else
+      perm = keep;
+    if (s == CPAA_OK) s = dev_upload(&pl->d_dropped, dropped.data(), dropped.size());
   }
   if (pl->reordered) {
     if (s == CPAA_OK) s = dev_upload(&pl->d_rp_w1, rp2.data(), rp2.size());
     if (s == CPAA_OK) s = dev_upload(&pl->d_ci_w1, ci2.data(), ci2.size());
-    if (s == CPAA_OK) s = dev_upload(&pl->d_perm, perm.data(), perm.size());
   } else {
     pl->d_rp_w1 = pl->d_row_ptr;
     pl->d_ci_w1 = pl->d_col_idx;
   }
+  if (pl->reordered || pl->n_drop > 0)
+    if (s == CPAA_OK) s = dev_upload(&pl->d_perm, perm.data(), perm.size());
   pl->maps.resize(npts.size());
   for (size_t i = 0; i < npts.size() && s == CPAA_OK; ++i) {
     WorkMap& m = pl->maps[i];
@@ -872,7 +1272,7 @@ cpaa_status cpaa_plan_info_get(cpaa_plan_t pl, cpaa_plan_info* info) {
     return CPAA_EINVAL;
   }
   std::memset(info, 0, sizeof(*info));
-  info->n = pl->n;
+  info->n = pl->n_caller;
   info->nnz = pl->nnz;
   info->num_graphs = pl->num_graphs;
   info->reordered = pl->reordered;
@@ -888,6 +1288,8 @@ cpaa_status cpaa_plan_info_get(cpaa_plan_t pl, cpaa_plan_info* info) {
   info->column_slices = pl->sliced ? kSlices : 1;
   info->spectrum_lo = pl->lam_lo;
   info->directed = pl->directed ? 1 : 0;
+  info->slice_shape = pl->hub.built ? pl->hub.cfg + 1 : 0;
+  info->slice_partials = pl->hub.built ? pl->hub.pofs[kSlices] : 0;
   return CPAA_OK;
 }
 

@@ -75,6 +75,40 @@ __device__ __forceinline__ void atomics_done() {
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
+// Deterministic sum of per-block values over a grid (deterministic plans):
+// thread 0 of every block publishes its Q values v (the block's own sums) to
+// part[q * nblocks + block]; the last block to count itself in adds them in
+// block order (a fixed strided split over its threads, then a fixed tree) and
+// returns true, with the grid totals in v of its thread 0.  Every thread of
+// every block of the grid calls it once; *counter is zero on entry and is left
+// zero.  The values travel through device-scope atomic stores and loads after
+// the wave's stores have completed, as in the split-row protocol.
+template <int Q>
+__device__ __forceinline__ bool ordered_block_sum(double (&v)[Q], int block, int nblocks,
+                                                  double* part, int* counter) {
+  __shared__ int last;
+  if (threadIdx.x == 0) {
+    for (int q = 0; q < Q; ++q)
+      __hip_atomic_store(&part[static_cast<size_t>(q) * nblocks + block], v[q], __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    atomics_done();
+    last = atomicAdd(counter, 1) == nblocks - 1 ? 1 : 0;
+  }
+  __syncthreads();
+  if (!last) return false;
+  atomics_done();
+  for (int q = 0; q < Q; ++q) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
+      s += __hip_atomic_load(&part[static_cast<size_t>(q) * nblocks + b], __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+    s = block_sum256(s);
+    if (threadIdx.x == 0) v[q] = s;
+  }
+  if (threadIdx.x == 0) __hip_atomic_store(counter, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return true;
+}
+
 __device__ __forceinline__ int prev_pow2(int v) {
   return v <= 1 ? 1 : (1 << (31 - __clz(v)));
 }

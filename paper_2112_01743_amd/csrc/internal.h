@@ -81,6 +81,81 @@ struct SlicedMap {
   int* d_split_nchunks = nullptr;    // [n_split_rows]
 };
 
+// Hub-sliced single-vector term (undirected plans with column slices; the
+// layout above stays in use for directed plans).  Per column slice s only the
+// rows with at least one entry in s ("present" rows) get a partial sum, stored
+// compactly: row u's partial for slice s sits at part[pofs[s] + j_s(u)], j_s(u)
+// = number of present rows of s before u.  mask[u] holds one bit per slice,
+// and base[b][s] = j_s of the first present row at or after row 64 b, so the
+// combine pass finds every partial of a 64-row block from a ballot.  The
+// gather pass runs workgroups of several wavefronts, each on one slice, that
+// copy the slice's first `hub` vertices (its highest degrees) to LDS once for
+// their wavefronts, each of which takes one wave item: at most
+// kHubItemCap entries and kHubRows consecutive present rows, entries packed as
+// local column << kHubRowBits | (j - j0), lane l owning the contiguous run
+// [l RL, (l+1) RL) of the item's entries, stored transposed (element i of the
+// run at i * 64 + l).  A row with more than kHubItemCap entries in a slice is
+// cut into chunk items (plain local columns); the last chunk to finish adds
+// the chunk sums in chunk order.
+constexpr int kHubNpt = 32;                  // entries per lane of a wave item
+constexpr int kHubItemCap = 64 * kHubNpt;    // entries per wave item
+constexpr int kHubRowBits = 11;              // packed row field (j - j0 < kHubRows)
+constexpr int kHubRows = 1024;               // present rows per wave item (LDS row sums)
+// LDS row sums are padded by one word per 32 (row r at r + r / 32): the rows a
+// lane finishes step by its run length, which would otherwise put the lanes
+// of a store on a few banks
+constexpr int kHubRowsPad = kHubRows + kHubRows / 32;
+constexpr int kHubConfigs = 4;               // launch shapes (waves per workgroup, hub size)
+#ifdef CPAA_TEST_SLICE_ENTRY_LIMIT
+constexpr int64_t kSliceEntryLimit = CPAA_TEST_SLICE_ENTRY_LIMIT;   // test builds only
+#else
+constexpr int64_t kSliceEntryLimit = INT32_MAX;   // int32 entry offsets of the work items
+#endif
+
+// Launch shapes of the hub-sliced gather pass: wavefronts per workgroup and
+// hub vertices in LDS (one copy per workgroup, shared by its wavefronts).  LDS
+// per workgroup: waves * kHubRowsPad * 4 + hub * 4 bytes (gfx950: at most
+// 160 KB).  Measured on the 4M-vertex power-law graph (gather pass per term):
+// 16 / 16,384 188 us, 16 / 22,528 188 us, 8 / 8,192 197 us, 4 / 2,048 224 us;
+// a persistent variant (workgroups looping over items claimed from a counter)
+// took 420-540 us, and the per-item layout's pass 219 us.
+struct HubShape {
+  int waves, hub;   // one workgroup per `waves` consecutive wave items of a slice
+};
+constexpr HubShape kHubShapes[kHubConfigs] = {{16, 16384}, {8, 8192}, {4, 2048}, {16, 22528}};
+// slice_shape 1-4 select a shape above, 5 the per-item layout (SlicedMap);
+// automatic choice and the shape of deterministic plans (compact partials)
+constexpr int kSliceShapeAuto = 1;
+constexpr int kHubDeterministicShape = 3;
+inline int hub_groups_per_slice(int k, int max_items) {
+  return (max_items + kHubShapes[k].waves - 1) / kHubShapes[k].waves;
+}
+
+struct HubItem {
+  int j0;     // first present row of the item (slice-local compact index)
+  int e0;     // first packed entry (global index into the entry array)
+  int len;    // entries of the item (the run layout pads to a multiple of 64)
+  int rows;   // present rows j0 .. j0 + rows - 1; < 0: chunk -(rows + 1) of a long row
+};
+
+struct HubMap {
+  uint32_t* d_entries = nullptr;
+  HubItem* d_items = nullptr;
+  int item_off[kSlices + 1] = {};      // items of slice s
+  int pofs[kSlices + 1] = {};          // partial sums of slice s: part[pofs[s] .. pofs[s+1])
+  uint8_t* d_mask = nullptr;           // [n] bit s: row present in slice s
+  int* d_base = nullptr;               // [ceil(n / 64)][kSlices]
+  int groups[kHubConfigs] = {};        // workgroups per slice of each launch shape
+  int cfg = 0;                         // launch shape in use
+  int n_long = 0;                      // rows cut into chunks
+  int n_chunks = 0;
+  int* d_chunk_long = nullptr;         // [n_chunks] long row of each chunk
+  int* d_long_first = nullptr;         // [n_long] first chunk
+  int* d_long_nch = nullptr;           // [n_long] chunks
+  int* d_long_out = nullptr;           // [n_long] index of the row's partial in part
+  bool built = false;
+};
+
 // One decomposition of the CSR into single-vector work items (for one npt).
 struct WorkMap {
   int npt = 0;
@@ -120,6 +195,14 @@ struct Workspace {
   int* terms = nullptr;          // [tiles]
   double* series_cert = nullptr; // [cols]
   float* part = nullptr;         // column-sliced term: [kSlices][n] FP32 partial row sums
+                                 // (directed plans), or the compact partials of HubMap
+  double* det_part = nullptr;    // deterministic plans: per-block partial sums (4 x blocks)
+  int* det_count = nullptr;      // deterministic plans: arrival counter of those sums
+  double* det_chunk = nullptr;   // deterministic plans: [split rows][det_max_chunks][2] chunk
+                                 // sums of the residual's split rows
+  int det_max_chunks = 0;
+  float* chunk_val = nullptr;    // hub-sliced term: [n_chunks] sums of long-row chunks
+  int* long_cnt = nullptr;       // hub-sliced term: [n_long] chunk arrivals
   double* dang = nullptr;        // directed plans: [5][kSlots] dangling mass of the increment
                                  // in z[0..2], then of x and |x| for the residual
   double* wdir = nullptr;        // directed plans: [n] FP64 D_out^+ x for the residual
@@ -163,11 +246,17 @@ struct cpaa_plan_s {
   int32_t* d_rp_w1 = nullptr;
   int32_t* d_ci_w1 = nullptr;
   int32_t* d_perm = nullptr;         // [n] single-vector label -> caller's label, or null
+  int32_t n_caller = 0;              // the caller's vertex count (n plus dropped vertices)
+  int32_t n_drop = 0;                // edgeless vertices dropped (opts.drop_isolated)
+  int32_t* d_dropped = nullptr;      // [n_drop] their labels in the caller's numbering
   int reordered = 0;                 // 0 caller's labels, 1 column slices, 2 reverse Cuthill-McKee
   bool directed = false;             // rows list in-neighbours; solved by the power method only
   int32_t* d_dout = nullptr;         // directed plans: [n] out-degrees
+  bool fp64 = false;                 // FP64 recurrence (opts.fp64_recurrence): row order only
+  bool deterministic = false;        // opts.deterministic
   bool sliced = false;
-  cpaa::SlicedMap slc;
+  cpaa::SlicedMap slc;               // directed plans
+  cpaa::HubMap hub;                  // undirected plans
 
   // single-vector work map in use (one of `maps`)
   int npt = 8;                       // nnz per thread of a work item
@@ -231,17 +320,21 @@ struct TermShape {
   float alpha, gamma_c, gamma;  // z_{k+1} = alpha D^{-1}A z_k - gamma_c z_k - gamma zp
   double beta;
   bool zp_is_cur;
+  double alpha_d, gamma_c_d, gamma_d;   // the same constants for the FP64 recurrence
 };
 inline TermShape term_shape(const cpaa_plan_s* pl, const Workspace& ws, bool first) {
   if (ws.method == Method::kPower) {
-    const float c = static_cast<float>(pl->c);
-    return {c, 0.f, first ? c : 0.f, 0.0, first};
+    const double c = pl->c;
+    const float cf = static_cast<float>(c);
+    return {cf, 0.f, first ? cf : 0.f, 0.0, first, c, 0.0, first ? c : 0.0};
   }
   // T_1 = t(P) T_0, T_{k+1} = 2 t(P) T_k - T_{k-1}, t(P) = (2P - (1+a)I)/(1-a)
   const double a = pl->lam_lo;
-  const float al = static_cast<float>(2.0 / (1.0 - a));
-  const float gc = static_cast<float>((1.0 + a) / (1.0 - a));
-  return {first ? al : 2.f * al, first ? gc : 2.f * gc, first ? 0.f : 1.f, pl->beta, false};
+  const double al = 2.0 / (1.0 - a);
+  const double gc = (1.0 + a) / (1.0 - a);
+  const double A = first ? al : 2.0 * al, G = first ? gc : 2.0 * gc, P = first ? 0.0 : 1.0;
+  return {static_cast<float>(A), static_cast<float>(G), static_cast<float>(P), pl->beta, false,
+          A, G, P};
 }
 
 hipError_t fill_f64(double* p, double v, size_t count, hipStream_t st);
@@ -271,6 +364,13 @@ hipError_t check_series(const cpaa_plan_s* pl, Workspace& ws, const double* cert
                         double scale, double target, int term_index, hipStream_t st);
 hipError_t residual_w1(const cpaa_plan_s* pl, Workspace& ws, hipStream_t st);
 hipError_t finalize_w1(const cpaa_plan_s* pl, Workspace& ws, double* x, double scale,
+                       hipStream_t st);
+// Dropped (edgeless) vertices of a drop_isolated plan: their share of the
+// right-hand side's statistics ([0] sum, [3] sum over dropped vertices, [4]
+// negative and [5] non-finite counts), and their results x_v = scale * p_v.
+hipError_t dropped_stats(const cpaa_plan_s* pl, Workspace& ws, const double* src,
+                         hipStream_t st);
+hipError_t dropped_out(const cpaa_plan_s* pl, const double* src, double scale, double* x,
                        hipStream_t st);
 
 // ---- directed graphs: the power method in x-space (kernels_w1.hip) ----

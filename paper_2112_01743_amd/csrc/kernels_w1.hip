@@ -34,7 +34,8 @@ __device__ __forceinline__ void split_chunk_finish(const WorkItem it, const int*
                                                    V s, V sa, V* __restrict__ split_part,
                                                    int* __restrict__ split_count,
                                                    const int* __restrict__ split_nchunks,
-                                                   Epi& epi) {
+                                                   Epi& epi, V* __restrict__ det_chunk = nullptr,
+                                                   int max_chunks = 0, int chunk_cap = 1) {
   __shared__ V wsum[4];
   __shared__ V wabs[4];
   const int t = threadIdx.x;
@@ -45,6 +46,35 @@ __device__ __forceinline__ void split_chunk_finish(const WorkItem it, const int*
     wabs[t >> 6] = sa;
   }
   __syncthreads();
+  if (t == 0 && det_chunk != nullptr) {
+    // deterministic plans: each chunk publishes its sums in its own slot and the
+    // last chunk to arrive adds the chunks in chunk order
+    const int slot = -(it.row1 + 1);
+    const int c = (it.nnz0 - rp[it.row0]) / chunk_cap;
+    V* own = det_chunk + (static_cast<size_t>(slot) * max_chunks + c) * 2;
+    __hip_atomic_store(&own[0], (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    if (ABS)
+      __hip_atomic_store(&own[1], (wabs[0] + wabs[1]) + (wabs[2] + wabs[3]), __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    atomics_done();
+    const int nch = split_nchunks[slot];
+    const int prev = atomicAdd(&split_count[slot], 1);
+    if (prev == nch - 1) {
+      atomics_done();
+      V full = V(0), full_abs = V(0);
+      const V* row_chunks = det_chunk + static_cast<size_t>(slot) * max_chunks * 2;
+      for (int q = 0; q < nch; ++q) {
+        full += __hip_atomic_load(&row_chunks[2 * q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (ABS)
+          full_abs += __hip_atomic_load(&row_chunks[2 * q + 1], __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT);
+      }
+      __hip_atomic_exchange(&split_count[slot], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      epi.row(it.row0, rp[it.row0 + 1] - rp[it.row0], full, full_abs);
+    }
+    return;
+  }
   if (t == 0) {
     const int slot = -(it.row1 + 1);
     const int ps = ABS ? 2 * slot : slot;
@@ -74,7 +104,9 @@ template <typename V, int NPT, bool ABS, typename Epi>
 __device__ __forceinline__ void spmv_item(const WorkItem it, const int* __restrict__ rp,
                                           const int* __restrict__ ci, const V* __restrict__ x,
                                           V* __restrict__ split_part, int* __restrict__ split_count,
-                                          const int* __restrict__ split_nchunks, Epi& epi) {
+                                          const int* __restrict__ split_nchunks, Epi& epi,
+                                          V* __restrict__ det_chunk = nullptr,
+                                          int max_chunks = 0) {
   constexpr int CAP = kWG * NPT;
   __shared__ V vals[CAP];
   __shared__ int lrp[kWG * 4 + 1];
@@ -99,7 +131,8 @@ __device__ __forceinline__ void spmv_item(const WorkItem it, const int* __restri
       s += v[i];
       if (ABS) sa += fabs(v[i]);
     }
-    split_chunk_finish<V, ABS>(it, rp, s, sa, split_part, split_count, split_nchunks, epi);
+    split_chunk_finish<V, ABS>(it, rp, s, sa, split_part, split_count, split_nchunks, epi,
+                               det_chunk, max_chunks, CAP);
     return;
   }
 
@@ -149,64 +182,77 @@ __device__ __forceinline__ void spmv_item(const WorkItem it, const int* __restri
   }
 }
 
-struct TermEpi {
-  const float* __restrict__ zc;
-  const float* __restrict__ zp;
-  float* __restrict__ zn;
+// Term epilogue in the precision Z of the recurrence (float; double for the
+// FP64 debug recurrence); the accumulator and certificate are FP64 always.
+template <typename Z>
+struct TermEpiT {
+  const Z* __restrict__ zc;
+  const Z* __restrict__ zp;
+  Z* __restrict__ zn;
   double* __restrict__ acc;
-  float alpha, gamma_c, gamma;
+  Z alpha, gamma_c, gamma;
   AccUpdate au;
   double beta;
   int want_cert;
   double cert;
-  __device__ __forceinline__ void row(int r, int d, float s, float) {
-    float y = alpha * (s / static_cast<float>(d));
-    float p = 0.f, c = 0.f;
-    if (gamma != 0.f || au.a_prev != 0.0) p = zp[r];
-    if ((want_cert && beta != 0.0) || au.a_cur != 0.0 || gamma_c != 0.f) c = zc[r];
-    if (gamma_c != 0.f) y -= gamma_c * c;
-    if (gamma != 0.f) y -= gamma * p;
+  __device__ __forceinline__ bool needs_p() const { return gamma != Z(0) || au.a_prev != 0.0; }
+  __device__ __forceinline__ bool needs_c() const {
+    return (want_cert && beta != 0.0) || au.a_cur != 0.0 || gamma_c != Z(0);
+  }
+  __device__ __forceinline__ void row(int r, int d, Z s, Z) {
+    const Z p = needs_p() ? zp[r] : Z(0);
+    const Z c = needs_c() ? zc[r] : Z(0);
+    const double a_old = au.on ? acc[r] : 0.0;
+    row_loaded(r, d, s, p, c, a_old);
+  }
+  // the same with z_{k-1}(r), z_k(r) and acc(r) already loaded (as needed)
+  __device__ __forceinline__ void row_loaded(int r, int d, Z s, Z p, Z c, double a_old) {
+    Z y = alpha * (s / static_cast<Z>(d));
+    if (gamma_c != Z(0)) y -= gamma_c * c;
+    if (gamma != Z(0)) y -= gamma * p;
     zn[r] = y;
     if (au.on) {
       // the newest (smallest) term first
       double add = au.a_next * static_cast<double>(y);
       if (au.a_cur != 0.0) add += au.a_cur * static_cast<double>(c);
       if (au.a_prev != 0.0) add += au.a_prev * static_cast<double>(p);
-      acc[r] += add;
+      acc[r] = a_old + add;
     }
     if (want_cert)
       cert += static_cast<double>(d) *
               fabs(static_cast<double>(y) - beta * static_cast<double>(c));
   }
 };
+using TermEpi = TermEpiT<float>;
 
-struct TermArgs {
+template <typename Z>
+struct TermArgsT {
   const int* rp;
   const int* ci;
   const WorkItem* items;
-  const float* zc;
-  const float* zp;
-  float* zn;
+  const Z* zc;
+  const Z* zp;
+  Z* zn;
   double* acc;
-  float alpha, gamma_c, gamma;
+  Z alpha, gamma_c, gamma;
   AccUpdate au;
   double beta;
   double* cert;          // [kSlots] or null
   const int* done;       // stop flag or null
-  float* split_part;
+  Z* split_part;
   int* split_count;
   const int* split_nchunks;
   int xcd;
 };
 
-template <int NPT>
-__global__ __launch_bounds__(kWG) void k_term_w1(TermArgs a) {
+template <int NPT, typename Z>
+__global__ __launch_bounds__(kWG) void k_term_w1(TermArgsT<Z> a) {
   if (a.done != nullptr && *a.done) return;
   const int lb = xcd_logical(blockIdx.x, gridDim.x, a.xcd);
-  TermEpi epi{a.zc, a.zp, a.zn, a.acc, a.alpha, a.gamma_c, a.gamma, a.au, a.beta,
-              a.cert != nullptr, 0.0};
-  spmv_item<float, NPT, false>(a.items[lb], a.rp, a.ci, a.zc, a.split_part, a.split_count,
-                        a.split_nchunks, epi);
+  TermEpiT<Z> epi{a.zc, a.zp, a.zn, a.acc, a.alpha, a.gamma_c, a.gamma, a.au, a.beta,
+                  a.cert != nullptr, 0.0};
+  spmv_item<Z, NPT, false>(a.items[lb], a.rp, a.ci, a.zc, a.split_part, a.split_count,
+                           a.split_nchunks, epi);
   if (a.cert != nullptr) {
     const double s = block_sum256(epi.cert);
     if (threadIdx.x == 0 && s != 0.0) atomic_add(&a.cert[lb % kSlots], s);
@@ -407,6 +453,230 @@ __global__ __launch_bounds__(kWG) void k_combine_w1(CombineArgs a) {
   }
 }
 
+// ---- hub-sliced term (undirected plans; layout in internal.h) ----
+// Pass 1 (k_term_hub): workgroup b serves column slice b % 8 (the XCD the
+// hardware places it on, so the slice's part of z_k stays in that XCD's L2),
+// copies the slice's first HUB vertices to LDS once for its WAVES wavefronts,
+// and each wavefront sums one wave item.  Gathers of hub columns read LDS, the
+// rest read the slice in L2.  Row sums are formed without atomics and in a
+// fixed order: each lane sums the rows of its run in a register, rows inside
+// the run are complete, and the rows that cross lane boundaries are finished
+// by a segmented scan over the lanes (Hillis-Steele, keyed by row), so every
+// present row is written once, in LDS, and then copied out coalesced.
+// Pass 2 (k_combine_hub) adds a row's partials in slice order and runs the
+// term epilogue.
+struct HubArgs {
+  const uint32_t* entries;
+  const HubItem* items;
+  const float* zc;
+  float* part;             // [pofs[kSlices]]
+  const int* done;
+  float* chunk_val;
+  int* long_cnt;
+  const int* chunk_long;
+  const int* long_first;
+  const int* long_nch;
+  const int* long_out;
+  int item_off[kSlices + 1];
+  int slice_off[kSlices + 1];
+  int pofs[kSlices + 1];
+};
+
+// ordering of LDS accesses between the lanes of one wavefront
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int WAVES, int HUB>
+__global__ __launch_bounds__(WAVES * 64) void k_term_hub(HubArgs a) {
+  if (a.done != nullptr && *a.done) return;
+  __shared__ float hub[HUB];
+  __shared__ float rsum[WAVES][kHubRowsPad];
+  const int sl = blockIdx.x % kSlices;
+  const int grp = blockIdx.x / kSlices;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nk = a.item_off[sl + 1] - a.item_off[sl];
+  if (grp * WAVES >= nk) return;   // past the slice's last item (whole workgroup)
+  const int lo = a.slice_off[sl];
+  const float* __restrict__ xs = a.zc + lo;
+  const int nh = min(HUB, a.slice_off[sl + 1] - lo);
+  for (int c = threadIdx.x; c < nh; c += WAVES * 64) hub[c] = xs[c];
+  __syncthreads();
+  const HubItem* __restrict__ items = a.items + a.item_off[sl];
+  float* __restrict__ part = a.part + a.pofs[sl];
+  float* rs = rsum[wv];
+  constexpr uint32_t kNone = kSliceNone;
+  constexpr uint32_t row_mask = (1u << kHubRowBits) - 1u;
+  const int k = grp * WAVES + wv;
+  if (k < nk) {
+    const HubItem it = items[k];
+    if (it.rows < 0) {
+      // chunk of a long row: plain local columns, one wavefront sum
+      float sum = 0.f;
+#pragma unroll
+      for (int i = 0; i < kHubNpt; ++i) {
+        const int j = lane + i * 64;
+        if (j < it.len) {
+          const uint32_t c = __builtin_nontemporal_load(a.entries + it.e0 + j);
+          sum += c < static_cast<uint32_t>(HUB) ? hub[c] : xs[c];
+        }
+      }
+      sum = wave_sum(sum);
+      if (lane == 0) {
+        // publish the chunk sum, then count the arrival; the last chunk adds
+        // all chunk sums in chunk order (fixed order whatever the arrivals)
+        const int slot = -(it.rows + 1);
+        __hip_atomic_exchange(&a.chunk_val[slot], sum, __ATOMIC_RELAXED,
+                              __HIP_MEMORY_SCOPE_AGENT);
+        atomics_done();
+        const int lr = a.chunk_long[slot];
+        const int prev = atomicAdd(&a.long_cnt[lr], 1);
+        if (prev == a.long_nch[lr] - 1) {
+          atomics_done();
+          const int f = a.long_first[lr], nc = a.long_nch[lr];
+          float tot = 0.f;
+          for (int q = 0; q < nc; ++q)
+            tot += __hip_atomic_exchange(&a.chunk_val[f + q], 0.f, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_exchange(&a.long_cnt[lr], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          a.part[a.long_out[lr]] = tot;
+        }
+      }
+      return;
+    }
+    const int RL = (it.len + 63) >> 6;
+    const int rl = max(0, min(RL, it.len - lane * RL));   // entries of this lane's run
+    const uint32_t* __restrict__ pe = a.entries + it.e0 + lane;
+    uint32_t e[kHubNpt];
+#pragma unroll
+    for (int i = 0; i < kHubNpt; ++i) e[i] = (i < RL) ? __builtin_nontemporal_load(pe + i * 64) : kNone;
+    // Present rows of an item are consecutive and each has an entry, so along
+    // a run the row rises by exactly one where a new row starts: the run's
+    // first row and a bit mask of row starts replace the packed entries once
+    // the gathers are issued.
+    const int fr = rl > 0 ? static_cast<int>(e[0] & row_mask) : -1;
+    uint32_t starts = 0;
+#pragma unroll
+    for (int i = 1; i < kHubNpt; ++i)
+      if (i < rl && ((e[i] ^ e[i - 1]) & row_mask) != 0) starts |= 1u << i;
+    float v[kHubNpt];
+#pragma unroll
+    for (int i = 0; i < kHubNpt; ++i) {
+      const uint32_t c = e[i] >> kHubRowBits;
+      float h = 0.f, g = 0.f;
+      if (i < rl && c < static_cast<uint32_t>(HUB)) h = hub[c];
+      if (i < rl && c >= static_cast<uint32_t>(HUB)) g = xs[c];
+      v[i] = h + g;
+    }
+    // rows of the run: the first (fr, fs) and last (lr, ls) may continue in the
+    // neighbouring lanes; rows strictly between are complete here.  Every
+    // finished row is stored; the first row's store is overwritten below with
+    // its complete sum by this same lane.  (v[i] = 0 past the run.)
+    int row = fr;
+    float fs = 0.f, cur = v[0];
+#pragma unroll
+    for (int i = 1; i < kHubNpt; ++i) {
+      const bool st = (starts >> i) & 1u;
+      if (st) rs[row + (row >> 5)] = cur;
+      fs = (st && row == fr) ? cur : fs;
+      row += st ? 1 : 0;
+      cur = st ? v[i] : cur + v[i];
+    }
+    const int lr = row;
+    const float ls = cur;
+    if (fr == lr) fs = ls;
+    // segmented inclusive scan of the last-row sums over the lanes (rows
+    // ascend with the lane, so equal keys are contiguous); empty lanes get
+    // keys of their own
+    const int key = rl > 0 ? lr : -2 - lane;
+    float S = rl > 0 ? ls : 0.f;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const float So = __shfl_up(S, off);
+      const int ko = __shfl_up(key, off);
+      if (lane >= off && ko == key) S = So + S;
+    }
+    const int key_prev = __shfl_up(key, 1);
+    const float S_prev = __shfl_up(S, 1);
+    const int fr_next = __shfl_down(rl > 0 ? fr : -1, 1);
+    if (rl > 0) {
+      if (fr != lr) rs[fr + (fr >> 5)] = (lane > 0 && key_prev == fr) ? S_prev + fs : fs;
+      if (lane == 63 || fr_next != lr) rs[lr + (lr >> 5)] = S;
+    }
+    wave_lds_sync();
+    for (int r = lane; r < it.rows; r += 64) part[it.j0 + r] = rs[r + (r >> 5)];
+  }
+}
+
+struct HubCombineArgs {
+  double* det_part;       // deterministic plans: per-block certificate partials, else null
+  int* det_count;
+  const int* rp;
+  const uint8_t* mask;
+  const int* base;        // [ceil(n/64)][kSlices]
+  const float* part;
+  int pofs[kSlices];
+  const float* zc;
+  const float* zp;
+  float* zn;
+  double* acc;
+  float alpha, gamma_c, gamma;
+  AccUpdate au;
+  double beta;
+  double* cert;
+  const int* done;
+  int n;
+};
+
+__global__ __launch_bounds__(kWG) void k_combine_hub(HubCombineArgs a) {
+  if (a.done != nullptr && *a.done) return;
+  TermEpi epi{a.zc, a.zp, a.zn, a.acc, a.alpha, a.gamma_c, a.gamma, a.au, a.beta,
+              a.cert != nullptr, 0.0};
+  // one row per thread, one 64-row block per wavefront (grid covers n)
+  const int lane = threadIdx.x & 63;
+  const uint64_t below = (uint64_t(1) << lane) - 1;
+  const int blk = __builtin_amdgcn_readfirstlane(static_cast<int>(
+      blockIdx.x * (kWG / 64) + (threadIdx.x >> 6)));
+  const int u = blk * 64 + lane;
+  if (blk * 64 < a.n) {
+    // the row's own inputs are loaded first, so they are in flight together
+    // with the partials (whose addresses need the mask and the block bases)
+    const bool in = u < a.n;
+    const int d = in ? a.rp[u + 1] - a.rp[u] : 1;
+    const float p = in && epi.needs_p() ? a.zp[u] : 0.f;
+    const float c = in && epi.needs_c() ? a.zc[u] : 0.f;
+    const double a_old = in && a.au.on ? a.acc[u] : 0.0;
+    const uint32_t m = in ? a.mask[u] : 0u;
+    const int* __restrict__ bs = a.base + static_cast<size_t>(blk) * kSlices;
+    int idx[kSlices];
+#pragma unroll
+    for (int sl = 0; sl < kSlices; ++sl) {
+      const bool bit = (m >> sl) & 1u;
+      idx[sl] = bit ? a.pofs[sl] + bs[sl] + __popcll(__ballot(bit) & below) : -1;
+    }
+    float pv[kSlices];
+#pragma unroll
+    for (int sl = 0; sl < kSlices; ++sl) pv[sl] = idx[sl] >= 0 ? a.part[idx[sl]] : 0.f;
+    float s = 0.f;
+#pragma unroll
+    for (int sl = 0; sl < kSlices; ++sl)
+      if (idx[sl] >= 0) s += pv[sl];
+    if (in) epi.row_loaded(u, d, s, p, c, a_old);
+  }
+  if (a.cert != nullptr) {
+    double c[1] = {block_sum256(epi.cert)};
+    if (a.det_part != nullptr) {
+      if (ordered_block_sum<1>(c, blockIdx.x, gridDim.x, a.det_part, a.det_count) &&
+          threadIdx.x == 0)
+        atomic_add(&a.cert[0], c[0]);
+    } else if (threadIdx.x == 0 && c[0] != 0.0) {
+      atomic_add(&a.cert[blockIdx.x % kSlots], c[0]);
+    }
+  }
+}
+
 struct ResidEpi {
   const double* __restrict__ acc;
   const double* __restrict__ b;
@@ -446,6 +716,10 @@ struct ResidArgs {
   int* split_count;
   const int* split_nchunks;
   int xcd;
+  double* det_part;     // deterministic plans: per-block statistics, else null
+  int* det_count;
+  double* det_chunk;    // deterministic plans: per-chunk sums of split rows
+  int max_chunks;
 };
 
 template <int NPT>
@@ -453,13 +727,29 @@ __global__ __launch_bounds__(kWG) void k_resid_w1(ResidArgs a) {
   const int lb = xcd_logical(blockIdx.x, gridDim.x, a.xcd);
   ResidEpi epi{a.acc, a.b, a.r, a.c, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   spmv_item<double, NPT, true>(a.items[lb], a.rp, a.ci, a.acc, a.split_part, a.split_count,
-                         a.split_nchunks, epi);
-  const double s_abs = block_sum256(epi.f_abs);
+                               a.split_nchunks, epi, a.det_part ? a.det_chunk : nullptr,
+                               a.max_chunks);
+  double sums[4] = {block_sum256(epi.f_abs), block_sum256(epi.f_q), block_sum256(epi.f_mass),
+                    block_sum256(epi.f_round)};
   const double s_max = block_max256(epi.f_max);
-  const double s_q = block_sum256(epi.f_q);
-  const double s_mass = block_sum256(epi.f_mass);
-  const double s_round = block_sum256(epi.f_round);
   const double s_bad = block_sum256(epi.f_bad);
+  if (a.det_part != nullptr) {
+    // deterministic plans: real-valued sums in block order; the maximum and the
+    // count of non-finite rows are exact in any order
+    if (ordered_block_sum<4>(sums, lb, gridDim.x, a.det_part, a.det_count) &&
+        threadIdx.x == 0) {
+      atomic_add(&a.stat_slots[0], sums[0]);
+      atomic_add(&a.stat_slots[2], sums[1]);
+      atomic_add(&a.stat_slots[3], sums[2]);
+      atomic_add(&a.stat_slots[4], sums[3]);
+    }
+    if (threadIdx.x == 0) {
+      atomic_max_nonneg(&a.stat_slots[1], s_max);
+      if (s_bad != 0.0) atomic_add(&a.stat_slots[5], s_bad);
+    }
+    return;
+  }
+  const double s_abs = sums[0], s_q = sums[1], s_mass = sums[2], s_round = sums[3];
   if (threadIdx.x == 0) {
     double* o = a.stat_slots + (size_t)(lb % kSlots) * kStat;
     atomic_add(&o[0], s_abs);
@@ -473,13 +763,16 @@ __global__ __launch_bounds__(kWG) void k_resid_w1(ResidArgs a) {
 
 // z_0 = b / d (FP32), acc (+)= (c_0/2) b / d (FP64), b = scale * src.
 // Statistics: [0] sum src, [2] sum b^2/d, [4] #negative src, [5] #non-finite src.
+template <typename Z>
 __global__ __launch_bounds__(kWG) void k_init_w1(int n, const int* __restrict__ rp,
                                                  const int* __restrict__ perm,
                                                  const double* __restrict__ src, double scale,
                                                  int add, int store_b, int series, double c0h,
-                                                 double* __restrict__ b, float* __restrict__ z0,
+                                                 double* __restrict__ b, Z* __restrict__ z0,
                                                  double* __restrict__ acc,
-                                                 double* __restrict__ stat_slots) {
+                                                 double* __restrict__ stat_slots,
+                                                 double* __restrict__ det_part,
+                                                 int* __restrict__ det_count) {
   double f_sum = 0, f_q = 0, f_neg = 0, f_bad = 0;
   for (int u = blockIdx.x * kWG + threadIdx.x; u < n; u += gridDim.x * kWG) {
     const double p = src[perm ? perm[u] : u];
@@ -488,7 +781,7 @@ __global__ __launch_bounds__(kWG) void k_init_w1(int n, const int* __restrict__ 
     const double y = bu / d;
     if (store_b) b[u] = bu;
     if (series) {
-      z0[u] = static_cast<float>(y);
+      z0[u] = static_cast<Z>(y);
       acc[u] = add ? acc[u] + c0h * y : c0h * y;
     }
     f_sum += p;
@@ -496,12 +789,26 @@ __global__ __launch_bounds__(kWG) void k_init_w1(int n, const int* __restrict__ 
     f_neg += (p < 0.0) ? 1.0 : 0.0;
     f_bad += isfinite(p) ? 0.0 : 1.0;
   }
-  const double s0 = block_sum256(f_sum), s2 = block_sum256(f_q);
+  double sums[2] = {block_sum256(f_sum), block_sum256(f_q)};
   const double s4 = block_sum256(f_neg), s5 = block_sum256(f_bad);
+  if (det_part != nullptr) {
+    // deterministic plans: the real-valued sums in block order (the counts are
+    // exact in any order)
+    if (ordered_block_sum<2>(sums, blockIdx.x, gridDim.x, det_part, det_count) &&
+        threadIdx.x == 0) {
+      atomic_add(&stat_slots[0], sums[0]);
+      atomic_add(&stat_slots[2], sums[1]);
+    }
+    if (threadIdx.x == 0) {
+      if (s4 != 0.0) atomic_add(&stat_slots[4], s4);
+      if (s5 != 0.0) atomic_add(&stat_slots[5], s5);
+    }
+    return;
+  }
   if (threadIdx.x == 0) {
     double* o = stat_slots + (size_t)(blockIdx.x % kSlots) * kStat;
-    atomic_add(&o[0], s0);
-    atomic_add(&o[2], s2);
+    atomic_add(&o[0], sums[0]);
+    atomic_add(&o[2], sums[1]);
     if (s4 != 0.0) atomic_add(&o[4], s4);
     if (s5 != 0.0) atomic_add(&o[5], s5);
   }
@@ -866,11 +1173,22 @@ __global__ __launch_bounds__(kWG) void k_combine_dir(DirCombineArgs a) {
 
 hipError_t init_w1(const cpaa_plan_s* pl, Workspace& ws, const double* src, double scale,
                    bool add, bool store_b, bool series, hipStream_t st) {
-  hipLaunchKernelGGL(k_init_w1, dim3(elem_grid(pl->n)), dim3(kWG), 0, st, pl->n, pl->d_rp_w1,
-                     src == ws.r ? nullptr : pl->d_perm, src, scale, add ? 1 : 0,
-                     store_b ? 1 : 0, series ? 1 : 0, series_a0(pl, ws),
-                     ws.b, ws.z[0], ws.acc, ws.stat_slots);
-  return hipGetLastError();
+  if (pl->fp64)
+    hipLaunchKernelGGL(k_init_w1<double>, dim3(elem_grid(pl->n)), dim3(kWG), 0, st, pl->n,
+                       pl->d_rp_w1, src == ws.r ? nullptr : pl->d_perm, src, scale, add ? 1 : 0,
+                       store_b ? 1 : 0, series ? 1 : 0, series_a0(pl, ws), ws.b,
+                       reinterpret_cast<double*>(ws.z[0]), ws.acc, ws.stat_slots,
+                       pl->deterministic ? ws.det_part : nullptr, ws.det_count);
+  else
+    hipLaunchKernelGGL(k_init_w1<float>, dim3(elem_grid(pl->n)), dim3(kWG), 0, st, pl->n,
+                       pl->d_rp_w1, src == ws.r ? nullptr : pl->d_perm, src, scale, add ? 1 : 0,
+                       store_b ? 1 : 0, series ? 1 : 0, series_a0(pl, ws), ws.b, ws.z[0],
+                       ws.acc, ws.stat_slots, pl->deterministic ? ws.det_part : nullptr,
+                       ws.det_count);
+  hipError_t e = hipGetLastError();
+  // a caller's right-hand side: its dropped vertices join the statistics
+  if (e == hipSuccess && store_b && src != ws.r) e = dropped_stats(pl, ws, src, st);
+  return e;
 }
 
 hipError_t load_x0_w1(const cpaa_plan_s* pl, Workspace& ws, const double* x0, hipStream_t st) {
@@ -913,11 +1231,71 @@ void sliced_pass(const cpaa_plan_s* pl, Workspace& ws, int cur, const int* done,
     hipLaunchKernelGGL((k_term_sliced<kSliceNpt, 11>), grid, dim3(kWG), 0, st, s);
 }
 
+// Pass 1 of a hub-sliced term with launch shape cfg: partial sums of z_cur
+// into ws.part.
+void hub_pass(const cpaa_plan_s* pl, Workspace& ws, int cur, const int* done, int cfg,
+              hipStream_t st) {
+  const HubMap& hm = pl->hub;
+  HubArgs h;
+  h.entries = hm.d_entries;
+  h.items = hm.d_items;
+  h.zc = ws.z[cur];
+  h.part = ws.part;
+  h.done = done;
+  h.chunk_val = ws.chunk_val;
+  h.long_cnt = ws.long_cnt;
+  h.chunk_long = hm.d_chunk_long;
+  h.long_first = hm.d_long_first;
+  h.long_nch = hm.d_long_nch;
+  h.long_out = hm.d_long_out;
+  for (int i = 0; i <= kSlices; ++i) {
+    h.item_off[i] = hm.item_off[i];
+    h.slice_off[i] = pl->slc.slice_off[i];
+    h.pofs[i] = hm.pofs[i];
+  }
+  const dim3 grid(kSlices * hm.groups[cfg]);
+#define CPAA_HUB_LAUNCH(K)                                                            \
+  hipLaunchKernelGGL((k_term_hub<kHubShapes[K].waves, kHubShapes[K].hub>), grid,      \
+                     dim3(kHubShapes[K].waves * 64), 0, st, h)
+  switch (cfg) {
+    case 1: CPAA_HUB_LAUNCH(1); break;
+    case 2: CPAA_HUB_LAUNCH(2); break;
+    case 3: CPAA_HUB_LAUNCH(3); break;
+    default: CPAA_HUB_LAUNCH(0); break;
+  }
+#undef CPAA_HUB_LAUNCH
+}
+
 }  // namespace
 
 hipError_t term_w1(const cpaa_plan_s* pl, Workspace& ws, int cur, int prev, int next, bool first,
                    const AccUpdate& au, double* cert_slot, const int* done, hipStream_t st) {
   const TermShape sh = term_shape(pl, ws, first);
+  if (pl->sliced && pl->hub.built) {
+    hub_pass(pl, ws, cur, done, pl->hub.cfg, st);
+    HubCombineArgs c;
+    c.det_part = pl->deterministic ? ws.det_part : nullptr;
+    c.det_count = ws.det_count;
+    c.rp = pl->d_rp_w1;
+    c.mask = pl->hub.d_mask;
+    c.base = pl->hub.d_base;
+    c.part = ws.part;
+    for (int i = 0; i < kSlices; ++i) c.pofs[i] = pl->hub.pofs[i];
+    c.zc = ws.z[cur];
+    c.zp = first ? (sh.zp_is_cur ? ws.z[cur] : nullptr) : ws.z[prev];
+    c.zn = ws.z[next];
+    c.acc = ws.acc;
+    c.alpha = sh.alpha;
+    c.gamma_c = sh.gamma_c;
+    c.gamma = sh.gamma;
+    c.au = au;
+    c.beta = sh.beta;
+    c.cert = cert_slot;
+    c.done = done;
+    c.n = pl->n;
+    hipLaunchKernelGGL(k_combine_hub, dim3((pl->n + kWG - 1) / kWG), dim3(kWG), 0, st, c);
+    return hipGetLastError();
+  }
   if (pl->sliced) {
     sliced_pass(pl, ws, cur, done, st);
     CombineArgs c;
@@ -938,7 +1316,38 @@ hipError_t term_w1(const cpaa_plan_s* pl, Workspace& ws, int cur, int prev, int 
     hipLaunchKernelGGL(k_combine_w1, dim3(elem_grid(pl->n)), dim3(kWG), 0, st, c);
     return hipGetLastError();
   }
-  TermArgs a;
+  if (pl->fp64) {
+    // FP64 recurrence (debug option): the same row-order kernel in double
+    double* const* zd = reinterpret_cast<double* const*>(ws.z);
+    TermArgsT<double> a;
+    a.rp = pl->d_rp_w1;
+    a.ci = pl->d_ci_w1;
+    a.items = pl->d_items;
+    a.zc = zd[cur];
+    a.zp = first ? (sh.zp_is_cur ? zd[cur] : nullptr) : zd[prev];
+    a.zn = zd[next];
+    a.acc = ws.acc;
+    a.alpha = sh.alpha_d;
+    a.gamma_c = sh.gamma_c_d;
+    a.gamma = sh.gamma_d;
+    a.au = au;
+    a.beta = sh.beta;
+    a.cert = cert_slot;
+    a.done = done;
+    a.split_part = ws.split_d;
+    a.split_count = ws.split_count;
+    a.split_nchunks = pl->d_split_nchunks;
+    a.xcd = pl->xcd_remap;
+    const dim3 grid(pl->n_items);
+    switch (pl->npt) {
+      case 4: hipLaunchKernelGGL((k_term_w1<4, double>), grid, dim3(kWG), 0, st, a); break;
+      case 16: hipLaunchKernelGGL((k_term_w1<16, double>), grid, dim3(kWG), 0, st, a); break;
+      case 32: hipLaunchKernelGGL((k_term_w1<32, double>), grid, dim3(kWG), 0, st, a); break;
+      default: hipLaunchKernelGGL((k_term_w1<8, double>), grid, dim3(kWG), 0, st, a); break;
+    }
+    return hipGetLastError();
+  }
+  TermArgsT<float> a;
   a.rp = pl->d_rp_w1;
   a.ci = pl->d_ci_w1;
   a.items = pl->d_items;
@@ -959,10 +1368,10 @@ hipError_t term_w1(const cpaa_plan_s* pl, Workspace& ws, int cur, int prev, int 
   a.xcd = pl->xcd_remap;
   const dim3 grid(pl->n_items);
   switch (pl->npt) {
-    case 4: hipLaunchKernelGGL(k_term_w1<4>, grid, dim3(kWG), 0, st, a); break;
-    case 16: hipLaunchKernelGGL(k_term_w1<16>, grid, dim3(kWG), 0, st, a); break;
-    case 32: hipLaunchKernelGGL(k_term_w1<32>, grid, dim3(kWG), 0, st, a); break;
-    default: hipLaunchKernelGGL(k_term_w1<8>, grid, dim3(kWG), 0, st, a); break;
+    case 4: hipLaunchKernelGGL((k_term_w1<4, float>), grid, dim3(kWG), 0, st, a); break;
+    case 16: hipLaunchKernelGGL((k_term_w1<16, float>), grid, dim3(kWG), 0, st, a); break;
+    case 32: hipLaunchKernelGGL((k_term_w1<32, float>), grid, dim3(kWG), 0, st, a); break;
+    default: hipLaunchKernelGGL((k_term_w1<8, float>), grid, dim3(kWG), 0, st, a); break;
   }
   return hipGetLastError();
 }
@@ -981,6 +1390,10 @@ hipError_t residual_w1(const cpaa_plan_s* pl, Workspace& ws, hipStream_t st) {
   a.split_count = ws.split_count;
   a.split_nchunks = pl->d_split_nchunks;
   a.xcd = pl->xcd_remap;
+  a.det_part = pl->deterministic ? ws.det_part : nullptr;
+  a.det_count = ws.det_count;
+  a.det_chunk = ws.det_chunk;
+  a.max_chunks = ws.det_max_chunks;
   const dim3 grid(pl->n_items);
   switch (pl->npt) {
     case 4: hipLaunchKernelGGL(k_resid_w1<4>, grid, dim3(kWG), 0, st, a); break;
@@ -988,6 +1401,56 @@ hipError_t residual_w1(const cpaa_plan_s* pl, Workspace& ws, hipStream_t st) {
     case 32: hipLaunchKernelGGL(k_resid_w1<32>, grid, dim3(kWG), 0, st, a); break;
     default: hipLaunchKernelGGL(k_resid_w1<8>, grid, dim3(kWG), 0, st, a); break;
   }
+  return hipGetLastError();
+}
+
+namespace {
+
+// One workgroup, a fixed summation order: the dropped vertices' p into the
+// statistics of the right-hand side (so the whole p is validated).
+__global__ __launch_bounds__(kWG) void k_dropped_stats(int nd, const int* __restrict__ dropped,
+                                                       const double* __restrict__ src,
+                                                       double* __restrict__ stat) {
+  double sum = 0.0, neg = 0.0, bad = 0.0;
+  for (int i = threadIdx.x; i < nd; i += kWG) {
+    const double p = src[dropped[i]];
+    sum += p;
+    neg += p < 0.0 ? 1.0 : 0.0;
+    bad += isfinite(p) ? 0.0 : 1.0;
+  }
+  sum = block_sum256(sum);
+  neg = block_sum256(neg);
+  bad = block_sum256(bad);
+  if (threadIdx.x == 0) {
+    atomic_add(&stat[0], sum);
+    atomic_add(&stat[3], sum);
+    if (neg != 0.0) atomic_add(&stat[4], neg);
+    if (bad != 0.0) atomic_add(&stat[5], bad);
+  }
+}
+
+__global__ __launch_bounds__(kWG) void k_dropped_out(int nd, const int* __restrict__ dropped,
+                                                     const double* __restrict__ src, double scale,
+                                                     double* __restrict__ x) {
+  for (int i = blockIdx.x * kWG + threadIdx.x; i < nd; i += gridDim.x * kWG)
+    x[dropped[i]] = scale * src[dropped[i]];
+}
+
+}  // namespace
+
+hipError_t dropped_stats(const cpaa_plan_s* pl, Workspace& ws, const double* src,
+                         hipStream_t st) {
+  if (pl->n_drop == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_dropped_stats, dim3(1), dim3(kWG), 0, st, pl->n_drop, pl->d_dropped, src,
+                     ws.stat_slots);
+  return hipGetLastError();
+}
+
+hipError_t dropped_out(const cpaa_plan_s* pl, const double* src, double scale, double* x,
+                       hipStream_t st) {
+  if (pl->n_drop == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_dropped_out, dim3(elem_grid(pl->n_drop)), dim3(kWG), 0, st, pl->n_drop,
+                     pl->d_dropped, src, scale, x);
   return hipGetLastError();
 }
 

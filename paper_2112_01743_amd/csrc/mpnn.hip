@@ -684,9 +684,10 @@ cpaa_status cpaa_model_create(cpaa_plan_t pl, int32_t layers, int32_t hidden, co
     return CPAA_EINVAL;
   }
   *out = nullptr;
-  if (layers < 1 || layers > 4 || hidden != kHid || pl->num_graphs > 1 || pl->directed) {
+  if (layers < 1 || layers > 4 || hidden != kHid || pl->num_graphs > 1 || pl->directed ||
+      pl->n_drop > 0) {
     set_error("the warm-start network supports 1..4 layers of width 64 on a single-graph "
-              "undirected plan");
+              "undirected plan without dropped vertices");
     return CPAA_EINVAL;
   }
   cpaa_model_s* md = new (std::nothrow) cpaa_model_s();

@@ -26,7 +26,9 @@
 namespace cpaa {
 
 void free_workspace(Workspace& ws) {
-  void* ptrs[] = {ws.z[0], ws.z[1], ws.z[2], ws.acc, ws.part, ws.dang, ws.wdir, ws.part_d,
+  void* ptrs[] = {ws.z[0], ws.z[1], ws.z[2], ws.acc, ws.part, ws.chunk_val, ws.long_cnt,
+                  ws.det_part, ws.det_count, ws.det_chunk,
+                  ws.dang, ws.wdir, ws.part_d,
                   ws.b, ws.r,
                   ws.slots, ws.stat_slots,
                   ws.stat, ws.done, ws.terms, ws.series_cert, ws.split_f, ws.split_d,
@@ -66,10 +68,35 @@ cpaa_status ensure_workspace(cpaa_plan_s* pl, Workspace& ws, int W, int tiles) {
     return true;
   };
   bool ok = true;
-  for (int i = 0; i < 3; ++i) ok = ok && alloc((void**)&ws.z[i], ws.vec_elems * sizeof(float));
+  // the FP64 recurrence (single-vector path only) keeps doubles in the z buffers
+  const size_t zbytes = (W == 1 && pl->fp64) ? sizeof(double) : sizeof(float);
+  for (int i = 0; i < 3; ++i) ok = ok && alloc((void**)&ws.z[i], ws.vec_elems * zbytes);
   ok = ok && alloc((void**)&ws.acc, ws.vec_elems * sizeof(double));
-  if (W == 1 && pl->sliced)
+  if (W == 1 && pl->sliced && pl->hub.built) {
+    ok = ok && alloc((void**)&ws.part, (size_t)pl->hub.pofs[kSlices] * sizeof(float));
+    ok = ok && alloc((void**)&ws.chunk_val, (size_t)pl->hub.n_chunks * sizeof(float));
+    ok = ok && alloc((void**)&ws.long_cnt, (size_t)pl->hub.n_long * sizeof(int));
+    if (ok)
+      ok = hipMemset(ws.chunk_val, 0, (size_t)std::max(pl->hub.n_chunks, 1) * sizeof(float)) ==
+               hipSuccess &&
+           hipMemset(ws.long_cnt, 0, (size_t)std::max(pl->hub.n_long, 1) * sizeof(int)) ==
+               hipSuccess;
+  } else if (W == 1 && pl->sliced) {
     ok = ok && alloc((void**)&ws.part, (size_t)kSlices * pl->n * sizeof(float));
+  }
+  if (W == 1 && pl->deterministic) {
+    // per-block partials of the largest grid that reduces: the combine pass
+    // (one row per thread), the init kernel, the residual (one block per item)
+    const size_t blocks = std::max<size_t>({(size_t)(pl->n + kWG - 1) / kWG, (size_t)8192,
+                                            (size_t)std::max(pl->n_items, 1)});
+    ws.det_max_chunks = pl->max_deg / (kWG * 4) + 2;   // chunks of 256 x 4 entries or more
+    ok = ok && alloc((void**)&ws.det_part, 4 * blocks * sizeof(double));
+    ok = ok && alloc((void**)&ws.det_count, sizeof(int));
+    ok = ok && alloc((void**)&ws.det_chunk,
+                     (size_t)std::max(pl->max_split_rows, 1) * ws.det_max_chunks * 2 *
+                         sizeof(double));
+    if (ok) ok = hipMemset(ws.det_count, 0, sizeof(int)) == hipSuccess;
+  }
   if (W == 1 && pl->directed) {
     ok = ok && alloc((void**)&ws.dang, (size_t)5 * kSlots * sizeof(double));
     ok = ok && alloc((void**)&ws.wdir, (size_t)pl->n * sizeof(double));
@@ -398,6 +425,33 @@ namespace {
 cpaa_status solve_directed(cpaa_plan_t pl, const double* p, double tol, double* x,
                            cpaa_report* rep, void* stream);
 
+cpaa_status solve_single(cpaa_plan_t pl, const double* p, double tol, const double* x0, double* x,
+                         cpaa_report* rep, void* stream, Method method);
+
+// Batched solves of plans whose options live on the single-vector path only
+// (fp64_recurrence, deterministic): one column after another.
+cpaa_status solve_columns(cpaa_plan_t pl, int32_t B, const double* P, int64_t ldp, double tol,
+                          const double* X0, int64_t ldx0, double* X, int64_t ldx,
+                          cpaa_report* reps, void* stream, Method method) {
+  bool all_ok = true;
+  for (int32_t j = 0; j < B; ++j) {
+    cpaa_report R;
+    std::memset(&R, 0, sizeof(R));
+    const cpaa_status s = solve_single(pl, P + (size_t)j * ldp, tol,
+                                       X0 ? X0 + (size_t)j * ldx0 : nullptr,
+                                       X + (size_t)j * ldx, &R, stream, method);
+    if (s != CPAA_OK && s != CPAA_ENOCONV) return s;
+    all_ok = all_ok && s == CPAA_OK;
+    if (reps) reps[j] = R;
+  }
+  if (!all_ok) {
+    set_error("tolerance not certified for every column");
+    return CPAA_ENOCONV;
+  }
+  set_error("");
+  return CPAA_OK;
+}
+
 // Batched solves of a directed plan: the power method, one column after
 // another through the single-vector path (no tiled directed kernel).
 cpaa_status solve_directed_columns(cpaa_plan_t pl, int32_t B, const double* P, int64_t ldp,
@@ -457,16 +511,17 @@ cpaa_status solve_single(cpaa_plan_t pl, const double* p, double tol, const doub
   const double* dp = p;
   const double* dx0 = x0;
   double* dx = x;
+  const size_t n_io = static_cast<size_t>(pl->n_caller);   // p, x0, x: the caller's vertices
   if (!pl->opts.io_device) {
-    if (hipMalloc(&tp.p, n * sizeof(double)) != hipSuccess ||
-        hipMalloc(&tx.p, n * sizeof(double)) != hipSuccess ||
-        (x0 && hipMalloc(&tx0.p, n * sizeof(double)) != hipSuccess)) {
+    if (hipMalloc(&tp.p, n_io * sizeof(double)) != hipSuccess ||
+        hipMalloc(&tx.p, n_io * sizeof(double)) != hipSuccess ||
+        (x0 && hipMalloc(&tx0.p, n_io * sizeof(double)) != hipSuccess)) {
       (void)hipGetLastError();
       set_error("device allocation for host I/O failed");
       return CPAA_ENOMEM;
     }
-    CPAA_HIP(hipMemcpyAsync(tp.p, p, n * sizeof(double), hipMemcpyHostToDevice, st));
-    if (x0) CPAA_HIP(hipMemcpyAsync(tx0.p, x0, n * sizeof(double), hipMemcpyHostToDevice, st));
+    CPAA_HIP(hipMemcpyAsync(tp.p, p, n_io * sizeof(double), hipMemcpyHostToDevice, st));
+    if (x0) CPAA_HIP(hipMemcpyAsync(tx0.p, x0, n_io * sizeof(double), hipMemcpyHostToDevice, st));
     dp = static_cast<const double*>(tp.p);
     dx0 = x0 ? static_cast<const double*>(tx0.p) : nullptr;
     dx = static_cast<double*>(tx.p);
@@ -565,7 +620,8 @@ cpaa_status solve_single(cpaa_plan_t pl, const double* p, double tol, const doub
     R.series_cert = hv.series_cert[0];
     R.resid_l1 = stat_at(ws, 1, 0, 0);
     R.resid_max = stat_at(ws, 1, 0, 1);
-    R.mass = stat_at(ws, 1, 0, 3);
+    // the dropped vertices of a drop_isolated plan hold (1-c) p_v each
+    R.mass = stat_at(ws, 1, 0, 3) + (1.0 - c) * stat_at(ws, 0, 0, 3);
     bound = rigorous_bound(pl, R.resid_l1, stat_at(ws, 1, 0, 4), R.mass);
     if (bound <= tol || !std::isfinite(bound) || R.refinements >= pl->opts.max_refine) break;
     // correction series on b' = r: x += x_M(r)
@@ -583,9 +639,10 @@ cpaa_status solve_single(cpaa_plan_t pl, const double* p, double tol, const doub
   R.certified = (bound <= tol) ? 1 : 0;
   const double scale = pl->opts.normalize ? 1.0 / R.mass : 1.0;
   CPAA_HIP(finalize_w1(pl, ws, dx, scale, st));
+  CPAA_HIP(dropped_out(pl, dp, (1.0 - c) * scale, dx, st));
   CPAA_HIP(hipEventRecord(pl->ev_end, st));
   if (!pl->opts.io_device)
-    CPAA_HIP(hipMemcpyAsync(x, dx, n * sizeof(double), hipMemcpyDeviceToHost, st));
+    CPAA_HIP(hipMemcpyAsync(x, dx, n_io * sizeof(double), hipMemcpyDeviceToHost, st));
   CPAA_HIP(hipStreamSynchronize(st));
   float ms = 0.f;
   CPAA_HIP(hipEventElapsedTime(&ms, pl->ev_begin, pl->ev_end));
@@ -636,10 +693,13 @@ cpaa_status solve_batched(cpaa_plan_t pl, int32_t B, const double* P, int64_t ld
     return CPAA_EINVAL;
   }
   const int64_t n = pl->n;
-  if (ldp < n || ldx < n || (X0 && ldx0 < n)) {
+  const int64_t n_io = pl->n_caller;
+  if (ldp < n_io || ldx < n_io || (X0 && ldx0 < n_io)) {
     set_error("leading dimensions must be >= n");
     return CPAA_EINVAL;
   }
+  if (pl->fp64 || pl->deterministic || pl->n_drop > 0)
+    return solve_columns(pl, B, P, ldp, tol, X0, ldx0, X, ldx, reps, stream, method);
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   cpaa_status s;
   if (pl->opts.autotune && pl->opts.tile_w == 0 && !pl->tuned_tile && pl->opts.io_device) {
@@ -933,7 +993,8 @@ cpaa_status solve_directed(cpaa_plan_t pl, const double* p, double tol, double* 
     R.series_cert = hv.series_cert[0];
     R.resid_l1 = stat_at(ws, 1, 0, 0);
     R.resid_max = stat_at(ws, 1, 0, 1);
-    R.mass = stat_at(ws, 1, 0, 3);
+    // the dropped vertices of a drop_isolated plan hold (1-c) p_v each
+    R.mass = stat_at(ws, 1, 0, 3) + (1.0 - c) * stat_at(ws, 0, 0, 3);
     bound = rigorous_bound(pl, R.resid_l1, stat_at(ws, 1, 0, 4), R.mass);
     if (bound <= tol || !std::isfinite(bound) || R.refinements >= pl->opts.max_refine) break;
     // correction: the same iteration on b' = r from x_0 = r/(1-c), added to acc

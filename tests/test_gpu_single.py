@@ -145,21 +145,43 @@ def test_work_item_sizes_agree(torch_cuda, npt):
     _assert_parity(g, p, x, rep, 1e-8)
 
 
+@pytest.mark.parametrize("shape", [1, 2, 3, 4])
 @pytest.mark.parametrize("case", ["chung_lu", "grid", "star", "path", "complete", "big_star"])
-def test_column_sliced_term_agrees(torch_cuda, case):
-    """Column-sliced term (relabelled vertices, one column slice per XCD,
-    partial row sums combined per term), forced on graphs of every shape;
-    big_star's centre has more entries per slice than a work item holds."""
-    g = {"chung_lu": lambda: gg.chung_lu(60000, 12, 2.1, seed=5, dmax=20000),
+def test_column_sliced_term_agrees(torch_cuda, case, shape):
+    """Column-sliced term (relabelled vertices, one column slice per XCD, a
+    partial sum per row and slice with entries, combined per term), forced on
+    graphs of every shape and with every launch shape of its gather pass;
+    big_star's centre has more entries per slice than a wave item holds (long
+    row cut into chunks), chung_lu has more rows than the LDS hub of every
+    shape."""
+    g = {"chung_lu": lambda: gg.chung_lu(300000, 12, 2.1, seed=5, dmax=20000),
          "grid": lambda: gg.perturbed_grid(150, 0.05, 0.01, seed=4),
          "star": lambda: gg.star(40), "path": lambda: gg.path(7),
          "complete": lambda: gg.complete(30), "big_star": lambda: gg.star(100000)}[case]()
     for p in (gg.uniform_personalization(g.n), gg.source_personalization(g.n, [g.n // 2])[0],
               gg.source_personalization(g.n, [0])[0]):
-        x, rep, plan = _solve(torch_cuda, g, p, 1e-9, column_slices=8)
+        x, rep, plan = _solve(torch_cuda, g, p, 1e-9, column_slices=8, slice_shape=shape)
         info = plan.info()
         assert info["column_slices"] == 8 and info["reordered"] == 1
+        assert info["slice_shape"] == shape
         _assert_parity(g, p, x, rep, 1e-9)
+
+
+@pytest.mark.parametrize("shape", [1, 4])
+def test_column_sliced_term_parity_with_oracle_cpaa(torch_cuda, shape):
+    """Pinned term counts on the column-sliced path: the FP32-recurrence x_M
+    against the oracle's FP64 x_M (hubs split into chunks, rows spread over
+    every slice)."""
+    g = gg.chung_lu(200000, 10, 2.1, seed=78, dmax=30000)
+    p = gg.source_personalization(g.n, [3])[0]
+    for M in (1, 2, 5, 12, 30):
+        x, rep, _ = _solve(torch_cuda, g, p, 1e-14, k_max=M, max_refine=0, column_slices=8,
+                           slice_shape=shape)
+        assert rep["terms"] == M and rep["refinements"] == 0
+        ref = oracle.cpaa(g, (1 - C) * p, C, M)
+        err = np.abs(x - ref).sum()
+        _note(f"shape={shape} M={M} term-parity L1={err:.3e}")
+        assert err <= 2e-6 * max(1.0, np.abs(ref).sum()), (M, err)
 
 
 def test_column_sliced_warm_start_and_host_io(torch_cuda):
@@ -432,3 +454,149 @@ def test_independent_plans_on_two_streams(torch_cuda):
     for i, (plan, g, p) in enumerate(cases):
         x, rep = out[i]
         _assert_parity(g, p, x, rep, 1e-8)
+
+
+@pytest.mark.parametrize("name,g", [
+    ("chung_lu", lambda: gg.chung_lu(20000, 10, 2.1, seed=9, dmax=5000)),
+    ("grid", lambda: gg.perturbed_grid(80, 0.05, 0.01, seed=3)),
+    ("star", lambda: gg.star(3000)),
+])
+def test_fp64_recurrence_matches_oracle_terms(torch_cuda, name, g):
+    """fp64_recurrence = 1 (the debug mode): with the term count pinned the
+    result is the oracle's FP64 x_M up to rounding order (1e-12 in L1), for
+    the Chebyshev series and for the power method's iterates; the star has a
+    hub split across workgroups."""
+    g = g()
+    p = gg.source_personalization(g.n, [g.n // 3])[0]
+    for M in (1, 2, 5, 12, 30):
+        x, rep, plan = _solve(torch_cuda, g, p, 1e-15, k_max=M, max_refine=0, fp64_recurrence=1)
+        assert plan.info()["column_slices"] == 1
+        assert rep["terms"] == M and rep["refinements"] == 0
+        ref = oracle.cpaa(g, (1 - C) * p, C, M)
+        err = np.abs(x - ref).sum()
+        _note(f"{name} fp64 M={M} L1={err:.3e}")
+        assert err <= 1e-12, (M, err)
+    ref = oracle.power_method(g, p, C, 20, return_all=True)
+    from paper_2112_01743_amd import Plan
+    for t in (1, 7, 20):
+        plan = Plan.from_graph(g, C, k_max=t, max_refine=0, fp64_recurrence=1)
+        xp, rp = plan.solve_power(_dev(torch_cuda, p), 1e-15)
+        assert rp["terms"] == t
+        err = np.abs(xp.cpu().numpy() - ref[t]).sum()
+        _note(f"{name} fp64 power t={t} L1={err:.3e}")
+        assert err <= 1e-12, (t, err)
+
+
+def test_fp64_recurrence_batched_and_certified(torch_cuda):
+    """Batched calls on an FP64-recurrence plan solve column by column and
+    certify to a tolerance the FP32 recurrence cannot reach in one series."""
+    from paper_2112_01743_amd import Plan
+    g = gg.chung_lu(8000, 8, 2.3, seed=21)
+    src = [0, 17, 4000]
+    P = gg.source_personalization(g.n, src)
+    plan = Plan.from_graph(g, C, fp64_recurrence=1, max_refine=0)
+    X, reps = plan.solve_batched(_dev(torch_cuda, P), 1e-11)
+    ref = oracle.pagerank_power(g, P.T, C, tol=1e-14)[0].T
+    errs = np.abs(X.cpu().numpy() - ref).sum(axis=1)
+    _note(f"fp64 batched errors {errs}")
+    assert all(r["certified"] for r in reps) and errs.max() <= 1e-11
+    for j, s in enumerate(src):
+        x, rep = plan.solve(_dev(torch_cuda, P[j]), 1e-11)
+        assert np.abs(x.cpu().numpy() - X[j].cpu().numpy()).sum() <= 1e-14
+
+
+def test_fp64_recurrence_option_checks(torch_cuda):
+    from paper_2112_01743_amd import Plan, binding as B
+    g = gg.chung_lu(2000, 8, 2.3, seed=3)
+    with pytest.raises(B.CpaaError):
+        Plan.from_graph(g, C, fp64_recurrence=1, column_slices=8)
+    with pytest.raises(B.CpaaError):
+        Plan.from_graph(g, C, fp64_recurrence=1, deterministic=1)
+
+
+@pytest.mark.parametrize("name,g", [
+    ("chung_lu", lambda: gg.chung_lu(200000, 12, 2.1, seed=41, dmax=30000)),
+    ("big_star", lambda: gg.star(100000)),
+])
+def test_deterministic_solves_are_bitwise_equal(torch_cuda, name, g):
+    """deterministic = 1: two solves of the same input, on the same plan and on
+    a second plan, give identical bits (hub rows split into chunks in the
+    column-sliced term and in the residual, every reduction in block order),
+    and the result is certified against the oracle like any other."""
+    from paper_2112_01743_amd import Plan
+    torch = torch_cuda
+    g = g()
+    plan = Plan.from_graph(g, C, deterministic=1)
+    assert plan.info()["column_slices"] == 8 and plan.info()["slice_shape"] > 0
+    for p in (gg.uniform_personalization(g.n), gg.source_personalization(g.n, [1])[0]):
+        pd = _dev(torch, p)
+        x1, r1 = plan.solve(pd, 1e-9)
+        x2, r2 = plan.solve(pd, 1e-9)
+        x3, r3 = Plan.from_graph(g, C, deterministic=1).solve(pd, 1e-9)
+        a, b, c = (v.cpu().numpy() for v in (x1, x2, x3))
+        assert np.array_equal(a, b) and np.array_equal(a, c)
+        assert r1["cert_bound"] == r2["cert_bound"] == r3["cert_bound"]
+        assert r1["terms"] == r3["terms"] and r1["refine_terms"] == r3["refine_terms"]
+        _assert_parity(g, p, a, r1, 1e-9)
+        # a warm start and the power method are deterministic too
+        xw1, _ = plan.solve(pd, 1e-9, x0=x1)
+        xw2, _ = plan.solve(pd, 1e-9, x0=x1)
+        assert np.array_equal(xw1.cpu().numpy(), xw2.cpu().numpy())
+        xp1, _ = plan.solve_power(pd, 1e-7)
+        xp2, _ = plan.solve_power(pd, 1e-7)
+        assert np.array_equal(xp1.cpu().numpy(), xp2.cpu().numpy())
+    # batched calls solve column by column: each column equals its single solve
+    P = gg.source_personalization(g.n, [0, 5, g.n - 1])
+    X, reps = plan.solve_batched(_dev(torch, P), 1e-9)
+    for j in range(P.shape[0]):
+        xj, _ = plan.solve(_dev(torch, P[j]), 1e-9)
+        assert np.array_equal(X[j].cpu().numpy(), xj.cpu().numpy())
+
+
+def _with_isolated(base, n_iso, seed):
+    """base plus n_iso edgeless vertices at random labels; returns (graph, kept labels)."""
+    n = base.n + n_iso
+    iso = np.sort(gg.philox(seed).choice(n, n_iso, replace=False))
+    keep = np.setdiff1d(np.arange(n), iso)
+    rows = np.repeat(np.arange(base.n), np.diff(base.row_ptr))
+    u, v = keep[rows], keep[base.col_idx]
+    m = u < v
+    return gg.csr_from_edges(n, u[m], v[m]), keep, iso
+
+
+@pytest.mark.parametrize("opts", [{}, {"column_slices": 8}, {"deterministic": 1},
+                                  {"normalize": 1}])
+def test_drop_isolated_matches_oracle_on_kept_vertices(torch_cuda, opts):
+    """drop_isolated = 1 on a graph with edgeless vertices: P has a zero column
+    there, so the kept vertices hold the PageRank of the graph without them for
+    p restricted to them (the linear system (I - cP) x = (1-c) p), and each
+    dropped vertex holds (1-c) p_v (Sec. 2.1); single and batched solves."""
+    from paper_2112_01743_amd import Plan
+    torch = torch_cuda
+    base = gg.chung_lu(6000, 8, 2.3, seed=5)
+    g, keep, iso = _with_isolated(base, 37, seed=3)
+    assert np.all(np.diff(g.row_ptr)[iso] == 0)
+    plan = Plan.from_graph(g, C, drop_isolated=1, **opts)
+    assert plan.info()["n"] == g.n
+    P = np.stack([gg.uniform_personalization(g.n),
+                  gg.source_personalization(g.n, [keep[10]])[0],
+                  gg.source_personalization(g.n, [iso[3]])[0]])
+    X, reps = plan.solve_batched(_dev(torch, P), 1e-9)
+    for j in range(P.shape[0]):
+        want = np.zeros(g.n)
+        want[keep] = oracle.pagerank_exact(base, P[j][keep], C) if base.n <= 2500 else \
+            oracle.pagerank_power(base, P[j][keep], C, tol=1e-13)[0]
+        want[iso] = (1 - C) * P[j][iso]
+        if opts.get("normalize"):
+            want /= want.sum()
+        got = X[j].cpu().numpy()
+        x1, r1 = plan.solve(_dev(torch, P[j]), 1e-9)
+        assert np.abs(x1.cpu().numpy() - got).sum() <= 1e-12
+        err = np.abs(got - want).sum()
+        _note(f"drop_isolated {opts} column {j}: L1 {err:.2e}")
+        assert reps[j]["certified"] == 1 and err <= 1e-9, (j, err)
+        assert np.array_equal(got[iso], want[iso] if not opts.get("normalize") else got[iso])
+    # without the option the plan refuses the graph
+    from paper_2112_01743_amd import binding as B
+    with pytest.raises(B.CpaaError):
+        Plan.from_graph(g, C)

@@ -65,11 +65,13 @@ def test_default_opts():
     assert o.max_refine == 2 and o.validate == 1 and o.io_device == 1 and o.xcd_remap == -1
 
 
-def _plan_status(rp, ci, c=0.85, **kw):
+def _plan_status(rp, ci, c=0.85, values=None, **kw):
     rp = np.asarray(rp, dtype=np.int32)
     ci = np.asarray(ci, dtype=np.int32)
+    val = None if values is None else np.ascontiguousarray(values, dtype=np.float64)
     csr = B.cpaa_csr(n=len(rp) - 1, nnz=len(ci), row_ptr=rp.ctypes.data, col_idx=ci.ctypes.data,
-                     num_graphs=0, graph_ptr=None, on_device=0)
+                     num_graphs=0, graph_ptr=None, on_device=0,
+                     values=None if val is None else val.ctypes.data)
     o = B.cpaa_default_opts()
     for k, v in kw.items():
         setattr(o, k, v)
@@ -181,3 +183,55 @@ def test_bench_refuses_more_than_one_gpu():
     res = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
                          capture_output=True, text=True, timeout=120)
     assert res.returncode == 2 and "one GPU" in res.stderr and res.stdout == ""
+
+
+def test_plan_checks_values_against_inverse_degrees():
+    """The optional values must be the entries of P = A D^-1 (Sec. 2.1): 1/deg of
+    the column (1/out-degree for a directed plan); anything else is refused
+    before device work, and valid values pass the check (on a CPU-only host
+    the plan then stops at its first device allocation)."""
+    g = gg.chung_lu(300, 6, 2.3, seed=8)
+    rp, ci = g.row_ptr, g.col_idx
+    deg = np.diff(rp).astype(np.float64)
+    good = 1.0 / deg[ci]
+    assert _plan_status(rp, ci, values=good) in (B.CPAA_OK, B.CPAA_ENOMEM, B.CPAA_EDEVICE)
+    for j in (0, len(ci) // 2, len(ci) - 1):
+        bad = good.copy()
+        bad[j] *= 1.0 + 1e-12
+        assert _plan_status(rp, ci, values=bad) == B.CPAA_EINVAL
+        assert f"values[{j}]" in B.cpaa_last_error()
+    # the row's own degree instead of the column's (P transposed) is refused
+    rowdeg = 1.0 / np.repeat(deg, np.diff(rp))
+    assert not np.allclose(rowdeg, good)
+    assert _plan_status(rp, ci, values=rowdeg) == B.CPAA_EINVAL
+    # directed: out-degree of the column vertex (the number of rows listing it)
+    drp = np.array([0, 0, 1, 3], dtype=np.int32)      # edges 0->1, 0->2, 1->2
+    dci = np.array([0, 0, 1], dtype=np.int32)
+    dout = np.bincount(dci, minlength=3).astype(np.float64)
+    assert _plan_status(drp, dci, values=1.0 / dout[dci], directed=1) in (
+        B.CPAA_OK, B.CPAA_ENOMEM, B.CPAA_EDEVICE)
+    assert _plan_status(drp, dci, values=np.ones(3), directed=1) == B.CPAA_EINVAL
+
+
+def test_drop_isolated_plan_options():
+    """drop_isolated = 1 accepts edgeless vertices in an undirected graph (the
+    plan then stops only at its first device allocation without a GPU), refuses
+    a graph without edges and the directed and block-diagonal cases."""
+    rp = np.array([0, 1, 2, 2, 2], dtype=np.int32)    # edge 0-1, vertices 2 and 3 alone
+    ci = np.array([1, 0], dtype=np.int32)
+    assert _plan_status(rp, ci) == B.CPAA_EISOLATED
+    assert _plan_status(rp, ci, drop_isolated=1) in (B.CPAA_OK, B.CPAA_ENOMEM, B.CPAA_EDEVICE)
+    assert _plan_status(rp, ci, drop_isolated=1, column_slices=8) in (
+        B.CPAA_OK, B.CPAA_ENOMEM, B.CPAA_EDEVICE)
+    assert _plan_status(np.zeros(4, dtype=np.int32), np.zeros(0, dtype=np.int32),
+                        drop_isolated=1) == B.CPAA_EISOLATED
+    assert _plan_status(rp, ci, drop_isolated=1, directed=1) == B.CPAA_EINVAL
+    assert _plan_status(rp, ci, drop_isolated=2) == B.CPAA_EINVAL
+    for bad in ({"fp64_recurrence": 2}, {"deterministic": 3},
+                {"fp64_recurrence": 1, "column_slices": 8},
+                {"fp64_recurrence": 1, "deterministic": 1},
+                {"deterministic": 1, "column_slices": 1},
+                {"deterministic": 1, "slice_shape": 5},
+                {"slice_shape": 6}):
+        g = gg.cycle(6)
+        assert _plan_status(g.row_ptr, g.col_idx, **bad) == B.CPAA_EINVAL, bad

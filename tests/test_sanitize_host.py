@@ -17,6 +17,9 @@ sys.path.insert(0, ROOT)
 # sanitizers on the host side of every translation unit (never on device code)
 HOST_SAN = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
             "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer"]
+# a low cap on the packed entries of the column-sliced layout (int32 offsets in
+# the product build), so that the driver reaches the guard with small graphs
+ENTRY_LIMIT = ["-DCPAA_TEST_SLICE_ENTRY_LIMIT=100000"]
 
 
 @pytest.mark.slow
@@ -29,7 +32,8 @@ def test_plan_host_code_under_asan_and_ubsan(tmp_path):
     procs = []
     for src in B.SOURCES:
         obj = str(tmp_path / (os.path.splitext(src)[0] + ".o"))
-        cmd = [B.HIPCC, *B.FLAGS, "-O1", *HOST_SAN, "-c", os.path.join(B.CSRC, src), "-o", obj]
+        cmd = [B.HIPCC, *B.FLAGS, "-O1", *HOST_SAN, *ENTRY_LIMIT, "-c", os.path.join(B.CSRC, src),
+               "-o", obj]
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT,
                                             text=True)))
         objs.append(obj)
@@ -40,7 +44,7 @@ def test_plan_host_code_under_asan_and_ubsan(tmp_path):
     subprocess.run([B.HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *HOST_SAN, "-o", lib,
                     *objs], check=True, capture_output=True)
     exe = str(tmp_path / "plan_driver")
-    subprocess.run([clang, "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined",
+    subprocess.run([clang, "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined", *ENTRY_LIMIT,
                     "-fno-sanitize-recover=all", "-I", os.path.join(ROOT, "include"),
                     os.path.join(ROOT, "tests", "sanitize_plan_driver.cpp"), lib,
                     "-Wl,-rpath," + str(tmp_path), "-L/opt/rocm/lib", "-lamdhip64",
