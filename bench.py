@@ -435,6 +435,99 @@ def bench_graph_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_config0(args):
+    """Plain CPAA, global PageRank on the Erdos-Renyi graph n = 10,000, average
+    degree 10 (seed 2112000, isolated vertices dropped), p = e/n, terms from the
+    coefficient tail: the first K whose eq. 4.1 tail bound is below 1e-10
+    (K = 39 at c = 0.85), every solve certified to 1e-10 in L1 by the FP64
+    residual.  The graph (0.4 MB of pattern, 40 KB vectors) lives in L2, so a
+    term is bound by launch latency; its roofline fraction is reported, not
+    targeted."""
+    import torch
+    import graphgen as gg
+    from paper_2112_01743_amd import Plan
+    c = 0.85
+    g = gg.erdos_renyi(10_000, 10, seed=2112000)
+    k = mass_rule_terms(c, 1e-10)
+    plan = Plan.from_graph(g, c, time_kernels=1)
+    p = torch.full((g.n,), 1.0 / g.n, dtype=torch.float64, device="cuda")
+    x = torch.empty_like(p)
+    for _ in range(args.warmup):
+        plan.solve(p, 1e-10, out=x)
+    torch.cuda.synchronize()
+    reps = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, rep = plan.solve(p, 1e-10, out=x)
+        reps.append(rep)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    certified = all(r["certified"] for r in reps)
+    edges = sum(r["edges"] for r in reps)
+    launches = sum(r["term_launches"] for r in reps)
+    avg_launch_s = sum(r["ms_terms"] for r in reps) / 1e3 / max(launches, 1)
+    alg = term_bytes(g.n, g.nnz)
+    out = {"metric": METRIC, "value": edges / wall / 1e9 if certified else None, "unit": "GTEPS",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": wall * 1e3 / args.steps, "higher_is_better": True,
+           "dtype": "f32 recurrence, f64 accumulation", "data": "synthetic",
+           "config": {"workload": "erdos_renyi_10k_global_pagerank", "n": g.n, "nnz": g.nnz,
+                      "avg_degree_target": 10, "seed": 2112000, "c": c, "tol_l1": 1e-10,
+                      "tail_bound_terms": k},
+           "solves_per_s": args.steps / wall, "terms": reps[-1]["terms"],
+           "refine_terms": reps[-1]["refine_terms"], "cert_bound": reps[-1]["cert_bound"],
+           "certified": certified,
+           "roofline": {"bound": "hbm", "achieved": alg / avg_launch_s / 1e9,
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": alg / avg_launch_s / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                        "kernel": "term = k_term_w1 (row order; L2-resident, launch-bound)",
+                        "bytes_per_launch": alg, "avg_launch_us": avg_launch_s * 1e6}}
+    print(json.dumps(out), flush=True)
+
+
+def bench_warmstart(args):
+    """The learned warm start (the configured workload): the network trained on
+    plain-CPAA targets of 20,000 random sources of the 1M-vertex Chung-Lu
+    training graph (seed 2112004), evaluated on 1,024 held-out sources of an
+    unseen graph (seed 2112005): warm-started solves (network guess, CPAA on the
+    residual, plain CPAA as fallback and judge) against plain batched solves at
+    1e-6 L1.  value = warm-started solves/s including inference."""
+    import torch
+    torch.cuda.init()
+    import graphgen as gg
+    from paper_2112_01743_amd import Plan
+    from paper_2112_01743_amd.binding import Model
+    from paper_2112_01743_amd import warmstart as ws
+    c = 0.85
+    g_tr = gg.chung_lu(1_000_000, 16, 2.1, seed=2112004, dmax=50000)
+    g_ev = gg.chung_lu(1_000_000, 16, 2.1, seed=2112005, dmax=50000)
+    plan_tr = Plan.from_graph(g_tr, c)
+    model = Model(plan_tr, gg.mpnn_init(2112004))
+    tr_src = gg.random_sources(g_tr.n, args.train_sources, seed=2112004)
+    t0 = time.perf_counter()
+    stats = ws.train(plan_tr, model, g_tr, tr_src, batch=8, epochs=1, tol=args.tol)
+    train_s = time.perf_counter() - t0
+    w, m, v, step = model.get_state()
+    plan_ev = Plan.from_graph(g_ev, c)
+    model_ev = Model(plan_ev, gg.mpnn_init(0))
+    model_ev.set_state(w, m, v, step)
+    ev_src = gg.random_sources(g_ev.n, 1024, seed=2112005)
+    res = ws.evaluate(plan_ev, model_ev, g_ev, ev_src, tol=args.tol)
+    out = {"metric": METRIC, "value": res["warm_solves_per_s_incl_inference"],
+           "unit": "solves/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+           "ms_per_step": 1e3 * 1024 / res["warm_solves_per_s_incl_inference"],
+           "higher_is_better": True, "dtype": "bf16 network / f32 recurrence, f64 accumulation",
+           "data": "synthetic",
+           "config": {"workload": "learned_warm_start_chung_lu_1m", "n": g_ev.n, "nnz": g_ev.nnz,
+                      "train_sources": len(tr_src), "eval_sources": len(ev_src),
+                      "train_seed": 2112004, "eval_seed": 2112005, "c": c, "tol_l1": args.tol},
+           "plain_solves_per_s": res["plain_solves_per_s"], "warm": res,
+           "train": dict(stats, wall_s=train_s,
+                         ms_per_source=1e3 * stats["train_s"] / max(len(tr_src), 1)),
+           "certified": True}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -454,14 +547,19 @@ def main():
                          "1-4 a fixed shape")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="chung_lu",
-                    choices=["chung_lu", "grid_batched", "graph_batch", "table3", "directed"],
+                    choices=["chung_lu", "grid_batched", "graph_batch", "table3", "directed",
+                             "config0", "warmstart"],
                     help="chung_lu: global PageRank on the 4M-vertex power-law graph (default); "
                          "grid_batched: 256 single-source solves on the 1000x1000 perturbed "
                          "lattice in one batched call; graph_batch: 10,000 small Chung-Lu graphs "
                          "in one persistent launch; table3: rounds and time to ERR < 1e-3 "
                          "for CPAA and the power method on a Delaunay stand-in for delaunay-n21; "
                          "directed: the power method on a 4M-vertex directed graph with dangling "
-                         "vertices")
+                         "vertices; config0: global PageRank on the Erdos-Renyi 10k graph with the "
+                         "1e-10 tail; warmstart: the learned warm start trained on 20,000 sources "
+                         "of the 1M-vertex Chung-Lu graph, evaluated on 1,024 held-out sources")
+    ap.add_argument("--train-sources", type=int, default=20000,
+                    help="warmstart: training sources")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters against a known byte count)")
@@ -489,6 +587,10 @@ def main():
         return bench_table3(args)
     if args.workload == "directed":
         return bench_directed(args)
+    if args.workload == "config0":
+        return bench_config0(args)
+    if args.workload == "warmstart":
+        return bench_warmstart(args)
 
     import torch
     import graphgen as gg

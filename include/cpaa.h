@@ -260,15 +260,20 @@ CPAA_API cpaa_status cpaa_plan_info_get(cpaa_plan_t plan, cpaa_plan_info* info);
 CPAA_API cpaa_status cpaa_solve(cpaa_plan_t plan, const double* p, double tol, const double* x0,
                        double* x, cpaa_report* rep, void* stream);
 
-/* B solves at once (single-graph plan): column j of P is P[j*ldp + i], i < n,
- * likewise X0 (may be NULL) and X.  The right-hand sides are processed in
- * tiles of opts.tile_w columns by one SpMM kernel per term; each tile stops
- * when all its columns are certified (per-column in-loop certificate), and
- * each column gets its own FP64 residual and report.  On a directed plan the
- * columns are solved one after another by the single-vector power method
- * (X0 must be NULL); a column that fails validation stops the call with its
- * error, and the columns before it are already written.
- * reps: [B] or NULL.  ldp, ldx0, ldx >= n.  Other rules as cpaa_solve. */
+/* B solves at once: column j of P is P[j*ldp + i], i < n, likewise X0 (may be
+ * NULL) and X.  The right-hand sides are processed in tiles of opts.tile_w
+ * columns by one SpMM kernel per term; each tile stops when all its columns
+ * are certified (per-column in-loop certificate), and each column gets its own
+ * FP64 residual and report.  On a directed plan the columns are solved one
+ * after another by the single-vector power method (X0 must be NULL); plans
+ * with fp64_recurrence, deterministic or dropped vertices also solve their
+ * columns one after another through cpaa_solve.  A column that fails
+ * validation stops the call with its error, and the columns before it are
+ * already written.  reps: [B] or NULL.  ldp, ldx0, ldx >= n.
+ * A block-diagonal plan (num_graphs > 1) takes B = 1: the one column holds
+ * every graph's personalization at that graph's vertices (each part a
+ * distribution), X0 must be NULL, and reps receives num_graphs reports; the
+ * call is cpaa_solve_graphs.  Other rules as cpaa_solve. */
 CPAA_API cpaa_status cpaa_solve_batched(cpaa_plan_t plan, int32_t B, const double* P, int64_t ldp,
                                double tol, const double* X0, int64_t ldx0, double* X,
                                int64_t ldx, cpaa_report* reps, void* stream);

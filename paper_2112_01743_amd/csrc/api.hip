@@ -502,10 +502,11 @@ bool build_hub_sliced(int32_t n, const std::vector<int32_t>& rp2, const std::vec
     auto flush = [&]() {
       if (cur_rows == 0) return;
       const int L = static_cast<int>(logical.size());
-      const int RL = (L + 63) / 64;
+      const int RL = hub_run_length(L);
+      o.E.resize((o.E.size() + 3) & ~size_t(3), kSliceNone);   // 16-byte aligned item
       const size_t pb = o.E.size();
       o.E.resize(pb + static_cast<size_t>(64) * RL, kSliceNone);
-      for (int q = 0; q < L; ++q) o.E[pb + (q % RL) * 64 + q / RL] = logical[q];
+      for (int q = 0; q < L; ++q) o.E[pb + hub_slot(q / RL, q % RL)] = logical[q];
       o.I.push_back({cur_j0, static_cast<int64_t>(pb), L, cur_rows});
       logical.clear();
       cur_rows = 0;
@@ -620,9 +621,10 @@ bool check_hub_map(int32_t n, const int slice_off[kSlices + 1], const HubHost& h
           }
         continue;
       }
-      const int RL = (it.len + 63) / 64;
+      const int RL = hub_run_length(it.len);
       if (it.rows > kHubRows || it.rows > it.len || it.j0 + static_cast<int64_t>(it.rows) > P ||
-          static_cast<size_t>(it.e0) + static_cast<size_t>(64) * RL > ne) {
+          static_cast<size_t>(it.e0) + static_cast<size_t>(64) * RL > ne || (it.e0 & 3) != 0 ||
+          RL > kHubNpt) {
         why = "item rows or run layout";
         return false;
       }
@@ -630,7 +632,7 @@ bool check_hub_map(int32_t n, const int slice_off[kSlices + 1], const HubHost& h
       // (the kernel's cross-lane scan relies on it) and every row appears
       int prev = 0;
       for (int q = 0; q < it.len; ++q) {
-        const uint32_t e = h.entries[it.e0 + (q % RL) * 64 + q / RL];
+        const uint32_t e = h.entries[it.e0 + hub_slot(q / RL, q % RL)];
         const int r = static_cast<int>(e & ((1u << kHubRowBits) - 1u));
         if (e == kSliceNone || (e >> kHubRowBits) >= nsl || r >= it.rows || r < prev ||
             r > prev + 1 || (q == 0 && r != 0)) {
@@ -645,7 +647,7 @@ bool check_hub_map(int32_t n, const int slice_off[kSlices + 1], const HubHost& h
       }
       for (int l = 0; l < 64; ++l)
         for (int i = std::max(0, std::min(RL, it.len - l * RL)); i < RL; ++i)
-          if (h.entries[it.e0 + i * 64 + l] != kSliceNone) {
+          if (h.entries[it.e0 + hub_slot(l, i)] != kSliceNone) {
             why = "padding";
             return false;
           }

@@ -131,6 +131,15 @@ inline int hub_groups_per_slice(int k, int max_items) {
   return (max_items + kHubShapes[k].waves - 1) / kHubShapes[k].waves;
 }
 
+// Run layout of a wave item: L entries, lane l owning the logical run
+// [l RL, (l+1) RL), RL a multiple of 4, and element i of lane l's run stored at
+// hub_slot(l, i), so that each lane reads 4 consecutive run elements with one
+// 16-byte load and a wavefront's load covers 1 KB contiguously.
+__host__ __device__ inline int hub_run_length(int L) { return ((L + 255) >> 8) << 2; }
+__host__ __device__ inline int hub_slot(int lane, int i) {
+  return (i >> 2) * 256 + lane * 4 + (i & 3);
+}
+
 struct HubItem {
   int j0;     // first present row of the item (slice-local compact index)
   int e0;     // first packed entry (global index into the entry array)
@@ -201,6 +210,7 @@ struct Workspace {
   double* det_chunk = nullptr;   // deterministic plans: [split rows][det_max_chunks][2] chunk
                                  // sums of the residual's split rows
   int det_max_chunks = 0;
+  double* det_defer = nullptr;   // deterministic plans: [split rows][3] (sum, sum of |.|, row)
   float* chunk_val = nullptr;    // hub-sliced term: [n_chunks] sums of long-row chunks
   int* long_cnt = nullptr;       // hub-sliced term: [n_long] chunk arrivals
   double* dang = nullptr;        // directed plans: [5][kSlots] dangling mass of the increment
@@ -219,6 +229,7 @@ struct Workspace {
   double* host = nullptr;        // pinned host mirror
   int* poll_host = nullptr;      // pinned [2][tiles] stop flags of a series read while it runs
   size_t host_bytes = 0;
+  size_t split_elems = 0;        // split-row slots (all tiles)
 };
 
 }  // namespace cpaa

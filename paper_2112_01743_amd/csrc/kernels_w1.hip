@@ -35,7 +35,8 @@ __device__ __forceinline__ void split_chunk_finish(const WorkItem it, const int*
                                                    int* __restrict__ split_count,
                                                    const int* __restrict__ split_nchunks,
                                                    Epi& epi, V* __restrict__ det_chunk = nullptr,
-                                                   int max_chunks = 0, int chunk_cap = 1) {
+                                                   int max_chunks = 0, int chunk_cap = 1,
+                                                   V* __restrict__ det_defer = nullptr) {
   __shared__ V wsum[4];
   __shared__ V wabs[4];
   const int t = threadIdx.x;
@@ -71,7 +72,17 @@ __device__ __forceinline__ void split_chunk_finish(const WorkItem it, const int*
                                         __HIP_MEMORY_SCOPE_AGENT);
       }
       __hip_atomic_exchange(&split_count[slot], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      epi.row(it.row0, rp[it.row0 + 1] - rp[it.row0], full, full_abs);
+      if (det_defer != nullptr) {
+        // the row's epilogue (and its share of the block statistics) is left to
+        // the grid's last block, which runs the split rows in slot order
+        V* d = det_defer + static_cast<size_t>(slot) * 3;
+        __hip_atomic_store(&d[0], full, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&d[1], full_abs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&d[2], static_cast<V>(it.row0), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        epi.row(it.row0, rp[it.row0 + 1] - rp[it.row0], full, full_abs);
+      }
     }
     return;
   }
@@ -106,7 +117,7 @@ __device__ __forceinline__ void spmv_item(const WorkItem it, const int* __restri
                                           V* __restrict__ split_part, int* __restrict__ split_count,
                                           const int* __restrict__ split_nchunks, Epi& epi,
                                           V* __restrict__ det_chunk = nullptr,
-                                          int max_chunks = 0) {
+                                          int max_chunks = 0, V* __restrict__ det_defer = nullptr) {
   constexpr int CAP = kWG * NPT;
   __shared__ V vals[CAP];
   __shared__ int lrp[kWG * 4 + 1];
@@ -132,7 +143,7 @@ __device__ __forceinline__ void spmv_item(const WorkItem it, const int* __restri
       if (ABS) sa += fabs(v[i]);
     }
     split_chunk_finish<V, ABS>(it, rp, s, sa, split_part, split_count, split_nchunks, epi,
-                               det_chunk, max_chunks, CAP);
+                               det_chunk, max_chunks, CAP, det_defer);
     return;
   }
 
@@ -502,7 +513,21 @@ __global__ __launch_bounds__(WAVES * 64) void k_term_hub(HubArgs a) {
   const int lo = a.slice_off[sl];
   const float* __restrict__ xs = a.zc + lo;
   const int nh = min(HUB, a.slice_off[sl + 1] - lo);
-  for (int c = threadIdx.x; c < nh; c += WAVES * 64) hub[c] = xs[c];
+  {
+    // 16-byte loads for the 16-byte-aligned body of the hub, scalar head and tail
+    const int head = min(nh, (4 - (lo & 3)) & 3);
+    const int body = (nh - head) & ~3;
+    if (static_cast<int>(threadIdx.x) < head) hub[threadIdx.x] = xs[threadIdx.x];
+    const float4* __restrict__ src4 = reinterpret_cast<const float4*>(xs + head);
+    for (int c = threadIdx.x; c < body / 4; c += WAVES * 64) {
+      const float4 v = src4[c];
+      hub[head + 4 * c] = v.x;
+      hub[head + 4 * c + 1] = v.y;
+      hub[head + 4 * c + 2] = v.z;
+      hub[head + 4 * c + 3] = v.w;
+    }
+    for (int c = head + body + threadIdx.x; c < nh; c += WAVES * 64) hub[c] = xs[c];
+  }
   __syncthreads();
   const HubItem* __restrict__ items = a.items + a.item_off[sl];
   float* __restrict__ part = a.part + a.pofs[sl];
@@ -546,12 +571,21 @@ __global__ __launch_bounds__(WAVES * 64) void k_term_hub(HubArgs a) {
       }
       return;
     }
-    const int RL = (it.len + 63) >> 6;
+    const int RL = hub_run_length(it.len);
     const int rl = max(0, min(RL, it.len - lane * RL));   // entries of this lane's run
-    const uint32_t* __restrict__ pe = a.entries + it.e0 + lane;
+    // four consecutive run elements per 16-byte load (hub_slot layout)
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    const u32x4* __restrict__ pe4 = reinterpret_cast<const u32x4*>(a.entries + it.e0) + lane;
     uint32_t e[kHubNpt];
 #pragma unroll
-    for (int i = 0; i < kHubNpt; ++i) e[i] = (i < RL) ? __builtin_nontemporal_load(pe + i * 64) : kNone;
+    for (int q = 0; q < kHubNpt / 4; ++q) {
+      const u32x4 v = (4 * q < RL) ? __builtin_nontemporal_load(pe4 + q * 64)
+                                   : u32x4{kNone, kNone, kNone, kNone};
+      e[4 * q] = v.x;
+      e[4 * q + 1] = v.y;
+      e[4 * q + 2] = v.z;
+      e[4 * q + 3] = v.w;
+    }
     // Present rows of an item are consecutive and each has an entry, so along
     // a run the row rises by exactly one where a new row starts: the run's
     // first row and a bit mask of row starts replace the packed entries once
@@ -720,32 +754,52 @@ struct ResidArgs {
   int* det_count;
   double* det_chunk;    // deterministic plans: per-chunk sums of split rows
   int max_chunks;
+  double* det_defer;    // deterministic plans: [split rows][3] full sums and row, left to the
+                        // last block
+  int n_split;
 };
 
 template <int NPT>
 __global__ __launch_bounds__(kWG) void k_resid_w1(ResidArgs a) {
   const int lb = xcd_logical(blockIdx.x, gridDim.x, a.xcd);
   ResidEpi epi{a.acc, a.b, a.r, a.c, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  const bool det = a.det_part != nullptr;
   spmv_item<double, NPT, true>(a.items[lb], a.rp, a.ci, a.acc, a.split_part, a.split_count,
-                               a.split_nchunks, epi, a.det_part ? a.det_chunk : nullptr,
-                               a.max_chunks);
+                               a.split_nchunks, epi, det ? a.det_chunk : nullptr, a.max_chunks,
+                               det ? a.det_defer : nullptr);
   double sums[4] = {block_sum256(epi.f_abs), block_sum256(epi.f_q), block_sum256(epi.f_mass),
                     block_sum256(epi.f_round)};
   const double s_max = block_max256(epi.f_max);
   const double s_bad = block_sum256(epi.f_bad);
-  if (a.det_part != nullptr) {
+  if (det) {
     // deterministic plans: real-valued sums in block order; the maximum and the
-    // count of non-finite rows are exact in any order
-    if (ordered_block_sum<4>(sums, lb, gridDim.x, a.det_part, a.det_count) &&
-        threadIdx.x == 0) {
-      atomic_add(&a.stat_slots[0], sums[0]);
-      atomic_add(&a.stat_slots[2], sums[1]);
-      atomic_add(&a.stat_slots[3], sums[2]);
-      atomic_add(&a.stat_slots[4], sums[3]);
-    }
+    // count of non-finite rows are exact in any order.  The last block also runs
+    // the epilogue of the split rows, in slot order, and adds their statistics
+    // after the blocks'.
     if (threadIdx.x == 0) {
       atomic_max_nonneg(&a.stat_slots[1], s_max);
       if (s_bad != 0.0) atomic_add(&a.stat_slots[5], s_bad);
+    }
+    if (!ordered_block_sum<4>(sums, lb, gridDim.x, a.det_part, a.det_count)) return;
+    ResidEpi e{a.acc, a.b, a.r, a.c, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int slot = threadIdx.x; slot < a.n_split; slot += kWG) {
+      const double* d = a.det_defer + static_cast<size_t>(slot) * 3;
+      const double sv = __hip_atomic_load(&d[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const double sa = __hip_atomic_load(&d[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const int row = static_cast<int>(
+          __hip_atomic_load(&d[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+      e.row(row, a.rp[row + 1] - a.rp[row], sv, sa);
+    }
+    const double x_abs = block_sum256(e.f_abs), x_q = block_sum256(e.f_q);
+    const double x_mass = block_sum256(e.f_mass), x_round = block_sum256(e.f_round);
+    const double x_max = block_max256(e.f_max), x_bad = block_sum256(e.f_bad);
+    if (threadIdx.x == 0) {
+      atomic_add(&a.stat_slots[0], sums[0] + x_abs);
+      atomic_add(&a.stat_slots[2], sums[1] + x_q);
+      atomic_add(&a.stat_slots[3], sums[2] + x_mass);
+      atomic_add(&a.stat_slots[4], sums[3] + x_round);
+      atomic_max_nonneg(&a.stat_slots[1], x_max);
+      if (x_bad != 0.0) atomic_add(&a.stat_slots[5], x_bad);
     }
     return;
   }
@@ -1394,6 +1448,8 @@ hipError_t residual_w1(const cpaa_plan_s* pl, Workspace& ws, hipStream_t st) {
   a.det_count = ws.det_count;
   a.det_chunk = ws.det_chunk;
   a.max_chunks = ws.det_max_chunks;
+  a.det_defer = ws.det_defer;
+  a.n_split = pl->n_split_rows;
   const dim3 grid(pl->n_items);
   switch (pl->npt) {
     case 4: hipLaunchKernelGGL(k_resid_w1<4>, grid, dim3(kWG), 0, st, a); break;

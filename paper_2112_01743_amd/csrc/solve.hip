@@ -27,7 +27,7 @@ namespace cpaa {
 
 void free_workspace(Workspace& ws) {
   void* ptrs[] = {ws.z[0], ws.z[1], ws.z[2], ws.acc, ws.part, ws.chunk_val, ws.long_cnt,
-                  ws.det_part, ws.det_count, ws.det_chunk,
+                  ws.det_part, ws.det_count, ws.det_chunk, ws.det_defer,
                   ws.dang, ws.wdir, ws.part_d,
                   ws.b, ws.r,
                   ws.slots, ws.stat_slots,
@@ -47,9 +47,11 @@ static size_t host_mirror_bytes(int64_t cols, int tiles) {
          64;
 }
 
-cpaa_status ensure_workspace(cpaa_plan_s* pl, Workspace& ws, int W, int tiles) {
-  if (ws.W == W && ws.tiles == tiles && ws.z[0]) return CPAA_OK;
-  free_workspace(ws);
+// Device buffers of a workspace for W right-hand sides per tile, each taken
+// from `alloc(void** p, size_t bytes)` (which returns false when it cannot);
+// ws.W, ws.tiles, ws.cols and ws.vec_elems are set here.
+template <typename Alloc>
+bool layout_workspace(const cpaa_plan_s* pl, Workspace& ws, int W, int tiles, Alloc alloc) {
   ws.W = W;
   ws.tiles = tiles;
   ws.cols = static_cast<int64_t>(tiles) * W;
@@ -58,15 +60,6 @@ cpaa_status ensure_workspace(cpaa_plan_s* pl, Workspace& ws, int W, int tiles) {
   const size_t nsplit = (size_t)std::max(
       W == 1 ? std::max(pl->max_split_rows, pl->slc.n_split_rows) : pl->n_tsplit_rows, 1);
   const size_t split_sets = (size_t)tiles;
-  auto alloc = [&](void** p, size_t bytes) -> bool {
-    if (bytes == 0) bytes = 8;
-    if (hipMalloc(p, bytes) != hipSuccess) {
-      (void)hipGetLastError();
-      *p = nullptr;
-      return false;
-    }
-    return true;
-  };
   bool ok = true;
   // the FP64 recurrence (single-vector path only) keeps doubles in the z buffers
   const size_t zbytes = (W == 1 && pl->fp64) ? sizeof(double) : sizeof(float);
@@ -76,11 +69,6 @@ cpaa_status ensure_workspace(cpaa_plan_s* pl, Workspace& ws, int W, int tiles) {
     ok = ok && alloc((void**)&ws.part, (size_t)pl->hub.pofs[kSlices] * sizeof(float));
     ok = ok && alloc((void**)&ws.chunk_val, (size_t)pl->hub.n_chunks * sizeof(float));
     ok = ok && alloc((void**)&ws.long_cnt, (size_t)pl->hub.n_long * sizeof(int));
-    if (ok)
-      ok = hipMemset(ws.chunk_val, 0, (size_t)std::max(pl->hub.n_chunks, 1) * sizeof(float)) ==
-               hipSuccess &&
-           hipMemset(ws.long_cnt, 0, (size_t)std::max(pl->hub.n_long, 1) * sizeof(int)) ==
-               hipSuccess;
   } else if (W == 1 && pl->sliced) {
     ok = ok && alloc((void**)&ws.part, (size_t)kSlices * pl->n * sizeof(float));
   }
@@ -95,7 +83,8 @@ cpaa_status ensure_workspace(cpaa_plan_s* pl, Workspace& ws, int W, int tiles) {
     ok = ok && alloc((void**)&ws.det_chunk,
                      (size_t)std::max(pl->max_split_rows, 1) * ws.det_max_chunks * 2 *
                          sizeof(double));
-    if (ok) ok = hipMemset(ws.det_count, 0, sizeof(int)) == hipSuccess;
+    ok = ok && alloc((void**)&ws.det_defer,
+                     (size_t)std::max(pl->max_split_rows, 1) * 3 * sizeof(double));
   }
   if (W == 1 && pl->directed) {
     ok = ok && alloc((void**)&ws.dang, (size_t)5 * kSlots * sizeof(double));
@@ -117,6 +106,59 @@ cpaa_status ensure_workspace(cpaa_plan_s* pl, Workspace& ws, int W, int tiles) {
   ok = ok && alloc((void**)&ws.active, (size_t)tiles * sizeof(int));
   ok = ok && alloc((void**)&ws.plain, (size_t)ws.cols * sizeof(int));
   ok = ok && alloc((void**)&ws.col_scale, (size_t)ws.cols * sizeof(double));
+  ws.split_elems = split_sets * nsplit;
+  return ok;
+}
+
+// Buffers that must start at zero: split-row partials and arrival counters,
+// long-row chunk sums and counters, the deterministic arrival counter (every
+// protocol leaves them at zero again).  With fill kernels (`async`, for a
+// caller that may not allocate or synchronise) or synchronous memsets.
+static cpaa_status zero_workspace(Workspace& ws, const cpaa_plan_s* pl, bool async,
+                                  hipStream_t st) {
+  const size_t nsp = ws.split_elems;
+  if (async) {
+    CPAA_HIP(fill_i32(reinterpret_cast<int*>(ws.split_f), 0, nsp * ws.W, st));
+    CPAA_HIP(fill_f64(ws.split_d, 0.0, nsp * 2 * ws.W, st));
+    CPAA_HIP(fill_i32(ws.split_count, 0, nsp, st));
+    if (ws.chunk_val)
+      CPAA_HIP(fill_i32(reinterpret_cast<int*>(ws.chunk_val), 0, (size_t)pl->hub.n_chunks, st));
+    if (ws.long_cnt) CPAA_HIP(fill_i32(ws.long_cnt, 0, (size_t)pl->hub.n_long, st));
+    if (ws.det_count) CPAA_HIP(fill_i32(ws.det_count, 0, 1, st));
+    return CPAA_OK;
+  }
+  bool ok = hipMemset(ws.split_f, 0, nsp * ws.W * sizeof(float)) == hipSuccess &&
+            hipMemset(ws.split_d, 0, nsp * 2 * ws.W * sizeof(double)) == hipSuccess &&
+            hipMemset(ws.split_count, 0, nsp * sizeof(int)) == hipSuccess;
+  if (ok && ws.chunk_val)
+    ok = hipMemset(ws.chunk_val, 0, (size_t)std::max(pl->hub.n_chunks, 1) * sizeof(float)) ==
+         hipSuccess;
+  if (ok && ws.long_cnt)
+    ok = hipMemset(ws.long_cnt, 0, (size_t)std::max(pl->hub.n_long, 1) * sizeof(int)) ==
+         hipSuccess;
+  if (ok && ws.det_count) ok = hipMemset(ws.det_count, 0, sizeof(int)) == hipSuccess;
+  if (ok) ok = hipDeviceSynchronize() == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    set_error("workspace initialisation failed");
+    return CPAA_EDEVICE;
+  }
+  return CPAA_OK;
+}
+
+cpaa_status ensure_workspace(cpaa_plan_s* pl, Workspace& ws, int W, int tiles) {
+  if (ws.W == W && ws.tiles == tiles && ws.z[0]) return CPAA_OK;
+  free_workspace(ws);
+  auto alloc = [&](void** p, size_t bytes) -> bool {
+    if (bytes == 0) bytes = 8;
+    if (hipMalloc(p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      *p = nullptr;
+      return false;
+    }
+    return true;
+  };
+  bool ok = layout_workspace(pl, ws, W, tiles, alloc);
   ws.host_bytes = host_mirror_bytes(ws.cols, tiles);
   if (ok && hipHostMalloc((void**)&ws.host, ws.host_bytes, hipHostMallocDefault) != hipSuccess) {
     (void)hipGetLastError();
@@ -129,19 +171,16 @@ cpaa_status ensure_workspace(cpaa_plan_s* pl, Workspace& ws, int W, int tiles) {
     ws.poll_host = nullptr;
     ok = false;
   }
-  if (ok) {
-    ok = hipMemset(ws.split_f, 0, split_sets * nsplit * W * sizeof(float)) == hipSuccess &&
-         hipMemset(ws.split_d, 0, split_sets * nsplit * 2 * W * sizeof(double)) == hipSuccess &&
-         hipMemset(ws.split_count, 0, split_sets * nsplit * sizeof(int)) == hipSuccess &&
-         hipDeviceSynchronize() == hipSuccess;
-  }
   if (!ok) {
+    const int64_t cols = ws.cols;
     free_workspace(ws);
     set_error("workspace allocation failed (n = " + std::to_string(pl->n) +
-              ", columns = " + std::to_string(static_cast<long long>(tiles) * W) + ")");
+              ", columns = " + std::to_string(static_cast<long long>(cols)) + ")");
     return CPAA_ENOMEM;
   }
-  return CPAA_OK;
+  const cpaa_status s = zero_workspace(ws, pl, false, nullptr);
+  if (s != CPAA_OK) free_workspace(ws);
+  return s;
 }
 
 double series_tail(const cpaa_plan_s* pl, int M) {
@@ -689,8 +728,14 @@ cpaa_status solve_batched(cpaa_plan_t pl, int32_t B, const double* P, int64_t ld
     return CPAA_EINVAL;
   }
   if (pl->num_graphs > 1) {
-    set_error("block-diagonal plans are solved with cpaa_solve_graphs");
-    return CPAA_EINVAL;
+    // a block-diagonal plan: one right-hand side per graph, stacked in one
+    // vector (graph g's entries at its own vertices); reps gets one report per graph
+    if (B != 1 || X0 != nullptr || method != Method::kChebyshev) {
+      set_error("a block-diagonal plan takes B = 1 (one column holding every graph's "
+                "personalization), no X0, CPAA only");
+      return CPAA_EINVAL;
+    }
+    return cpaa_solve_graphs(pl, P, tol, X, reps, stream);
   }
   const int64_t n = pl->n;
   const int64_t n_io = pl->n_caller;
