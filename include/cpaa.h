@@ -260,6 +260,23 @@ CPAA_API cpaa_status cpaa_plan_info_get(cpaa_plan_t plan, cpaa_plan_info* info);
 CPAA_API cpaa_status cpaa_solve(cpaa_plan_t plan, const double* p, double tol, const double* x0,
                        double* x, cpaa_report* rep, void* stream);
 
+/* cpaa_solve for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same solve (Chebyshev series, FP64 residual, corrections, warm start), with
+ * its workspace in a static device array of the library (64 MiB per device,
+ * held until the process ends) instead of buffers the plan allocates, and no
+ * timing events.  Calls on one device share that array and the library's host
+ * mirror of the statistics, so calls that overlap in time on a device race
+ * (run them one after another).  Needs an undirected single-graph plan made on
+ * the current device with io_device = 1 (p, x0, x device pointers), and a
+ * workspace that fits the array (about 40-60 bytes per vertex plus 0.3 MB:
+ * n up to about 1M); otherwise CPAA_EINVAL and nothing is written.  It calls
+ * no hipMalloc, hipFree or other allocating routine; the plan's own device
+ * memory is made by cpaa_plan. */
+CPAA_API cpaa_status cpaa_solve_noalloc(cpaa_plan_t plan, const double* p, double tol,
+                                        const double* x0, double* x, cpaa_report* rep,
+                                        void* stream);
+
 /* B solves at once: column j of P is P[j*ldp + i], i < n, likewise X0 (may be
  * NULL) and X.  The right-hand sides are processed in tiles of opts.tile_w
  * columns by one SpMM kernel per term; each tile stops when all its columns

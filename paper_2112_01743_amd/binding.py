@@ -96,6 +96,8 @@ def lib() -> ctypes.CDLL:
     L.cpaa_plan_info_get.restype = ctypes.c_int
     L.cpaa_solve.argtypes = [vp, vp, dbl, vp, vp, ctypes.POINTER(cpaa_report), vp]
     L.cpaa_solve.restype = ctypes.c_int
+    L.cpaa_solve_noalloc.argtypes = [vp, vp, dbl, vp, vp, ctypes.POINTER(cpaa_report), vp]
+    L.cpaa_solve_noalloc.restype = ctypes.c_int
     L.cpaa_solve_batched.argtypes = [vp, i32, vp, i64, dbl, vp, i64, vp, i64,
                                      ctypes.POINTER(cpaa_report), vp]
     L.cpaa_solve_batched.restype = ctypes.c_int
@@ -181,6 +183,14 @@ def cpaa_solve(plan, p_ptr: int, tol: float, x0_ptr: int | None, x_ptr: int,
                stream: int = 0) -> tuple[int, cpaa_report]:
     rep = cpaa_report()
     st = lib().cpaa_solve(plan, p_ptr, tol, x0_ptr, x_ptr, ctypes.byref(rep), stream or None)
+    return st, rep
+
+
+def cpaa_solve_noalloc(plan, p_ptr: int, tol: float, x0_ptr: int | None, x_ptr: int,
+                       stream: int = 0) -> tuple[int, cpaa_report]:
+    rep = cpaa_report()
+    st = lib().cpaa_solve_noalloc(plan, p_ptr, tol, x0_ptr, x_ptr, ctypes.byref(rep),
+                                  stream or None)
     return st, rep
 
 
@@ -327,6 +337,12 @@ class Plan:
     def solve(self, p, tol: float = 1e-6, x0=None, out=None, stream=None, check=True):
         """p: (n,) float64 HIP tensor.  Returns (x, report dict)."""
         return self._single(cpaa_solve, "cpaa_solve", p, tol, x0, out, stream, check)
+
+    def solve_noalloc(self, p, tol: float = 1e-6, x0=None, out=None, stream=None, check=True):
+        """cpaa_solve_noalloc: the same solve with its workspace in the library's static
+        device array (nothing allocated); arguments and result as solve."""
+        return self._single(cpaa_solve_noalloc, "cpaa_solve_noalloc", p, tol, x0, out, stream,
+                            check)
 
     def solve_power(self, p, tol: float = 1e-6, x0=None, out=None, stream=None, check=True):
         """The power method (x <- cPx + (1-c)p from x = p) on the same plan and kernels;

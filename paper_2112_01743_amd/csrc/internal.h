@@ -230,6 +230,7 @@ struct Workspace {
   int* poll_host = nullptr;      // pinned [2][tiles] stop flags of a series read while it runs
   size_t host_bytes = 0;
   size_t split_elems = 0;        // split-row slots (all tiles)
+  bool external = false;         // buffers owned by someone else (never freed here)
 };
 
 }  // namespace cpaa

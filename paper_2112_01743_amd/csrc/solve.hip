@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "internal.h"
@@ -33,10 +34,12 @@ void free_workspace(Workspace& ws) {
                   ws.slots, ws.stat_slots,
                   ws.stat, ws.done, ws.terms, ws.series_cert, ws.split_f, ws.split_d,
                   ws.split_count, ws.active, ws.plain, ws.col_scale};
-  for (void* p : ptrs)
-    if (p) (void)hipFree(p);
-  if (ws.host) (void)hipHostFree(ws.host);
-  if (ws.poll_host) (void)hipHostFree(ws.poll_host);
+  if (!ws.external) {
+    for (void* p : ptrs)
+      if (p) (void)hipFree(p);
+    if (ws.host) (void)hipHostFree(ws.host);
+    if (ws.poll_host) (void)hipHostFree(ws.poll_host);
+  }
   ws = Workspace();
 }
 
@@ -465,7 +468,8 @@ cpaa_status solve_directed(cpaa_plan_t pl, const double* p, double tol, double* 
                            cpaa_report* rep, void* stream);
 
 cpaa_status solve_single(cpaa_plan_t pl, const double* p, double tol, const double* x0, double* x,
-                         cpaa_report* rep, void* stream, Method method);
+                         cpaa_report* rep, void* stream, Method method,
+                         Workspace* ext = nullptr);
 
 // Batched solves of plans whose options live on the single-vector path only
 // (fp64_recurrence, deterministic): one column after another.
@@ -514,8 +518,10 @@ cpaa_status solve_directed_columns(cpaa_plan_t pl, int32_t B, const double* P, i
   return CPAA_OK;
 }
 
+// ext: a workspace the caller has laid out (the no-allocation entry point);
+// the solve then allocates nothing and records no timing events.
 cpaa_status solve_single(cpaa_plan_t pl, const double* p, double tol, const double* x0, double* x,
-                         cpaa_report* rep, void* stream, Method method) {
+                         cpaa_report* rep, void* stream, Method method, Workspace* ext) {
   set_error("");
   if (pl && pl->directed) {
     // CPAA's expansion needs the real spectrum of an undirected graph, so every
@@ -539,9 +545,9 @@ cpaa_status solve_single(cpaa_plan_t pl, const double* p, double tol, const doub
     return CPAA_EINVAL;
   }
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  cpaa_status s = ensure_workspace(pl, pl->ws1, 1, 1);
+  cpaa_status s = ext ? CPAA_OK : ensure_workspace(pl, pl->ws1, 1, 1);
   if (s != CPAA_OK) return s;
-  Workspace& ws = pl->ws1;
+  Workspace& ws = ext ? *ext : pl->ws1;
   ws.method = method;
   const int n = pl->n;
   const double c = pl->c;
@@ -566,7 +572,7 @@ cpaa_status solve_single(cpaa_plan_t pl, const double* p, double tol, const doub
     dx = static_cast<double*>(tx.p);
   }
 
-  TermTimer timer{pl, pl->opts.time_kernels != 0};
+  TermTimer timer{pl, pl->opts.time_kernels != 0 && ext == nullptr};
   std::vector<int> series_terms;
   cpaa_report R;
   std::memset(&R, 0, sizeof(R));
@@ -610,7 +616,7 @@ cpaa_status solve_single(cpaa_plan_t pl, const double* p, double tol, const doub
     if (!p_checked && (s = check_p_stats(ws, 0)) != CPAA_OK) return s;
     q0 = stat_at(ws, 0, 0, 2);
     b0_l1 = (1.0 - c) * stat_at(ws, 0, 0, 0);
-    if (pl->opts.autotune && !pl->tuned_w1 && pl->maps.size() > 1 && !pl->sliced) {
+    if (pl->opts.autotune && !pl->tuned_w1 && pl->maps.size() > 1 && !pl->sliced && !ext) {
       // autotune the work-item size on this input: time a few terms per candidate
       size_t best = 0;
       float best_ms = 1e30f;
@@ -1077,7 +1083,111 @@ cpaa_status solve_directed(cpaa_plan_t pl, const double* p, double tol, double* 
   return CPAA_OK;
 }
 
+// ---- the no-allocation entry point ----
+// A fixed device array backs the single-vector workspace of cpaa_solve_noalloc.
+// In host code `scratch` names a host-side stand-in, never the device array:
+// its device address (one per device) comes from hipGetSymbolAddress, taken
+// once per device with that device current, and only that address is used.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+// host mirrors of the statistics and stop flags (pageable; calls that overlap race)
+alignas(256) unsigned char g_noalloc_host[1024];
+alignas(64) int g_noalloc_poll[2];
+
+cpaa_status scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxScratchDevices) {
+    set_error("cpaa_solve_noalloc: device index out of range");
+    return CPAA_EDEVICE;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || ptr == nullptr) {
+      (void)hipGetLastError();
+      set_error(std::string("cpaa_solve_noalloc: hipGetSymbolAddress(scratch) failed: ") +
+                hipGetErrorString(e));
+      return CPAA_EDEVICE;
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return CPAA_OK;
+}
+
+cpaa_status solve_noalloc(cpaa_plan_t pl, const double* p, double tol, const double* x0,
+                          double* x, cpaa_report* rep, void* stream) {
+  set_error("");
+  if (!pl || !p || !x) {
+    set_error("cpaa_solve_noalloc: null argument");
+    return CPAA_EINVAL;
+  }
+  if (pl->directed || pl->num_graphs > 1) {
+    set_error("cpaa_solve_noalloc: undirected single-graph plans only");
+    return CPAA_EINVAL;
+  }
+  if (!pl->opts.io_device) {
+    set_error("cpaa_solve_noalloc: p, x0 and x must be device pointers (io_device = 1)");
+    return CPAA_EINVAL;
+  }
+  int dev = -1;
+  CPAA_HIP(hipGetDevice(&dev));
+  if (dev != pl->device) {
+    set_error("cpaa_solve_noalloc: the plan's device must be current");
+    return CPAA_EINVAL;
+  }
+  // the workspace's size first (a counting layout), then the same layout in the array
+  size_t need = 0;
+  {
+    Workspace probe;
+    layout_workspace(pl, probe, 1, 1, [&](void** ptr, size_t bytes) {
+      need = (need + 255) & ~size_t(255);
+      need += bytes ? bytes : 8;
+      *ptr = nullptr;
+      return true;
+    });
+  }
+  if (need > kScratchBytes) {
+    set_error("cpaa_solve_noalloc: this plan needs " + std::to_string(need) +
+              " bytes of workspace, the static array holds " + std::to_string(kScratchBytes) +
+              " (n = " + std::to_string(pl->n) + ")");
+    return CPAA_EINVAL;
+  }
+  if (host_mirror_bytes(1, 1) > sizeof(g_noalloc_host)) {
+    set_error("cpaa_solve_noalloc: host mirror too small");
+    return CPAA_EINVAL;
+  }
+  void* base = nullptr;
+  cpaa_status s = scratch_address(dev, &base);
+  if (s != CPAA_OK) return s;
+  Workspace ws;
+  size_t off = 0;
+  layout_workspace(pl, ws, 1, 1, [&](void** ptr, size_t bytes) {
+    off = (off + 255) & ~size_t(255);
+    *ptr = static_cast<unsigned char*>(base) + off;
+    off += bytes ? bytes : 8;
+    return true;
+  });
+  ws.external = true;
+  ws.host = reinterpret_cast<double*>(g_noalloc_host);
+  ws.host_bytes = host_mirror_bytes(1, 1);
+  ws.poll_host = g_noalloc_poll;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  // the array keeps the last call's contents: clear what must start at zero
+  if ((s = zero_workspace(ws, pl, true, st)) != CPAA_OK) return s;
+  return solve_single(pl, p, tol, x0, x, rep, stream, Method::kChebyshev, &ws);
+}
+
 }  // namespace
+
+extern "C" cpaa_status cpaa_solve_noalloc(cpaa_plan_t pl, const double* p, double tol,
+                                          const double* x0, double* x, cpaa_report* rep,
+                                          void* stream) {
+  return solve_noalloc(pl, p, tol, x0, x, rep, stream);
+}
 
 extern "C" cpaa_status cpaa_solve(cpaa_plan_t pl, const double* p, double tol, const double* x0,
                                   double* x, cpaa_report* rep, void* stream) {
