@@ -44,6 +44,8 @@ TILE_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "term_tile_grid_256_traffic.j
 DIR_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_directed_n4m_traffic.json")
 TILE_KERNEL_SRC = [os.path.join(CSRC, f)
                    for f in ("kernels_tile.hip", "internal.h", "device.h", "api.hip", "solve.hip")]
+GRAPH_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "graphs_batch_10k_traffic.json")
+GRAPH_KERNEL_SRC = [os.path.join(CSRC, f) for f in ("graphs.hip", "internal.h", "device.h")]
 
 
 def log(msg):
@@ -427,7 +429,8 @@ def bench_graph_batch(args):
            "certified": all(r["certified"] for r in reps),
            "roofline": {"bound": "hbm", "achieved": streamed / kernel_s / 1e9,
                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": streamed / kernel_s / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                        "frac": streamed / kernel_s / 1e9 / HBM_PEAK_GBS,
+                        "traffic": load_traffic(g.n, g.nnz, GRAPH_TRAFFIC_FILE, GRAPH_KERNEL_SRC),
                         "kernel": "k_graphs (persistent)",
                         "bytes_per_launch": streamed, "avg_launch_us": kernel_s * 1e6,
                         "model": "pattern streamed once per term and residual pass + p, x, "
