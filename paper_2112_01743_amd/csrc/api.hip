@@ -469,6 +469,7 @@ struct HubHost {
   std::vector<uint8_t> mask;
   std::vector<int32_t> base;
   std::vector<int> chunk_long, long_first, long_nch, long_out;
+  int cfg = 0;   // launch shape (kHubShapes index) the map was built for
 };
 
 // Packed entries, wave items, compact partial indices and long-row chunks of
@@ -1124,6 +1125,7 @@ cpaa_status cpaa_plan(const cpaa_csr* g, double c, const cpaa_opts* opts, cpaa_p
                                                              : kSliceShapeAuto);
     const bool per_item_layout = pl->directed || shape == kHubConfigs + 1;
     if (s == CPAA_OK && !per_item_layout) {
+      hh.cfg = shape - 1;
       fits = build_hub_sliced(n, rp2, ci2, pl->slc.slice_off, hh);
       std::string why;
       if (fits && !check_hub_map(n, pl->slc.slice_off, hh, why)) {
@@ -1179,8 +1181,7 @@ cpaa_status cpaa_plan(const cpaa_csr* g, double c, const cpaa_opts* opts, cpaa_p
     if (s == CPAA_OK) s = dev_upload(&hm.d_long_first, hh.long_first.data(), hh.long_first.size());
     if (s == CPAA_OK) s = dev_upload(&hm.d_long_nch, hh.long_nch.data(), hh.long_nch.size());
     if (s == CPAA_OK) s = dev_upload(&hm.d_long_out, hh.long_out.data(), hh.long_out.size());
-    hm.cfg = (o.slice_shape > 0 ? o.slice_shape
-                                : (pl->deterministic ? kHubDeterministicShape : kSliceShapeAuto)) - 1;
+    hm.cfg = hh.cfg;
     hm.built = s == CPAA_OK;
     std::vector<uint32_t>().swap(hh.entries);
   } else if (s == CPAA_OK && pl->sliced) {
