@@ -546,8 +546,9 @@ def main():
     ap.add_argument("--column-slices", type=int, default=0,
                     help="0 auto (column-sliced on this graph), 1 off, 8 on")
     ap.add_argument("--slice-shape", type=int, default=0,
-                    help="launch shape of the column-sliced gather pass: 0 library default, "
-                         "1-4 a fixed shape")
+                    help="launch shape of the column-sliced gather pass: 0 chosen by the "
+                         "library's autotuner on the first (warm-up) solve, 1-4 a fixed shape, "
+                         "5 the per-item layout")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="chung_lu",
                     choices=["chung_lu", "grid_batched", "graph_batch", "table3", "directed",
@@ -607,7 +608,8 @@ def main():
     t0 = time.perf_counter()
     plan = Plan.from_graph(g, c, time_kernels=1, nnz_per_thread=args.nnz_per_thread,
                            xcd_remap=args.xcd_remap, column_slices=args.column_slices,
-                           slice_shape=args.slice_shape)
+                           slice_shape=args.slice_shape,
+                           autotune=int(args.slice_shape == 0 and args.warmup > 0))
     info = plan.info()
     plan_s = time.perf_counter() - t0
     log(f"plan {info} ({plan_s:.1f} s)")
@@ -617,6 +619,8 @@ def main():
     for _ in range(args.warmup):
         plan.solve(p, args.tol, out=x)
     torch.cuda.synchronize()
+    info = plan.info()   # the launch shape the first (warm-up) solve kept
+    log(f"slice shape in use: {info['slice_shape']}")
     reps = []
     t0 = time.perf_counter()
     for _ in range(args.steps):

@@ -147,11 +147,13 @@ typedef struct {
                              undirected; the other pattern rules are checked as for 1.
                              cpaa_plan_info_get reports which. */
   int32_t slice_shape;    /* column-sliced term of an undirected plan: launch shape of its gather
-                             pass, 0 auto (the default shape; with autotune the first cpaa_solve
-                             times every shape and keeps the fastest), 1-4 a fixed shape:
-                             1 = 8 wavefronts per workgroup and the slice's first 30,720
-                             vertices in LDS, 2 = 16 and 22,528, 3 = 16 and 16,384 (one
-                             workgroup per CU each), 4 = 8 and 8,192 (two per CU). */
+                             pass, 0 auto (shape 1; with autotune the first cpaa_solve times the
+                             shapes 1-4 and keeps the fastest), 1-4 a fixed shape, given as
+                             wavefronts per workgroup / vertices of the slice kept in LDS:
+                             1 = 16 / 16,384, 2 = 8 / 8,192 (two workgroups per CU),
+                             3 = 4 / 2,048, 4 = 16 / 22,528; 5 = the per-item layout (dense
+                             partial sums, the layout of directed plans).  Shapes 1-4 give
+                             identical results; only their speed differs. */
   int32_t fp64_recurrence; /* 1: debug mode, the Chebyshev (and power-method) recurrence in FP64
                              instead of FP32 (the accumulation, residual and certificate are FP64
                              always): results then follow the FP64 oracle's x_M to rounding.
@@ -212,8 +214,8 @@ typedef struct {
   int32_t column_slices;    /* single-vector term: 1 (row order) or 8 (column-sliced) */
   double spectrum_lo;       /* a of the expansion interval [a, 1] (-1: the paper's) */
   int32_t directed;         /* 1 for a directed plan (opts.directed = 1, or 2 and detected) */
-  int32_t slice_shape;      /* launch shape of the column-sliced gather pass in use (1-4), 0 when
-                               the plan has no such pass */
+  int32_t slice_shape;      /* launch shape of the column-sliced gather pass in use (1-4; 5 the
+                               per-item layout), 0 when the plan has no such pass */
   int64_t slice_partials;   /* partial row sums per term of the column-sliced term: rows with an
                                entry in a slice, summed over the 8 slices */
 } cpaa_plan_info;

@@ -1120,9 +1120,7 @@ cpaa_status cpaa_plan(const cpaa_csr* g, double c, const cpaa_opts* opts, cpaa_p
     bool fits = true;
     // the per-item layout (dense partials) serves directed plans and, unless a
     // deterministic plan needs the compact one, the automatic choice
-    const int shape = o.slice_shape > 0 ? o.slice_shape
-                                        : (pl->deterministic ? kHubDeterministicShape
-                                                             : kSliceShapeAuto);
+    const int shape = o.slice_shape > 0 ? o.slice_shape : kSliceShapeAuto;
     const bool per_item_layout = pl->directed || shape == kHubConfigs + 1;
     if (s == CPAA_OK && !per_item_layout) {
       hh.cfg = shape - 1;
@@ -1291,7 +1289,7 @@ cpaa_status cpaa_plan_info_get(cpaa_plan_t pl, cpaa_plan_info* info) {
   info->column_slices = pl->sliced ? kSlices : 1;
   info->spectrum_lo = pl->lam_lo;
   info->directed = pl->directed ? 1 : 0;
-  info->slice_shape = pl->hub.built ? pl->hub.cfg + 1 : 0;
+  info->slice_shape = pl->hub.built ? pl->hub.cfg + 1 : (pl->sliced ? kHubConfigs + 1 : 0);
   info->slice_partials = pl->hub.built ? pl->hub.pofs[kSlices] : 0;
   return CPAA_OK;
 }

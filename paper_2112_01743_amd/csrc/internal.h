@@ -123,10 +123,12 @@ struct HubShape {
   int waves, hub;   // one workgroup per `waves` consecutive wave items of a slice
 };
 constexpr HubShape kHubShapes[kHubConfigs] = {{16, 16384}, {8, 8192}, {4, 2048}, {16, 22528}};
-// slice_shape 1-4 select a shape above, 5 the per-item layout (SlicedMap);
-// automatic choice and the shape of deterministic plans (compact partials)
+// slice_shape 1-kHubConfigs selects a shape above, kHubConfigs + 1 the per-item
+// layout (SlicedMap); 0 takes kSliceShapeAuto, or with autotune the fastest of
+// the shapes above on the first solve.  Every shape sums a row's entries in the
+// same order (the order is fixed by the map, not by the launch), so the shape
+// changes the time of a term, never its result.
 constexpr int kSliceShapeAuto = 1;
-constexpr int kHubDeterministicShape = 3;
 inline int hub_groups_per_slice(int k, int max_items) {
   return (max_items + kHubShapes[k].waves - 1) / kHubShapes[k].waves;
 }
@@ -279,6 +281,7 @@ struct cpaa_plan_s {
   std::vector<cpaa::WorkMap> maps;   // candidates (several when autotuning)
   int max_split_rows = 0;            // over all candidates (workspace sizing)
   bool tuned_w1 = false;
+  bool tuned_hub = false;            // launch shape of the hub-sliced gather pass chosen
   bool tuned_tile = false;
   int xcd_remap = 0;                 // single-vector kernels
   int xcd_remap_tile = 1;            // tiled kernels

@@ -636,6 +636,27 @@ cpaa_status solve_single(cpaa_plan_t pl, const double* p, double tol, const doub
       // restart the series (the probes overwrote z and acc)
       CPAA_HIP(init_w1(pl, ws, dp, 1.0 - c, false, true, true, st));
     }
+    if (pl->opts.autotune && pl->opts.slice_shape == 0 && !pl->tuned_hub && pl->sliced &&
+        pl->hub.built && !ext) {
+      // launch shape of the hub-sliced gather pass: time a few terms with each
+      // (the shape does not change a term's result)
+      int best = pl->hub.cfg;
+      float best_ms = 1e30f;
+      for (int k = 0; k < kHubConfigs; ++k) {
+        pl->hub.cfg = k;
+        hipError_t e = hipSuccess;
+        time_terms(pl, ws, term_w1, 2, st, &e);            // warm-up
+        const float ms = time_terms(pl, ws, term_w1, 4, st, &e);
+        CPAA_HIP(e);
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = k;
+        }
+      }
+      pl->hub.cfg = best;
+      pl->tuned_hub = true;
+      CPAA_HIP(init_w1(pl, ws, dp, 1.0 - c, false, true, true, st));
+    }
   }
 
   const double target_main = 0.5 * tol;

@@ -127,28 +127,21 @@ int main() {
   const cpaa_opts interval = with([](cpaa_opts& o) { o.spectral_interval = 1; });
   const cpaa_opts small_items = with([](cpaa_opts& o) { o.nnz_per_thread = 4; });
   const cpaa_opts tuned = with([](cpaa_opts& o) { o.autotune = 1; });
-  // the smallest hub (2,048 vertices): slices of the larger graphs get tail lists
-  const cpaa_opts small_hub = with([](cpaa_opts& o) {
-    o.column_slices = 8;
-    o.slice_shape = 3;
-  });
 
   const Graph graphs[] = {star(7), star(30000), cycles(9, 14), lattice(40), power_law(20000, 7),
                           from_edges(2, {{0, 1}})};
   const char* names[] = {"star7", "star30000", "two_cycles", "lattice40", "power_law20000", "edge"};
   for (int i = 0; i < 6; ++i) {
     char buf[64];
-    const cpaa_opts* os[] = {&base, &slices, &rcm, &interval, &small_items, &tuned, &small_hub};
-    const char* on[] = {"default",       "column_slices=8",  "locality_order=2",
-                        "spectral_interval=1", "nnz_per_thread=4", "autotune=1",
-                        "column_slices=8 slice_shape=3"};
-    for (int k = 0; k < 7; ++k) {
+    const cpaa_opts* os[] = {&base, &slices, &rcm, &interval, &small_items, &tuned};
+    const char* on[] = {"default", "column_slices=8", "locality_order=2", "spectral_interval=1",
+                        "nnz_per_thread=4", "autotune=1"};
+    for (int k = 0; k < 6; ++k) {
       std::snprintf(buf, sizeof(buf), "%s %s", names[i], on[k]);
 #ifdef CPAA_TEST_SLICE_ENTRY_LIMIT
       // explicitly asked-for column slices whose packed entries pass the cap are
       // refused (int32 offsets of the work items)
-      if ((k == 1 || k == 6) &&
-          static_cast<int64_t>(graphs[i].ci.size()) > CPAA_TEST_SLICE_ENTRY_LIMIT) {
+      if (k == 1 && static_cast<int64_t>(graphs[i].ci.size()) > CPAA_TEST_SLICE_ENTRY_LIMIT) {
         expect(buf, graphs[i], *os[k], false, CPAA_EINVAL);
         if (std::strstr(cpaa_last_error(), "int32 offsets") == nullptr) {
           std::printf("  unexpected message: %s\n", cpaa_last_error());

@@ -145,7 +145,7 @@ def test_work_item_sizes_agree(torch_cuda, npt):
     _assert_parity(g, p, x, rep, 1e-8)
 
 
-@pytest.mark.parametrize("shape", [1, 2, 3, 4])
+@pytest.mark.parametrize("shape", [1, 2, 3, 4, 5])
 @pytest.mark.parametrize("case", ["chung_lu", "grid", "star", "path", "complete", "big_star"])
 def test_column_sliced_term_agrees(torch_cuda, case, shape):
     """Column-sliced term (relabelled vertices, one column slice per XCD, a
@@ -551,6 +551,36 @@ def test_deterministic_solves_are_bitwise_equal(torch_cuda, name, g):
     for j in range(P.shape[0]):
         xj, _ = plan.solve(_dev(torch, P[j]), 1e-9)
         assert np.array_equal(X[j].cpu().numpy(), xj.cpu().numpy())
+
+
+def test_launch_shapes_give_identical_bits_and_autotune_keeps_one(torch_cuda):
+    """The launch shape of the hub-sliced gather pass (workgroup size, LDS hub
+    size) changes a term's time, not its result: with
+    deterministic sums every shape returns the same bits.  autotune = 1 times
+    the shapes on the first solve and keeps one; later solves are unchanged."""
+    from paper_2112_01743_amd import Plan
+    torch = torch_cuda
+    g = gg.chung_lu(300000, 12, 2.1, seed=43, dmax=30000)
+    pd = _dev(torch, gg.source_personalization(g.n, [7])[0])
+    ref = None
+    for shape in range(1, 5):
+        plan = Plan.from_graph(g, C, deterministic=1, slice_shape=shape)
+        assert plan.info()["slice_shape"] == shape
+        x, rep = plan.solve(pd, 1e-9)
+        x = x.cpu().numpy()
+        if ref is None:
+            ref = (x, rep)
+            _assert_parity(g, pd.cpu().numpy(), x, rep, 1e-9)
+        else:
+            assert np.array_equal(x, ref[0]), shape
+            assert rep["cert_bound"] == ref[1]["cert_bound"]
+    plan = Plan.from_graph(g, C, deterministic=1, autotune=1)
+    x1, _ = plan.solve(pd, 1e-9)
+    kept = plan.info()["slice_shape"]
+    assert 1 <= kept <= 4
+    x2, _ = plan.solve(pd, 1e-9)
+    assert plan.info()["slice_shape"] == kept
+    assert np.array_equal(x1.cpu().numpy(), ref[0]) and np.array_equal(x2.cpu().numpy(), ref[0])
 
 
 def _with_isolated(base, n_iso, seed):
