@@ -210,7 +210,7 @@ def bench_grid_batched(args):
     c, B = 0.85, 256
     g = gg.perturbed_grid(1000, 0.05, 0.01, seed=2112002)
     src = gg.random_sources(g.n, B, seed=2112002)
-    plan = Plan.from_graph(g, c, time_kernels=1, tile_w=args.tile_w)
+    plan = Plan.from_graph(g, c, time_kernels=2, tile_w=args.tile_w)
     P = torch.zeros((B, g.n), dtype=torch.float64, device="cuda")
     P[torch.arange(B), torch.as_tensor(src, device="cuda")] = 1.0
     X = torch.empty_like(P)
@@ -268,7 +268,7 @@ def bench_table3(args):
     log(f"graph n={g.n} nnz={g.nnz} ({time.perf_counter() - t0:.1f} s)")
     p = torch.full((g.n,), 1.0 / g.n, dtype=torch.float64, device="cuda")
     x = torch.empty_like(p)
-    plan = Plan.from_graph(g, c, time_kernels=1)
+    plan = Plan.from_graph(g, c, time_kernels=2)
     pi, rep = plan.solve(p, 1e-12)
     pi = pi.clone()
     assert rep["certified"] == 1, rep
@@ -278,7 +278,7 @@ def bench_table3(args):
 
     def rounds(method, lo, hi, **opts):
         for k in range(lo, hi):
-            pk = Plan.from_graph(g, c, k_max=k, max_refine=0, time_kernels=1, **opts)
+            pk = Plan.from_graph(g, c, k_max=k, max_refine=0, time_kernels=2, **opts)
             getattr(pk, method)(p, 1e-15, out=x)
             e = err(x)
             log(f"{method} k={k} ERR={e:.3e}")
@@ -309,7 +309,7 @@ def bench_table3(args):
               "cpaa_interval": dict(rounds=k_i, spectrum_lo=plan_i.info()["spectrum_lo"],
                                     **timed(plan_i, "solve", 1e-15)),
               "power": dict(rounds=k_p, **timed(plan_p, "solve_power", 1e-15))}
-    plan_int = Plan.from_graph(g, c, time_kernels=1, spectral_interval=1)
+    plan_int = Plan.from_graph(g, c, time_kernels=2, spectral_interval=1)
     cert = {"cpaa": timed(plan, "solve", args.tol),
             "cpaa_interval": timed(plan_int, "solve", args.tol),
             "power": timed(plan, "solve_power", args.tol)}
@@ -345,7 +345,7 @@ def bench_directed(args):
     t0 = time.perf_counter()
     g = gg.directed_random(4_000_000, 16, 0.1, seed=2112020)
     log(f"graph n={g.n} nnz={g.nnz} ({time.perf_counter() - t0:.1f} s)")
-    plan = Plan.from_graph(g, c, directed=1, time_kernels=1,
+    plan = Plan.from_graph(g, c, directed=1, time_kernels=2,
                            column_slices=args.column_slices)
     info = plan.info()
     p = torch.full((g.n,), 1.0 / g.n, dtype=torch.float64, device="cuda")
@@ -452,7 +452,7 @@ def bench_config0(args):
     c = 0.85
     g = gg.erdos_renyi(10_000, 10, seed=2112000)
     k = mass_rule_terms(c, 1e-10)
-    plan = Plan.from_graph(g, c, time_kernels=1)
+    plan = Plan.from_graph(g, c, time_kernels=2)
     p = torch.full((g.n,), 1.0 / g.n, dtype=torch.float64, device="cuda")
     x = torch.empty_like(p)
     for _ in range(args.warmup):
@@ -606,7 +606,7 @@ def main():
     log(f"graph n={g.n} nnz={g.nnz} maxdeg={int(np.diff(g.row_ptr).max())} "
         f"({time.perf_counter() - t0:.1f} s)")
     t0 = time.perf_counter()
-    plan = Plan.from_graph(g, c, time_kernels=1, nnz_per_thread=args.nnz_per_thread,
+    plan = Plan.from_graph(g, c, time_kernels=2, nnz_per_thread=args.nnz_per_thread,
                            xcd_remap=args.xcd_remap, column_slices=args.column_slices,
                            slice_shape=args.slice_shape,
                            autotune=int(args.slice_shape == 0 and args.warmup > 0))

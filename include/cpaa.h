@@ -94,13 +94,19 @@ typedef struct {
   int32_t tile_w;         /* 0 auto; 8, 16, 32 or 64: right-hand sides per tile in batched solves */
   int32_t validate;       /* 1 (default): check the pattern (symmetry, loops, order) on the host */
   int32_t io_device;      /* 1 (default): p / x0 / x of solve calls are device pointers; 0: host */
-  int32_t time_kernels;   /* 1: time every term kernel with HIP events (report.ms_terms) */
+  int32_t time_kernels;   /* device time of the term kernels with HIP events (report.ms_terms):
+                             1 one pair of events around every term launch, 2 one pair around
+                             each series of back-to-back term launches (the convergence checks
+                             between them included).  An event between two launches leaves the
+                             GPU idle for about 10 us, so 1 slows a solve down; 2 does not. */
   int32_t xcd_remap;      /* -1 auto (off for single-vector kernels, on for tiled kernels),
                              0/1: map workgroups to contiguous row ranges per XCD */
   int32_t autotune;       /* 1: the first call of each solve path times its candidate launch
                              shapes on its own input and keeps the fastest for the plan:
                              cpaa_solve (plain solve): work maps of 8/16/32 entries per thread
-                             (when nnz_per_thread = 0); cpaa_solve_batched: tile_w 16/32/64
+                             (when nnz_per_thread = 0) in row order, or the launch shape of the
+                             column-sliced gather pass (when slice_shape = 0);
+                             cpaa_solve_batched: tile_w 16/32/64
                              (when tile_w = 0); cpaa_solve_graphs: 256/512/1024 threads per
                              graph */
   int32_t column_slices;  /* single-vector path: 0 auto, 1 off, 8 on.  On: vertices are relabelled
@@ -190,8 +196,8 @@ typedef struct {
   double mass;            /* sum_i x_i */
   double series_cert;     /* in-loop bound of the last series (from its last two terms) */
   double ms_total;        /* device time of the whole call (events on `stream`) */
-  double ms_terms;        /* device time inside term kernels (time_kernels = 1), whole call */
-  int64_t term_launches;  /* term kernels timed in ms_terms */
+  double ms_terms;        /* device time of the term launches (time_kernels = 1 or 2), whole call */
+  int64_t term_launches;  /* term launches that did work within ms_terms */
   int64_t edges;          /* nnz x terms (main + correction) processed for this right-hand side */
 } cpaa_report;
 

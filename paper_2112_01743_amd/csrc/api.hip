@@ -830,6 +830,10 @@ cpaa_status cpaa_plan(const cpaa_csr* g, double c, const cpaa_opts* opts, cpaa_p
     set_error("spectral_interval must be 0 or 1");
     return CPAA_EINVAL;
   }
+  if (o.time_kernels < 0 || o.time_kernels > 2) {
+    set_error("time_kernels must be 0, 1 or 2");
+    return CPAA_EINVAL;
+  }
   if (o.spectral_interval == 1 && g->num_graphs > 1) {
     set_error("spectral_interval needs a single-graph plan");
     return CPAA_EINVAL;

@@ -238,43 +238,66 @@ int series_first_check(const cpaa_plan_s* pl, const Workspace& ws, double target
 
 namespace {
 
+// Device time of term launches, from HIP events on the solve's stream.
+// mode 1: one pair of events around every term launch (each event adds about
+// 10 us of idle time between launches on this device); mode 2: one pair around
+// each series of back-to-back term launches, whose time includes what little
+// idle time lies between its kernels.
 struct TermTimer {
   cpaa_plan_s* pl;
-  bool on;
+  int mode;   // 0 off, 1 per term, 2 per series
   struct Rec {
     int ev;          // index of the first event of the pair
     int series;
-    int term;        // index of the term this launch produces
+    int term;        // index of the (first) term the bracketed launches produce
+    int last;        // index of the last one
   };
   std::vector<Rec> recs;
   int used = 0;
-  hipError_t before(int series, int term, hipStream_t st) {
-    if (!on) return hipSuccess;
+  bool open = false;   // mode 2: a series bracket is open
+  hipError_t new_pair(int series, int term, hipStream_t st) {
     while ((int)pl->ev_terms.size() < used + 2) {
       hipEvent_t e;
       hipError_t err = hipEventCreate(&e);
       if (err != hipSuccess) return err;
       pl->ev_terms.push_back(e);
     }
-    recs.push_back({used, series, term});
+    recs.push_back({used, series, term, term});
     hipError_t err = hipEventRecord(pl->ev_terms[used], st);
     used += 2;
     return err;
   }
+  hipError_t before(int series, int term, hipStream_t st) {
+    if (mode == 0) return hipSuccess;
+    if (mode == 2 && open) {
+      recs.back().last = term;
+      return hipSuccess;
+    }
+    open = mode == 2;
+    return new_pair(series, term, st);
+  }
   hipError_t after(hipStream_t st) {
-    if (!on) return hipSuccess;
+    if (mode != 1) return hipSuccess;
     return hipEventRecord(pl->ev_terms[recs.back().ev + 1], st);
   }
-  // sum of durations of the launches that did work (term <= terms run by their series)
+  hipError_t end_series(hipStream_t st) {
+    if (mode != 2 || !open) return hipSuccess;
+    open = false;
+    return hipEventRecord(pl->ev_terms[recs.back().ev + 1], st);
+  }
+  // device time of the launches that did work (term <= terms run by their
+  // series) and their number; mode 2 brackets hold whole series, whose
+  // launches past the stop return at once
   void total(const std::vector<int>& series_terms, double* ms, int64_t* launches) {
     *ms = 0.0;
     *launches = 0;
     for (const Rec& r : recs) {
-      if (r.term > series_terms[r.series]) continue;
+      const int worked = std::min(r.last, series_terms[r.series]) - r.term + 1;
+      if (worked <= 0) continue;
       float t = 0.f;
       if (hipEventElapsedTime(&t, pl->ev_terms[r.ev], pl->ev_terms[r.ev + 1]) == hipSuccess) {
         *ms += t;
-        ++*launches;
+        *launches += worked;
       }
     }
   }
@@ -362,6 +385,7 @@ cpaa_status run_series(cpaa_plan_s* pl, Workspace& ws, TermFn term, int series_i
       ++chunk;
     }
   }
+  CPAA_HIP(timer.end_series(st));
   return CPAA_OK;
 }
 
@@ -572,7 +596,7 @@ cpaa_status solve_single(cpaa_plan_t pl, const double* p, double tol, const doub
     dx = static_cast<double*>(tx.p);
   }
 
-  TermTimer timer{pl, pl->opts.time_kernels != 0 && ext == nullptr};
+  TermTimer timer{pl, ext == nullptr ? pl->opts.time_kernels : 0};
   std::vector<int> series_terms;
   cpaa_report R;
   std::memset(&R, 0, sizeof(R));
@@ -831,7 +855,7 @@ cpaa_status solve_batched(cpaa_plan_t pl, int32_t B, const double* P, int64_t ld
     lp = lx0 = lx = n;
   }
 
-  TermTimer timer{pl, pl->opts.time_kernels != 0};
+  TermTimer timer{pl, pl->opts.time_kernels};
   std::vector<int> series_terms;
   std::vector<int> terms_main(T, 0), refine_terms(T, 0), refinements(T, 0);
   std::vector<int> fallback(cols, 0);
@@ -1034,7 +1058,7 @@ cpaa_status solve_directed(cpaa_plan_t pl, const double* p, double tol, double* 
     dp = static_cast<const double*>(tp.p);
     dx = static_cast<double*>(tx.p);
   }
-  TermTimer timer{pl, pl->opts.time_kernels != 0};
+  TermTimer timer{pl, pl->opts.time_kernels};
   std::vector<int> series_terms;
   cpaa_report R;
   std::memset(&R, 0, sizeof(R));

@@ -417,12 +417,20 @@ def test_repeated_solves_reuse_plan(torch_cuda):
     assert np.abs(outs[0] - outs[1]).sum() < 1e-7 and np.abs(outs[1] - outs[2]).sum() < 1e-7
 
 
-def test_kernel_timing_report(torch_cuda):
+@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("slices", [1, 8])
+def test_kernel_timing_report(torch_cuda, mode, slices):
+    """time_kernels = 1 (events around every term launch) and 2 (around each
+    series): both count every term launch that did work, and the series
+    brackets hold the per-term ones' launches, so their total is no larger
+    than the solve's."""
     g = gg.chung_lu(100000, 16, 2.1, seed=45, dmax=30000)
-    x, rep, _ = _solve(torch_cuda, g, gg.uniform_personalization(g.n), 1e-6, time_kernels=1)
+    p = gg.uniform_personalization(g.n)
+    x, rep, _ = _solve(torch_cuda, g, p, 1e-6, time_kernels=mode, column_slices=slices)
     assert rep["term_launches"] == rep["terms"] + rep["refine_terms"]
     assert rep["ms_terms"] > 0 and rep["ms_total"] >= rep["ms_terms"]
     assert rep["edges"] == g.nnz * (rep["terms"] + rep["refine_terms"])
+    _assert_parity(g, p, x, rep, 1e-6)
 
 
 def test_independent_plans_on_two_streams(torch_cuda):
