@@ -110,16 +110,18 @@ def kernel_hash(src=KERNEL_SRC) -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(n, nnz, path: str = TRAFFIC_FILE, src=KERNEL_SRC):
+def load_traffic(n, nnz, path: str = TRAFFIC_FILE, src=KERNEL_SRC, shape=None):
     """Measured HBM bytes per term (all of its launches) from the committed
     counter runs, if they were taken on the current kernel source and the same
-    workload."""
+    workload (and, where the file lists launch shapes, on the shape in use)."""
     try:
         t = json.load(open(path))
     except (OSError, ValueError):
         return None
     if t.get("kernel_sha") != kernel_hash(src) or t.get("n") != n or t.get("nnz") != nnz:
         return None
+    if "bytes_per_launch_by_shape" in t:
+        return t["bytes_per_launch_by_shape"].get(str(shape))
     return t.get("bytes_per_launch")
 
 
@@ -644,7 +646,7 @@ def main():
                                series_acc_frac(reps[-1]["term_launches"], reps[-1]["terms"], c,
                                                args.tol))
     achieved = alg_bytes / avg_launch_s / 1e9
-    traffic = load_traffic(g.n, g.nnz)
+    traffic = load_traffic(g.n, g.nnz, shape=info["slice_shape"])
     out = {
         "metric": METRIC,
         "value": gteps if certified else None,

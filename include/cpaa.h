@@ -278,9 +278,11 @@ CPAA_API cpaa_status cpaa_solve(cpaa_plan_t plan, const double* p, double tol, c
  * (run them one after another).  Needs an undirected single-graph plan made on
  * the current device with io_device = 1 (p, x0, x device pointers), and a
  * workspace that fits the array (about 40-60 bytes per vertex plus 0.3 MB:
- * n up to about 1M); otherwise CPAA_EINVAL and nothing is written.  It calls
- * no hipMalloc, hipFree or other allocating routine; the plan's own device
- * memory is made by cpaa_plan. */
+ * n up to about 1M); otherwise CPAA_EINVAL and nothing is written.  The FP64
+ * residual of a column-sliced plan runs as in cpaa_solve (per column slice)
+ * when its partial sums fit the array too, else in row order (the same value
+ * up to rounding).  It calls no hipMalloc, hipFree or other allocating
+ * routine; the plan's own device memory is made by cpaa_plan. */
 CPAA_API cpaa_status cpaa_solve_noalloc(cpaa_plan_t plan, const double* p, double tol,
                                         const double* x0, double* x, cpaa_report* rep,
                                         void* stream);

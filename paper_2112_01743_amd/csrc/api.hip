@@ -742,7 +742,7 @@ void cpaa_plan_destroy(cpaa_plan_t pl) {
   {
     HubMap& hm = pl->hub;
     void* hp[] = {hm.d_entries, hm.d_items, hm.d_mask, hm.d_base, hm.d_chunk_long,
-                  hm.d_long_first, hm.d_long_nch, hm.d_long_out};
+                  hm.d_long_first, hm.d_long_nch, hm.d_long_out, hm.d_wround};
     for (void* p : hp)
       if (p) (void)hipFree(p);
   }
@@ -1175,6 +1175,8 @@ cpaa_status cpaa_plan(const cpaa_csr* g, double c, const cpaa_opts* opts, cpaa_p
       max_items = std::max(max_items, hh.item_off[sl + 1] - hh.item_off[sl]);
     for (int k = 0; k < kHubConfigs; ++k)
       hm.groups[k] = std::max(1, hub_groups_per_slice(k, max_items));
+    hm.groups_resid =
+        std::max(1, (max_items + kHubResidShape.waves - 1) / kHubResidShape.waves);
     s = dev_upload(&hm.d_entries, hh.entries.data(), hh.entries.size());
     if (s == CPAA_OK) s = dev_upload(&hm.d_items, hh.items.data(), hh.items.size());
     if (s == CPAA_OK) s = dev_upload(&hm.d_mask, hh.mask.data(), hh.mask.size());
@@ -1183,6 +1185,16 @@ cpaa_status cpaa_plan(const cpaa_csr* g, double c, const cpaa_opts* opts, cpaa_p
     if (s == CPAA_OK) s = dev_upload(&hm.d_long_first, hh.long_first.data(), hh.long_first.size());
     if (s == CPAA_OK) s = dev_upload(&hm.d_long_nch, hh.long_nch.data(), hh.long_nch.size());
     if (s == CPAA_OK) s = dev_upload(&hm.d_long_out, hh.long_out.data(), hh.long_out.size());
+    if (s == CPAA_OK) {
+      // rounding weights of the residual: sum over the neighbours u of v of (d_u + 3)
+      std::vector<double> wr(n);
+      parallel_for(n, [&](int64_t v) {
+        int64_t w = 0;
+        for (int32_t j = rp2[v]; j < rp2[v + 1]; ++j) w += rp2[ci2[j] + 1] - rp2[ci2[j]] + 3;
+        wr[v] = static_cast<double>(w);
+      });
+      s = dev_upload(&hm.d_wround, wr.data(), wr.size());
+    }
     hm.cfg = hh.cfg;
     hm.built = s == CPAA_OK;
     std::vector<uint32_t>().swap(hh.entries);

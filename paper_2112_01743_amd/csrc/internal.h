@@ -129,6 +129,9 @@ constexpr HubShape kHubShapes[kHubConfigs] = {{16, 16384}, {8, 8192}, {4, 2048},
 // same order (the order is fixed by the map, not by the launch), so the shape
 // changes the time of a term, never its result.
 constexpr int kSliceShapeAuto = 1;
+// The FP64 residual's gather pass on the same map: doubles in LDS, so a
+// smaller hub per workgroup (16 B per LDS row sum and 8 B per hub vertex)
+constexpr HubShape kHubResidShape = {8, 8192};
 inline int hub_groups_per_slice(int k, int max_items) {
   return (max_items + kHubShapes[k].waves - 1) / kHubShapes[k].waves;
 }
@@ -157,6 +160,10 @@ struct HubMap {
   uint8_t* d_mask = nullptr;           // [n] bit s: row present in slice s
   int* d_base = nullptr;               // [ceil(n / 64)][kSlices]
   int groups[kHubConfigs] = {};        // workgroups per slice of each launch shape
+  int groups_resid = 0;                // workgroups per slice of kHubResidShape
+  // [n] sum over the neighbours u of v of (d_u + 3): the weight of |acc_v| in the
+  // residual's rounding bound, which the hub-sliced residual adds per vertex
+  double* d_wround = nullptr;
   int cfg = 0;                         // launch shape in use
   int n_long = 0;                      // rows cut into chunks
   int n_chunks = 0;
@@ -214,6 +221,8 @@ struct Workspace {
   int det_max_chunks = 0;
   double* det_defer = nullptr;   // deterministic plans: [split rows][3] (sum, sum of |.|, row)
   float* chunk_val = nullptr;    // hub-sliced term: [n_chunks] sums of long-row chunks
+  double* part64 = nullptr;      // hub-sliced plans: compact FP64 partial sums of the residual
+  double* chunk64 = nullptr;     // hub-sliced plans: [n_chunks] FP64 long-row chunk sums
   int* long_cnt = nullptr;       // hub-sliced term: [n_long] chunk arrivals
   double* dang = nullptr;        // directed plans: [5][kSlots] dangling mass of the increment
                                  // in z[0..2], then of x and |x| for the residual

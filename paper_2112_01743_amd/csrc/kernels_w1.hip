@@ -476,13 +476,14 @@ __global__ __launch_bounds__(kWG) void k_combine_w1(CombineArgs a) {
 // present row is written once, in LDS, and then copied out coalesced.
 // Pass 2 (k_combine_hub) adds a row's partials in slice order and runs the
 // term epilogue.
-struct HubArgs {
+template <typename V>
+struct HubArgsT {
   const uint32_t* entries;
   const HubItem* items;
-  const float* zc;
-  float* part;             // [pofs[kSlices]]
+  const V* zc;             // the vector gathered (z_k; acc for the FP64 residual)
+  V* part;                 // [pofs[kSlices]]
   const int* done;
-  float* chunk_val;
+  V* chunk_val;
   int* long_cnt;
   const int* chunk_long;
   const int* long_first;
@@ -492,6 +493,8 @@ struct HubArgs {
   int slice_off[kSlices + 1];
   int pofs[kSlices + 1];
 };
+using HubArgs = HubArgsT<float>;
+
 
 // ordering of LDS accesses between the lanes of one wavefront
 __device__ __forceinline__ void wave_lds_sync() {
@@ -500,20 +503,21 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int WAVES, int HUB>
-__global__ __launch_bounds__(WAVES * 64) void k_term_hub(HubArgs a) {
+template <int WAVES, int HUB, typename V = float>
+__global__ __launch_bounds__(WAVES * 64) void k_term_hub(HubArgsT<V> a) {
   if (a.done != nullptr && *a.done) return;
-  __shared__ float hub[HUB];
-  __shared__ float rsum[WAVES][kHubRowsPad];
+  static_assert((WAVES * kHubRowsPad + HUB) * sizeof(V) <= 160 * 1024, "LDS of one workgroup");
+  __shared__ V hub[HUB];
+  __shared__ V rsum[WAVES][kHubRowsPad];
   const int sl = blockIdx.x % kSlices;
   const int grp = blockIdx.x / kSlices;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int nk = a.item_off[sl + 1] - a.item_off[sl];
   if (grp * WAVES >= nk) return;   // past the slice's last item (whole workgroup)
   const int lo = a.slice_off[sl];
-  const float* __restrict__ xs = a.zc + lo;
+  const V* __restrict__ xs = a.zc + lo;
   const int nh = min(HUB, a.slice_off[sl + 1] - lo);
-  {
+  if constexpr (sizeof(V) == 4) {
     // 16-byte loads for the 16-byte-aligned body of the hub, scalar head and tail
     const int head = min(nh, (4 - (lo & 3)) & 3);
     const int body = (nh - head) & ~3;
@@ -527,11 +531,13 @@ __global__ __launch_bounds__(WAVES * 64) void k_term_hub(HubArgs a) {
       hub[head + 4 * c + 3] = v.w;
     }
     for (int c = head + body + threadIdx.x; c < nh; c += WAVES * 64) hub[c] = xs[c];
+  } else {
+    for (int c = threadIdx.x; c < nh; c += WAVES * 64) hub[c] = xs[c];
   }
   __syncthreads();
   const HubItem* __restrict__ items = a.items + a.item_off[sl];
-  float* __restrict__ part = a.part + a.pofs[sl];
-  float* rs = rsum[wv];
+  V* __restrict__ part = a.part + a.pofs[sl];
+  V* rs = rsum[wv];
   constexpr uint32_t kNone = kSliceNone;
   constexpr uint32_t row_mask = (1u << kHubRowBits) - 1u;
   const int k = grp * WAVES + wv;
@@ -539,7 +545,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_term_hub(HubArgs a) {
     const HubItem it = items[k];
     if (it.rows < 0) {
       // chunk of a long row: plain local columns, one wavefront sum
-      float sum = 0.f;
+      V sum = 0;
 #pragma unroll
       for (int i = 0; i < kHubNpt; ++i) {
         const int j = lane + i * 64;
@@ -561,9 +567,9 @@ __global__ __launch_bounds__(WAVES * 64) void k_term_hub(HubArgs a) {
         if (prev == a.long_nch[lr] - 1) {
           atomics_done();
           const int f = a.long_first[lr], nc = a.long_nch[lr];
-          float tot = 0.f;
+          V tot = 0;
           for (int q = 0; q < nc; ++q)
-            tot += __hip_atomic_exchange(&a.chunk_val[f + q], 0.f, __ATOMIC_RELAXED,
+            tot += __hip_atomic_exchange(&a.chunk_val[f + q], V(0), __ATOMIC_RELAXED,
                                          __HIP_MEMORY_SCOPE_AGENT);
           __hip_atomic_exchange(&a.long_cnt[lr], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           a.part[a.long_out[lr]] = tot;
@@ -595,11 +601,11 @@ __global__ __launch_bounds__(WAVES * 64) void k_term_hub(HubArgs a) {
 #pragma unroll
     for (int i = 1; i < kHubNpt; ++i)
       if (i < rl && ((e[i] ^ e[i - 1]) & row_mask) != 0) starts |= 1u << i;
-    float v[kHubNpt];
+    V v[kHubNpt];
 #pragma unroll
     for (int i = 0; i < kHubNpt; ++i) {
       const uint32_t c = e[i] >> kHubRowBits;
-      float h = 0.f, g = 0.f;
+      V h = 0, g = 0;
       if (i < rl && c < static_cast<uint32_t>(HUB)) h = hub[c];
       if (i < rl && c >= static_cast<uint32_t>(HUB)) g = xs[c];
       v[i] = h + g;
@@ -609,7 +615,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_term_hub(HubArgs a) {
     // finished row is stored; the first row's store is overwritten below with
     // its complete sum by this same lane.  (v[i] = 0 past the run.)
     int row = fr;
-    float fs = 0.f, cur = v[0];
+    V fs = 0, cur = v[0];
 #pragma unroll
     for (int i = 1; i < kHubNpt; ++i) {
       const bool st = (starts >> i) & 1u;
@@ -619,21 +625,21 @@ __global__ __launch_bounds__(WAVES * 64) void k_term_hub(HubArgs a) {
       cur = st ? v[i] : cur + v[i];
     }
     const int lr = row;
-    const float ls = cur;
+    const V ls = cur;
     if (fr == lr) fs = ls;
     // segmented inclusive scan of the last-row sums over the lanes (rows
     // ascend with the lane, so equal keys are contiguous); empty lanes get
     // keys of their own
     const int key = rl > 0 ? lr : -2 - lane;
-    float S = rl > 0 ? ls : 0.f;
+    V S = rl > 0 ? ls : V(0);
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
-      const float So = __shfl_up(S, off);
+      const V So = __shfl_up(S, off);
       const int ko = __shfl_up(key, off);
       if (lane >= off && ko == key) S = So + S;
     }
     const int key_prev = __shfl_up(key, 1);
-    const float S_prev = __shfl_up(S, 1);
+    const V S_prev = __shfl_up(S, 1);
     const int fr_next = __shfl_down(rl > 0 ? fr : -1, 1);
     if (rl > 0) {
       if (fr != lr) rs[fr + (fr >> 5)] = (lane > 0 && key_prev == fr) ? S_prev + fs : fs;
@@ -811,6 +817,103 @@ __global__ __launch_bounds__(kWG) void k_resid_w1(ResidArgs a) {
     atomic_add(&o[2], s_q);
     atomic_add(&o[3], s_mass);
     atomic_add(&o[4], s_round);
+    if (s_bad != 0.0) atomic_add(&o[5], s_bad);
+  }
+}
+
+// FP64 residual of hub-sliced plans, pass 2 (pass 1 is k_term_hub<..., double>
+// on acc, leaving each row's partial sums of acc over its neighbours per
+// slice): r = b - d a + c s per row with s the partials added in slice order,
+// and the statistics of k_resid_w1.  The rounding bound is the same sum,
+// regrouped: sum_u (d_u + 3) u (|b_u| + d_u |a_u| + c sum_{v in N(u)} |a_v|)
+// = sum_u (d_u + 3) u (|b_u| + d_u |a_u|) + c u sum_v |a_v| w_v, with the
+// plan's w_v = sum_{u in N(v)} (d_u + 3), so no sum of |a_v| is gathered.
+struct ResidHubArgs {
+  const int* rp;
+  const uint8_t* mask;
+  const int* base;        // [ceil(n/64)][kSlices]
+  const double* part;
+  int pofs[kSlices];
+  const double* acc;
+  const double* b;
+  const double* wround;
+  double* r;
+  double c;
+  double* stat_slots;     // [kSlots][1][kStat]
+  double* det_part;       // deterministic plans: per-block statistics, else null
+  int* det_count;
+  int n;
+};
+
+__global__ __launch_bounds__(kWG) void k_resid_hub(ResidHubArgs a) {
+  constexpr double u53 = 0x1p-53;
+  double f_abs = 0.0, f_max = 0.0, f_q = 0.0, f_mass = 0.0, f_round = 0.0, f_bad = 0.0;
+  const int lane = threadIdx.x & 63;
+  const uint64_t below = (uint64_t(1) << lane) - 1;
+  const int blk = __builtin_amdgcn_readfirstlane(static_cast<int>(
+      blockIdx.x * (kWG / 64) + (threadIdx.x >> 6)));
+  const int u = blk * 64 + lane;
+  if (blk * 64 < a.n) {
+    const bool in = u < a.n;
+    const int d = in ? a.rp[u + 1] - a.rp[u] : 1;
+    const double acc = in ? a.acc[u] : 0.0;
+    const double bb = in ? a.b[u] : 0.0;
+    const double w = in ? a.wround[u] : 0.0;
+    const uint32_t m = in ? a.mask[u] : 0u;
+    const int* __restrict__ bs = a.base + static_cast<size_t>(blk) * kSlices;
+    int idx[kSlices];
+#pragma unroll
+    for (int sl = 0; sl < kSlices; ++sl) {
+      const bool bit = (m >> sl) & 1u;
+      idx[sl] = bit ? a.pofs[sl] + bs[sl] + __popcll(__ballot(bit) & below) : -1;
+    }
+    double pv[kSlices];
+#pragma unroll
+    for (int sl = 0; sl < kSlices; ++sl) pv[sl] = idx[sl] >= 0 ? a.part[idx[sl]] : 0.0;
+    double s = 0.0;
+#pragma unroll
+    for (int sl = 0; sl < kSlices; ++sl)
+      if (idx[sl] >= 0) s += pv[sl];
+    if (in) {
+      const double dd = static_cast<double>(d);
+      const double res = bb - dd * acc + a.c * s;
+      a.r[u] = res;
+      const double ar = fabs(res);
+      if (!isfinite(res)) f_bad += 1.0;
+      f_abs += ar;
+      f_max = fmax(f_max, ar);
+      f_q += res * res / dd;
+      f_mass += dd * acc;
+      f_round += (dd + 3.0) * u53 * (fabs(bb) + dd * fabs(acc)) + a.c * u53 * fabs(acc) * w;
+    }
+  }
+  double sums[4] = {block_sum256(f_abs), block_sum256(f_q), block_sum256(f_mass),
+                    block_sum256(f_round)};
+  const double s_max = block_max256(f_max);
+  const double s_bad = block_sum256(f_bad);
+  if (a.det_part != nullptr) {
+    // deterministic plans: real-valued sums in block order; the maximum and the
+    // count of non-finite rows are exact in any order
+    if (threadIdx.x == 0) {
+      atomic_max_nonneg(&a.stat_slots[1], s_max);
+      if (s_bad != 0.0) atomic_add(&a.stat_slots[5], s_bad);
+    }
+    if (ordered_block_sum<4>(sums, blockIdx.x, gridDim.x, a.det_part, a.det_count) &&
+        threadIdx.x == 0) {
+      atomic_add(&a.stat_slots[0], sums[0]);
+      atomic_add(&a.stat_slots[2], sums[1]);
+      atomic_add(&a.stat_slots[3], sums[2]);
+      atomic_add(&a.stat_slots[4], sums[3]);
+    }
+    return;
+  }
+  if (threadIdx.x == 0) {
+    double* o = a.stat_slots + (size_t)(blockIdx.x % kSlots) * kStat;
+    atomic_add(&o[0], sums[0]);
+    atomic_max_nonneg(&o[1], s_max);
+    atomic_add(&o[2], sums[1]);
+    atomic_add(&o[3], sums[2]);
+    atomic_add(&o[4], sums[3]);
     if (s_bad != 0.0) atomic_add(&o[5], s_bad);
   }
 }
@@ -1287,17 +1390,18 @@ void sliced_pass(const cpaa_plan_s* pl, Workspace& ws, int cur, const int* done,
 
 // Pass 1 of a hub-sliced term with launch shape cfg: partial sums of z_cur
 // into ws.part.
-void hub_pass(const cpaa_plan_s* pl, Workspace& ws, int cur, const int* done, int cfg,
-              hipStream_t st) {
+template <typename V>
+HubArgsT<V> hub_args(const cpaa_plan_s* pl, const V* x, V* part, V* chunk_val, int* long_cnt,
+                     const int* done) {
   const HubMap& hm = pl->hub;
-  HubArgs h;
+  HubArgsT<V> h;
   h.entries = hm.d_entries;
   h.items = hm.d_items;
-  h.zc = ws.z[cur];
-  h.part = ws.part;
+  h.zc = x;
+  h.part = part;
   h.done = done;
-  h.chunk_val = ws.chunk_val;
-  h.long_cnt = ws.long_cnt;
+  h.chunk_val = chunk_val;
+  h.long_cnt = long_cnt;
   h.chunk_long = hm.d_chunk_long;
   h.long_first = hm.d_long_first;
   h.long_nch = hm.d_long_nch;
@@ -1307,7 +1411,13 @@ void hub_pass(const cpaa_plan_s* pl, Workspace& ws, int cur, const int* done, in
     h.slice_off[i] = pl->slc.slice_off[i];
     h.pofs[i] = hm.pofs[i];
   }
-  const dim3 grid(kSlices * hm.groups[cfg]);
+  return h;
+}
+
+void hub_pass(const cpaa_plan_s* pl, Workspace& ws, int cur, const int* done, int cfg,
+              hipStream_t st) {
+  const HubArgs h = hub_args<float>(pl, ws.z[cur], ws.part, ws.chunk_val, ws.long_cnt, done);
+  const dim3 grid(kSlices * pl->hub.groups[cfg]);
 #define CPAA_HUB_LAUNCH(K)                                                            \
   hipLaunchKernelGGL((k_term_hub<kHubShapes[K].waves, kHubShapes[K].hub>), grid,      \
                      dim3(kHubShapes[K].waves * 64), 0, st, h)
@@ -1431,6 +1541,32 @@ hipError_t term_w1(const cpaa_plan_s* pl, Workspace& ws, int cur, int prev, int 
 }
 
 hipError_t residual_w1(const cpaa_plan_s* pl, Workspace& ws, hipStream_t st) {
+  if (pl->sliced && pl->hub.built && ws.part64 != nullptr) {
+    // hub-sliced plans: FP64 partial sums of acc per slice on the term's map,
+    // then the residual and its statistics per row
+    const HubArgsT<double> h =
+        hub_args<double>(pl, ws.acc, ws.part64, ws.chunk64, ws.long_cnt, nullptr);
+    hipLaunchKernelGGL((k_term_hub<kHubResidShape.waves, kHubResidShape.hub, double>),
+                       dim3(kSlices * pl->hub.groups_resid), dim3(kHubResidShape.waves * 64), 0,
+                       st, h);
+    ResidHubArgs r;
+    r.rp = pl->d_rp_w1;
+    r.mask = pl->hub.d_mask;
+    r.base = pl->hub.d_base;
+    r.part = ws.part64;
+    for (int i = 0; i < kSlices; ++i) r.pofs[i] = pl->hub.pofs[i];
+    r.acc = ws.acc;
+    r.b = ws.b;
+    r.wround = pl->hub.d_wround;
+    r.r = ws.r;
+    r.c = pl->c;
+    r.stat_slots = ws.stat_slots + (size_t)kSlots * ws.cols * kStat;   // residual phase
+    r.det_part = pl->deterministic ? ws.det_part : nullptr;
+    r.det_count = ws.det_count;
+    r.n = pl->n;
+    hipLaunchKernelGGL(k_resid_hub, dim3((pl->n + kWG - 1) / kWG), dim3(kWG), 0, st, r);
+    return hipGetLastError();
+  }
   ResidArgs a;
   a.rp = pl->d_rp_w1;
   a.ci = pl->d_ci_w1;

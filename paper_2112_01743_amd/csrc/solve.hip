@@ -28,6 +28,7 @@ namespace cpaa {
 
 void free_workspace(Workspace& ws) {
   void* ptrs[] = {ws.z[0], ws.z[1], ws.z[2], ws.acc, ws.part, ws.chunk_val, ws.long_cnt,
+                  ws.part64, ws.chunk64,
                   ws.det_part, ws.det_count, ws.det_chunk, ws.det_defer,
                   ws.dang, ws.wdir, ws.part_d,
                   ws.b, ws.r,
@@ -52,9 +53,12 @@ static size_t host_mirror_bytes(int64_t cols, int tiles) {
 
 // Device buffers of a workspace for W right-hand sides per tile, each taken
 // from `alloc(void** p, size_t bytes)` (which returns false when it cannot);
-// ws.W, ws.tiles, ws.cols and ws.vec_elems are set here.
+// ws.W, ws.tiles, ws.cols and ws.vec_elems are set here.  Without `resid64`
+// the FP64 partials of the hub-sliced residual are left out (the residual then
+// runs in row order).
 template <typename Alloc>
-bool layout_workspace(const cpaa_plan_s* pl, Workspace& ws, int W, int tiles, Alloc alloc) {
+bool layout_workspace(const cpaa_plan_s* pl, Workspace& ws, int W, int tiles, Alloc alloc,
+                      bool resid64 = true) {
   ws.W = W;
   ws.tiles = tiles;
   ws.cols = static_cast<int64_t>(tiles) * W;
@@ -72,6 +76,10 @@ bool layout_workspace(const cpaa_plan_s* pl, Workspace& ws, int W, int tiles, Al
     ok = ok && alloc((void**)&ws.part, (size_t)pl->hub.pofs[kSlices] * sizeof(float));
     ok = ok && alloc((void**)&ws.chunk_val, (size_t)pl->hub.n_chunks * sizeof(float));
     ok = ok && alloc((void**)&ws.long_cnt, (size_t)pl->hub.n_long * sizeof(int));
+    if (resid64) {
+      ok = ok && alloc((void**)&ws.part64, (size_t)pl->hub.pofs[kSlices] * sizeof(double));
+      ok = ok && alloc((void**)&ws.chunk64, (size_t)pl->hub.n_chunks * sizeof(double));
+    }
   } else if (W == 1 && pl->sliced) {
     ok = ok && alloc((void**)&ws.part, (size_t)kSlices * pl->n * sizeof(float));
   }
@@ -127,6 +135,7 @@ static cpaa_status zero_workspace(Workspace& ws, const cpaa_plan_s* pl, bool asy
     if (ws.chunk_val)
       CPAA_HIP(fill_i32(reinterpret_cast<int*>(ws.chunk_val), 0, (size_t)pl->hub.n_chunks, st));
     if (ws.long_cnt) CPAA_HIP(fill_i32(ws.long_cnt, 0, (size_t)pl->hub.n_long, st));
+    if (ws.chunk64) CPAA_HIP(fill_f64(ws.chunk64, 0.0, (size_t)pl->hub.n_chunks, st));
     if (ws.det_count) CPAA_HIP(fill_i32(ws.det_count, 0, 1, st));
     return CPAA_OK;
   }
@@ -138,6 +147,9 @@ static cpaa_status zero_workspace(Workspace& ws, const cpaa_plan_s* pl, bool asy
          hipSuccess;
   if (ok && ws.long_cnt)
     ok = hipMemset(ws.long_cnt, 0, (size_t)std::max(pl->hub.n_long, 1) * sizeof(int)) ==
+         hipSuccess;
+  if (ok && ws.chunk64)
+    ok = hipMemset(ws.chunk64, 0, (size_t)std::max(pl->hub.n_chunks, 1) * sizeof(double)) ==
          hipSuccess;
   if (ok && ws.det_count) ok = hipMemset(ws.det_count, 0, sizeof(int)) == hipSuccess;
   if (ok) ok = hipDeviceSynchronize() == hipSuccess;
@@ -1184,16 +1196,29 @@ cpaa_status solve_noalloc(cpaa_plan_t pl, const double* p, double tol, const dou
     set_error("cpaa_solve_noalloc: the plan's device must be current");
     return CPAA_EINVAL;
   }
-  // the workspace's size first (a counting layout), then the same layout in the array
-  size_t need = 0;
-  {
+  // the workspace's size first (a counting layout), then the same layout in the
+  // array; the FP64 partials of the hub-sliced residual are included when they
+  // fit (the residual of the allocating entry point, so deterministic plans
+  // return the same bits from both), else the residual runs in row order
+  auto count = [&](bool resid64) {
+    size_t need = 0;
     Workspace probe;
-    layout_workspace(pl, probe, 1, 1, [&](void** ptr, size_t bytes) {
-      need = (need + 255) & ~size_t(255);
-      need += bytes ? bytes : 8;
-      *ptr = nullptr;
-      return true;
-    });
+    layout_workspace(
+        pl, probe, 1, 1,
+        [&](void** ptr, size_t bytes) {
+          need = (need + 255) & ~size_t(255);
+          need += bytes ? bytes : 8;
+          *ptr = nullptr;
+          return true;
+        },
+        resid64);
+    return need;
+  };
+  bool resid64 = true;
+  size_t need = count(true);
+  if (need > kScratchBytes) {
+    resid64 = false;
+    need = count(false);
   }
   if (need > kScratchBytes) {
     set_error("cpaa_solve_noalloc: this plan needs " + std::to_string(need) +
@@ -1210,12 +1235,15 @@ cpaa_status solve_noalloc(cpaa_plan_t pl, const double* p, double tol, const dou
   if (s != CPAA_OK) return s;
   Workspace ws;
   size_t off = 0;
-  layout_workspace(pl, ws, 1, 1, [&](void** ptr, size_t bytes) {
-    off = (off + 255) & ~size_t(255);
-    *ptr = static_cast<unsigned char*>(base) + off;
-    off += bytes ? bytes : 8;
-    return true;
-  });
+  layout_workspace(
+      pl, ws, 1, 1,
+      [&](void** ptr, size_t bytes) {
+        off = (off + 255) & ~size_t(255);
+        *ptr = static_cast<unsigned char*>(base) + off;
+        off += bytes ? bytes : 8;
+        return true;
+      },
+      resid64);
   ws.external = true;
   ws.host = reinterpret_cast<double*>(g_noalloc_host);
   ws.host_bytes = host_mirror_bytes(1, 1);

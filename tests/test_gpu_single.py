@@ -591,6 +591,46 @@ def test_launch_shapes_give_identical_bits_and_autotune_keeps_one(torch_cuda):
     assert np.array_equal(x1.cpu().numpy(), ref[0]) and np.array_equal(x2.cpu().numpy(), ref[0])
 
 
+def _host_residual_l1(g, p, x):
+    """||(1-c) p - (I - cP) x||_1 in FP64 on the host, P x = A D^-1 x."""
+    deg = np.diff(g.row_ptr).astype(np.float64)
+    y = x / deg
+    rows = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    ay = np.bincount(rows, weights=y[g.col_idx], minlength=g.n)
+    return np.abs((1 - C) * p - x + C * ay).sum()
+
+
+@pytest.mark.parametrize("deterministic", [0, 1])
+def test_sliced_fp64_residual_matches_row_order_and_host(torch_cuda, deterministic):
+    """The FP64 residual of hub-sliced plans (partial sums of acc per column
+    slice on the term's map, long rows in chunks, then r = b - (I - cP) x per
+    row) against the row-order residual of the same plan (the static-workspace
+    entry point keeps it) and against r recomputed on the host; with a capped
+    series the residual also drives the correction series."""
+    from paper_2112_01743_amd import Plan
+    torch = torch_cuda
+    g = gg.chung_lu(300000, 12, 2.1, seed=47, dmax=30000)
+    for p in (gg.uniform_personalization(g.n), gg.source_personalization(g.n, [5])[0]):
+        pd = _dev(torch, p)
+        for opts in ({}, {"k_max": 10, "max_refine": 6}):
+            plan = Plan.from_graph(g, C, column_slices=8, deterministic=deterministic, **opts)
+            x1, r1 = plan.solve(pd, 1e-9)
+            x2, r2 = plan.solve_noalloc(pd, 1e-9)
+            a, b = x1.cpu().numpy(), x2.cpu().numpy()
+            host = _host_residual_l1(g, p, a)
+            _note(f"resid sliced {r1['resid_l1']:.6e} row-order {r2['resid_l1']:.6e} "
+                  f"host {host:.6e} refinements {r1['refinements']}")
+            assert abs(r1["resid_l1"] - host) <= 1e-6 * host + 1e-15
+            if opts:
+                assert r1["refinements"] >= 1
+            if r1["refinements"] == r2["refinements"] == 0:
+                assert np.array_equal(a, b)
+                assert abs(r1["resid_l1"] - r2["resid_l1"]) <= 1e-9 * host + 1e-16
+            else:
+                assert np.abs(a - b).sum() <= 1e-12
+            _assert_parity(g, p, a, r1, 1e-9)
+
+
 def _with_isolated(base, n_iso, seed):
     """base plus n_iso edgeless vertices at random labels; returns (graph, kept labels)."""
     n = base.n + n_iso
