@@ -130,8 +130,10 @@ constexpr HubShape kHubShapes[kHubConfigs] = {{16, 16384}, {8, 8192}, {4, 2048},
 // changes the time of a term, never its result.
 constexpr int kSliceShapeAuto = 1;
 // The FP64 residual's gather pass on the same map: doubles in LDS, so a
-// smaller hub per workgroup (16 B per LDS row sum and 8 B per hub vertex)
-constexpr HubShape kHubResidShape = {8, 8192};
+// smaller hub per workgroup.  Measured on the 4M-vertex power-law graph:
+// 16 / 2,048 299 us, 8 / 4,096 305 us, 16 / 1,024 310 us, 8 / 8,192 320 us,
+// 4 / 14,336 622 us.
+constexpr HubShape kHubResidShape = {16, 2048};
 inline int hub_groups_per_slice(int k, int max_items) {
   return (max_items + kHubShapes[k].waves - 1) / kHubShapes[k].waves;
 }
@@ -386,7 +388,11 @@ hipError_t term_w1(const cpaa_plan_s* pl, Workspace& ws, int cur, int prev, int 
                    hipStream_t st);
 hipError_t check_series(const cpaa_plan_s* pl, Workspace& ws, const double* cert_slot,
                         double scale, double target, int term_index, hipStream_t st);
-hipError_t residual_w1(const cpaa_plan_s* pl, Workspace& ws, hipStream_t st);
+// r = b - (I - cP) x for x = D acc, with its statistics; where the residual's
+// pass can (hub-sliced plans) it also writes x (non-null) at the caller's
+// labels and sets *wrote_x
+hipError_t residual_w1(const cpaa_plan_s* pl, Workspace& ws, hipStream_t st,
+                       double* x = nullptr, bool* wrote_x = nullptr);
 hipError_t finalize_w1(const cpaa_plan_s* pl, Workspace& ws, double* x, double scale,
                        hipStream_t st);
 // Dropped (edgeless) vertices of a drop_isolated plan: their share of the

@@ -824,7 +824,8 @@ __global__ __launch_bounds__(kWG) void k_resid_w1(ResidArgs a) {
 // FP64 residual of hub-sliced plans, pass 2 (pass 1 is k_term_hub<..., double>
 // on acc, leaving each row's partial sums of acc over its neighbours per
 // slice): r = b - d a + c s per row with s the partials added in slice order,
-// and the statistics of k_resid_w1.  The rounding bound is the same sum,
+// and the statistics of k_resid_w1; optionally also x = D acc, the result as
+// it stands (what the finalize kernel would write with scale 1).  The rounding bound is the same sum,
 // regrouped: sum_u (d_u + 3) u (|b_u| + d_u |a_u| + c sum_{v in N(u)} |a_v|)
 // = sum_u (d_u + 3) u (|b_u| + d_u |a_u|) + c u sum_v |a_v| w_v, with the
 // plan's w_v = sum_{u in N(v)} (d_u + 3), so no sum of |a_v| is gathered.
@@ -838,6 +839,8 @@ struct ResidHubArgs {
   const double* b;
   const double* wround;
   double* r;
+  const int* perm;        // caller's label of each row
+  double* x;              // x = D acc written at the caller's labels, or null
   double c;
   double* stat_slots;     // [kSlots][1][kStat]
   double* det_part;       // deterministic plans: per-block statistics, else null
@@ -878,6 +881,7 @@ __global__ __launch_bounds__(kWG) void k_resid_hub(ResidHubArgs a) {
       const double dd = static_cast<double>(d);
       const double res = bb - dd * acc + a.c * s;
       a.r[u] = res;
+      if (a.x != nullptr) a.x[a.perm[u]] = dd * acc;
       const double ar = fabs(res);
       if (!isfinite(res)) f_bad += 1.0;
       f_abs += ar;
@@ -1540,7 +1544,9 @@ hipError_t term_w1(const cpaa_plan_s* pl, Workspace& ws, int cur, int prev, int 
   return hipGetLastError();
 }
 
-hipError_t residual_w1(const cpaa_plan_s* pl, Workspace& ws, hipStream_t st) {
+hipError_t residual_w1(const cpaa_plan_s* pl, Workspace& ws, hipStream_t st, double* x,
+                       bool* wrote_x) {
+  if (wrote_x != nullptr) *wrote_x = false;
   if (pl->sliced && pl->hub.built && ws.part64 != nullptr) {
     // hub-sliced plans: FP64 partial sums of acc per slice on the term's map,
     // then the residual and its statistics per row
@@ -1559,6 +1565,9 @@ hipError_t residual_w1(const cpaa_plan_s* pl, Workspace& ws, hipStream_t st) {
     r.b = ws.b;
     r.wround = pl->hub.d_wround;
     r.r = ws.r;
+    r.perm = pl->d_perm;
+    r.x = pl->d_perm != nullptr ? x : nullptr;
+    if (wrote_x != nullptr) *wrote_x = r.x != nullptr;
     r.c = pl->c;
     r.stat_slots = ws.stat_slots + (size_t)kSlots * ws.cols * kStat;   // residual phase
     r.det_part = pl->deterministic ? ws.det_part : nullptr;

@@ -706,10 +706,12 @@ cpaa_status solve_single(cpaa_plan_t pl, const double* p, double tol, const doub
   series_terms.push_back(k_cap);
 
   double bound = 0.0;
+  // without normalize the last residual pass can write the result itself
+  bool x_written = false;
   for (;;) {
     CPAA_HIP(fill_f64(ws.stat_slots + (size_t)kSlots * ws.cols * kStat, 0.0,
                       (size_t)kSlots * ws.cols * kStat, st));
-    CPAA_HIP(residual_w1(pl, ws, st));
+    CPAA_HIP(residual_w1(pl, ws, st, pl->opts.normalize ? nullptr : dx, &x_written));
     if ((s = read_back(ws, st)) != CPAA_OK) return s;
     HostView hv = host_view(ws);
     const int ran = hv.done[0] ? hv.terms[0] : series_terms.back();
@@ -740,7 +742,7 @@ cpaa_status solve_single(cpaa_plan_t pl, const double* p, double tol, const doub
   R.cert_bound = bound;
   R.certified = (bound <= tol) ? 1 : 0;
   const double scale = pl->opts.normalize ? 1.0 / R.mass : 1.0;
-  CPAA_HIP(finalize_w1(pl, ws, dx, scale, st));
+  if (!x_written) CPAA_HIP(finalize_w1(pl, ws, dx, scale, st));
   CPAA_HIP(dropped_out(pl, dp, (1.0 - c) * scale, dx, st));
   CPAA_HIP(hipEventRecord(pl->ev_end, st));
   if (!pl->opts.io_device)
