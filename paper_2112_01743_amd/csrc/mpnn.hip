@@ -12,9 +12,11 @@
 // nearest even); every product accumulates in FP32.  The dense layers of
 // width 64 run on MFMA (v_mfma_f32_16x16x16bf16_1k); layer 0 (two input
 // features) and the head use plain FMA.  The backward pass is FP32 (it uses
-// the bf16-rounded weights, as the forward did), gradients accumulate over
-// the sources of a step in FP32, and Adam updates FP32 master weights from
-// which the bf16 copies are re-derived.
+// the bf16-rounded weights, as the forward did); its weight gradients and
+// input gradients of the width-64 layers run on FP32 MFMA
+// (v_mfma_f32_16x16x4f32).  Gradients accumulate over the sources of a step
+// in FP32, and Adam updates FP32 master weights from which the bf16 copies
+// are re-derived.
 //
 // Layouts (row-major): H, M: n x 64 bf16 (128 B per vertex, one cache line
 // per neighbour gather); H^0, M^0: n x 2 bf16; gradients n x 64 FP32.
@@ -428,55 +430,112 @@ __global__ __launch_bounds__(kWG) void k_dz(int n, const uint16_t* __restrict__ 
   }
 }
 
-// dW_self += X^T dZ, dW_nbr += M^T dZ, db += colsum dZ for 64-wide inputs.
-// Each workgroup takes `chunk` rows; thread t owns W rows k = t/4, columns
-// 16*(t%4)..+15 of both matrices; tiles of 32 rows staged in LDS.
-__global__ __launch_bounds__(kWG) void k_wgrad64(int n, const uint16_t* __restrict__ x,
-                                                 const uint16_t* __restrict__ m,
-                                                 const float* __restrict__ dz,
-                                                 float* __restrict__ grad, int o_ws, int o_wn,
-                                                 int o_b, int chunk) {
-  __shared__ float sx[32][kHid + 1];
-  __shared__ float sm[32][kHid + 1];
-  __shared__ float sz[32][kHid + 1];
-  const int t = threadIdx.x;
-  const int k = t >> 2, j0 = (t & 3) * 16;
-  float as[16], an[16];
+// dW_self += X^T dZ, dW_nbr += M^T dZ, db += colsum dZ for 64-wide inputs, on
+// MFMA (v_mfma_f32_16x16x4f32: FP32 operands, FP32 accumulation, so the
+// backward pass keeps its FP32 precision).  Per group of 4
+// rows, lane l takes row r0 + l/16 and features 4(l%16)..+3 of X, M and dZ (8,
+// 8 and 16 contiguous bytes); tile (t, u) of the 64 x 64 result then holds
+// W[4m + t][4c + u] at lane (c = l%16, m = 4(l/16) + i, accumulator i).  Each
+// wavefront sums its rows into registers; the workgroup adds its wavefronts'
+// sums in LDS in wavefront order and writes one partial [W_self | W_nbr | b]
+// (kWgradPart floats) to `part`; k_wgrad_reduce adds the partials in a fixed
+// order (no atomics: the same bits on every run).
+constexpr int kWgradPart = 2 * kHid * kHid + kHid;
+constexpr int kWgradBlocks = 256;   // workgroups of the MFMA weight-gradient pass (at most)
+__global__ __launch_bounds__(kWG) void k_wgrad64_mfma(int n, const uint16_t* __restrict__ x,
+                                                      const uint16_t* __restrict__ m,
+                                                      const float* __restrict__ dz,
+                                                      float* __restrict__ part) {
+  const int lane = threadIdx.x & 63;
+  const int wave = (blockIdx.x * kWG + threadIdx.x) >> 6;
+  const int nwaves = (gridDim.x * kWG) >> 6;
+  const int rl = lane >> 4, c = lane & 15;
+  floatx4 as[4][4], an[4][4];
 #pragma unroll
-  for (int q = 0; q < 16; ++q) as[q] = an[q] = 0.f;
-  float ab = 0.f;
-  const int r_begin = blockIdx.x * chunk;
-  const int r_end = min(n, r_begin + chunk);
-  for (int base = r_begin; base < r_end; base += 32) {
-    __syncthreads();
-    for (int i = t; i < 32 * kHid; i += kWG) {
-      const int rr = i / kHid, c = i % kHid;
-      const int r = base + rr;
-      const bool ok = r < r_end;
-      sx[rr][c] = ok ? bf2f(x[(size_t)r * kHid + c]) : 0.f;
-      sm[rr][c] = ok ? bf2f(m[(size_t)r * kHid + c]) : 0.f;
-      sz[rr][c] = ok ? dz[(size_t)r * kHid + c] : 0.f;
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) as[t][u] = an[t][u] = floatx4{0.f, 0.f, 0.f, 0.f};
+  float bs[4] = {0.f, 0.f, 0.f, 0.f};
+  for (int g = wave; g * 4 < n; g += nwaves) {
+    const int r = g * 4 + rl;
+    uint2 xr = make_uint2(0u, 0u), mr = make_uint2(0u, 0u);
+    float4 zr = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (r < n) {
+      xr = *reinterpret_cast<const uint2*>(x + (size_t)r * kHid + 4 * c);
+      mr = *reinterpret_cast<const uint2*>(m + (size_t)r * kHid + 4 * c);
+      zr = *reinterpret_cast<const float4*>(dz + (size_t)r * kHid + 4 * c);
     }
-    __syncthreads();
-#pragma unroll 4
-    for (int rr = 0; rr < 32; ++rr) {
-      const float xv = sx[rr][k], mv = sm[rr][k];
+    const float xv[4] = {__uint_as_float(xr.x << 16), __uint_as_float(xr.x & 0xffff0000u),
+                         __uint_as_float(xr.y << 16), __uint_as_float(xr.y & 0xffff0000u)};
+    const float mv[4] = {__uint_as_float(mr.x << 16), __uint_as_float(mr.x & 0xffff0000u),
+                         __uint_as_float(mr.y << 16), __uint_as_float(mr.y & 0xffff0000u)};
+    const float zv[4] = {zr.x, zr.y, zr.z, zr.w};
 #pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const float zv = sz[rr][j0 + q];
-        as[q] += xv * zv;
-        an[q] += mv * zv;
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        as[t][u] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv[t], zv[u], as[t][u], 0, 0, 0);
+        an[t][u] = __builtin_amdgcn_mfma_f32_16x16x4f32(mv[t], zv[u], an[t][u], 0, 0, 0);
       }
-    }
-    if (t < kHid)
-      for (int rr = 0; rr < 32; ++rr) ab += sz[rr][t];
-  }
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    atomicAdd(&grad[o_ws + k * kHid + j0 + q], as[q]);
-    atomicAdd(&grad[o_wn + k * kHid + j0 + q], an[q]);
+    for (int u = 0; u < 4; ++u) bs[u] += zv[u];
   }
-  if (t < kHid) atomicAdd(&grad[o_b + t], ab);
+  // bias: the column sums of this lane's rows, then over the four row lanes
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    bs[u] += __shfl_xor(bs[u], 16);
+    bs[u] += __shfl_xor(bs[u], 32);
+  }
+  __shared__ float red[kWgradPart];
+  const int w_in = threadIdx.x >> 6;
+  for (int w = 0; w < kWG / 64; ++w) {
+    if (w_in == w) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int e = (4 * (4 * rl + i) + t) * kHid + 4 * c + u;
+            red[e] = (w == 0 ? 0.f : red[e]) + as[t][u][i];
+            red[kHid * kHid + e] = (w == 0 ? 0.f : red[kHid * kHid + e]) + an[t][u][i];
+          }
+      if (rl == 0)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int e = 2 * kHid * kHid + 4 * c + u;
+          red[e] = (w == 0 ? 0.f : red[e]) + bs[u];
+        }
+    }
+    __syncthreads();
+  }
+  float* __restrict__ out = part + (size_t)blockIdx.x * kWgradPart;
+  for (int e = threadIdx.x; e < kWgradPart; e += kWG) out[e] = red[e];
+}
+
+// grad[W_self | W_nbr | b] += the sum of the workgroup partials: each block
+// takes 64 entries, its four wavefronts sum four fixed ranges of partials in
+// order, and the four range sums are added in order
+__global__ __launch_bounds__(kWG) void k_wgrad_reduce(int parts, const float* __restrict__ part,
+                                                      float* __restrict__ grad, int o_ws,
+                                                      int o_wn, int o_b) {
+  __shared__ float seg[kWG / 64][64];
+  const int e = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int w = threadIdx.x >> 6;
+  const int per = (parts + kWG / 64 - 1) / (kWG / 64);
+  float s = 0.f;
+  if (e < kWgradPart)
+    for (int q = w * per; q < min(parts, (w + 1) * per); ++q) s += part[(size_t)q * kWgradPart + e];
+  seg[w][threadIdx.x & 63] = s;
+  __syncthreads();
+  if (threadIdx.x < 64 && e < kWgradPart) {
+    float t = seg[0][threadIdx.x];
+    for (int q = 1; q < kWG / 64; ++q) t += seg[q][threadIdx.x];
+    const int dst = e < kHid * kHid ? o_ws + e
+                    : e < 2 * kHid * kHid ? o_wn + (e - kHid * kHid)
+                                          : o_b + (e - 2 * kHid * kHid);
+    grad[dst] += t;
+  }
 }
 
 // same for the 2-wide input layer
@@ -505,11 +564,16 @@ __global__ __launch_bounds__(kWG) void k_wgrad2(int n, const uint16_t* __restric
   atomicAdd(&grad[o.b[0] + lane], bb);
 }
 
-// dHd = dZ W_self^T, dM = dZ W_nbr^T (bf16-rounded weights): wavefront per vertex
-__global__ __launch_bounds__(kWG) void k_dh(int n, const float* __restrict__ dz,
-                                            const float* __restrict__ wr, int o_ws, int o_wn,
-                                            float* __restrict__ dhd, float* __restrict__ dm) {
-  __shared__ float ws[kHid][kHid + 1];   // ws[k][j]
+// dHd = dZ W_self^T, dM = dZ W_nbr^T (bf16-rounded weights) on MFMA
+// (v_mfma_f32_16x16x4f32): each
+// wavefront takes 16 rows; K step s covers columns j = 16 kk + s of dZ (kk =
+// l/16: lane l reads its row's 16 contiguous floats 16 kk..+15), B[kk][o] =
+// W[o][16 kk + s] from LDS.  Lane l receives dH[r0 + 4(l/16) + i][16 t + l%16].
+__global__ __launch_bounds__(kWG) void k_dh_mfma(int n, const float* __restrict__ dz,
+                                                 const float* __restrict__ wr, int o_ws,
+                                                 int o_wn, float* __restrict__ dhd,
+                                                 float* __restrict__ dm) {
+  __shared__ float ws[kHid][kHid + 1];   // ws[o][j] = W_self[o][j]
   __shared__ float wn[kHid][kHid + 1];
   for (int i = threadIdx.x; i < kHid * kHid; i += kWG) {
     ws[i / kHid][i % kHid] = wr[o_ws + i];
@@ -519,17 +583,46 @@ __global__ __launch_bounds__(kWG) void k_dh(int n, const float* __restrict__ dz,
   const int lane = threadIdx.x & 63;
   const int wave = (blockIdx.x * kWG + threadIdx.x) >> 6;
   const int nwaves = (gridDim.x * kWG) >> 6;
-  for (int u = wave; u < n; u += nwaves) {
-    const float mine = dz[(size_t)u * kHid + lane];
-    float a = 0.f, b = 0.f;
-#pragma unroll 8
-    for (int j = 0; j < kHid; ++j) {
-      const float zj = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mine), j));
-      a += zj * ws[lane][j];
-      b += zj * wn[lane][j];
+  const int kk = lane >> 4, c = lane & 15;
+  for (int r0 = wave * 16; r0 < n; r0 += nwaves * 16) {
+    const int r = r0 + c;
+    float a[16];
+    if (r < n) {
+      const float4* src = reinterpret_cast<const float4*>(dz + (size_t)r * kHid + 16 * kk);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float4 v = src[q];
+        a[4 * q] = v.x;
+        a[4 * q + 1] = v.y;
+        a[4 * q + 2] = v.z;
+        a[4 * q + 3] = v.w;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) a[q] = 0.f;
     }
-    dhd[(size_t)u * kHid + lane] = a;
-    dm[(size_t)u * kHid + lane] = b;
+    floatx4 hs[4], hn[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) hs[t] = hn[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int sidx = 0; sidx < 16; ++sidx) {
+      const int j = 16 * kk + sidx;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        hs[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[sidx], ws[16 * t + c][j], hs[t], 0, 0, 0);
+        hn[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[sidx], wn[16 * t + c][j], hn[t], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int rr = r0 + 4 * kk + i;
+        if (rr < n) {
+          dhd[(size_t)rr * kHid + 16 * t + c] = hs[t][i];
+          dm[(size_t)rr * kHid + 16 * t + c] = hn[t][i];
+        }
+      }
   }
 }
 
@@ -585,6 +678,7 @@ struct cpaa_model_s {
   double* hred = nullptr;    // pinned [3]
   float* part = nullptr;     // [long-row slots][64] partial sums of split rows
   int* count = nullptr;      // [long-row slots] chunk arrivals
+  float* wpart = nullptr;    // [kWgradBlocks][kWgradPart] weight-gradient partials
 };
 
 static void model_free(cpaa_model_s* md) {
@@ -592,7 +686,7 @@ static void model_free(cpaa_model_s* md) {
   void* ptrs[] = {md->params, md->grads, md->adam_m, md->adam_v, md->wr, md->wt[0], md->wt[1],
                   md->wt[2], md->invd, md->h0, md->m0, md->h[0], md->h[1], md->h[2], md->h[3],
                   md->m[0], md->m[1], md->m[2], md->m[3], md->s, md->y, md->gs, md->dz, md->dh,
-                  md->dm, md->red, md->x0tmp, md->part, md->count};
+                  md->dm, md->red, md->x0tmp, md->part, md->count, md->wpart};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (md->hred) (void)hipHostFree(md->hred);
@@ -655,12 +749,15 @@ static hipError_t backward(cpaa_model_s* md, const double* x0, const double* pi,
     hipLaunchKernelGGL(k_dz, dim3(gw), dim3(kWG), 0, st, n, md->h[l], md->gs, md->wr, md->o,
                        l == L - 1 ? nullptr : md->dh, md->dz);
     if (l >= 1) {
-      const int chunk = 1024;   // ~1000 workgroups at n = 1M
-      hipLaunchKernelGGL(k_wgrad64, dim3((n + chunk - 1) / chunk), dim3(kWG), 0, st, n,
-                         md->h[l - 1], md->m[l - 1], md->dz, md->grads, md->o.w_self[l],
-                         md->o.w_nbr[l], md->o.b[l], chunk);
-      hipLaunchKernelGGL(k_dh, dim3(gw), dim3(kWG), 0, st, n, md->dz, md->wr, md->o.w_self[l],
-                         md->o.w_nbr[l], md->dh, md->dm);
+      // workgroups of 4 wavefronts, 16 rows per wavefront group step
+      const int wg_blocks = std::max(1, std::min(kWgradBlocks, (n + 1023) / 1024));
+      hipLaunchKernelGGL(k_wgrad64_mfma, dim3(wg_blocks), dim3(kWG), 0, st, n, md->h[l - 1],
+                         md->m[l - 1], md->dz, md->wpart);
+      hipLaunchKernelGGL(k_wgrad_reduce, dim3((kWgradPart + 63) / 64), dim3(kWG), 0, st,
+                         wg_blocks, md->wpart, md->grads, md->o.w_self[l], md->o.w_nbr[l],
+                         md->o.b[l]);
+      hipLaunchKernelGGL(k_dh_mfma, dim3(grid_rows(n, 64)), dim3(kWG), 0, st, n, md->dz, md->wr,
+                         md->o.w_self[l], md->o.w_nbr[l], md->dh, md->dm);
       hipLaunchKernelGGL(k_agg64<true>, dim3((pl->n_titems + 3) / 4), dim3(kWG), 0, st,
                          pl->d_titems, pl->n_titems, pl->d_row_ptr, pl->d_col_idx, md->invd,
                          (const void*)md->dm, (void*)md->dh, md->part, md->count,
@@ -731,6 +828,7 @@ cpaa_status cpaa_model_create(cpaa_plan_t pl, int32_t layers, int32_t hidden, co
   const size_t nslots = std::max(pl->n_tsplit_rows, 1);
   A((void**)&md->part, nslots * kHid * 4);
   A((void**)&md->count, nslots * 4);
+  A((void**)&md->wpart, (size_t)kWgradBlocks * kWgradPart * 4);
   if (ok && hipHostMalloc((void**)&md->hred, 4 * 8, hipHostMallocDefault) != hipSuccess) {
     (void)hipGetLastError();
     ok = false;
