@@ -249,7 +249,14 @@ def bench_grid_batched(args):
                         "unit": "GB/s", "frac": alg / avg / 1e9 / HBM_PEAK_GBS,
                         "traffic": load_traffic(g.n, g.nnz, TILE_TRAFFIC_FILE, TILE_KERNEL_SRC),
                         "kernel": f"k_term_tile<{W}>", "bytes_per_launch": alg,
-                        "avg_launch_us": avg * 1e6}}
+                        "avg_launch_us": avg * 1e6,
+                        "model": "grouped accumulator updates (the bytes this schedule needs)",
+                        # the per-term model that charges the FP64 accumulator's read and
+                        # write to every launch (28 bytes per vertex and column)
+                        "bytes_per_launch_every_term": tile_term_bytes(g.n, g.nnz, tiles,
+                                                                       tiles * W),
+                        "frac_every_term": tile_term_bytes(g.n, g.nnz, tiles, tiles * W)
+                        / avg / 1e9 / HBM_PEAK_GBS}}
     print(json.dumps(out), flush=True)
 
 
