@@ -98,6 +98,9 @@ struct SlicedMap {
 // cut into chunk items (plain local columns); the last chunk to finish adds
 // the chunk sums in chunk order.
 constexpr int kHubNpt = 32;                  // entries per lane of a wave item
+// the gather kernel keeps a lane's row starts in one 32-bit mask, and the run
+// layout loads four entries at a time
+static_assert(kHubNpt <= 32 && kHubNpt % 4 == 0, "entries per lane of a wave item");
 constexpr int kHubItemCap = 64 * kHubNpt;    // entries per wave item
 constexpr int kHubRowBits = 11;              // packed row field (j - j0 < kHubRows)
 constexpr int kHubRows = 1024;               // present rows per wave item (LDS row sums)
