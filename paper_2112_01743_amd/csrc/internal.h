@@ -134,9 +134,10 @@ constexpr HubShape kHubShapes[kHubConfigs] = {{16, 16384}, {8, 8192}, {4, 2048},
 constexpr int kSliceShapeAuto = 1;
 // The FP64 residual's gather pass on the same map: doubles in LDS, so a
 // smaller hub per workgroup.  Measured on the 4M-vertex power-law graph:
-// 16 / 2,048 299 us, 8 / 4,096 305 us, 16 / 1,024 310 us, 8 / 8,192 320 us,
-// 4 / 14,336 622 us.
-constexpr HubShape kHubResidShape = {16, 2048};
+// 12 / 7,168 253 us, 12 / 4,096 258 us, 16 / 2,048 299-309 us (its registers
+// spill at 16 wavefronts), 8 / 4,096 305 us, 16 / 1,024 310 us, 8 / 8,192
+// 320 us, 4 / 14,336 622 us.
+constexpr HubShape kHubResidShape = {12, 7168};
 inline int hub_groups_per_slice(int k, int max_items) {
   return (max_items + kHubShapes[k].waves - 1) / kHubShapes[k].waves;
 }
