@@ -185,6 +185,75 @@ def cpu_baseline(g, c, terms, seconds_target=20.0):
             "cpaa_solve_s": t_all / m_all * terms}
 
 
+def _median_time(fn, reps=3):
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        ts.append(time.perf_counter() - t0)
+    return float(np.median(ts))
+
+
+def _omp():
+    from oracle import omp
+    if not os.path.exists(omp.LIB_PATH):
+        omp.build()
+    return omp
+
+
+def cpu_baseline_sources(g, c, sources, terms, unit="GTEPS"):
+    """The C + OpenMP oracle's CPAA (FP64, all host threads) on a sample of the
+    workload's single-source right-hand sides, each with the GPU solve's term
+    count; median of 3.  GTEPS = stored entries x terms / s; also solves/s."""
+    omp = _omp()
+    th = host_threads()
+    k = len(sources)
+
+    def run():
+        for s in sources:
+            b = np.zeros(g.n)
+            b[s] = 1.0 - c
+            omp.cpaa(g, b, c, terms, threads=th)
+    t = _median_time(run)
+    gteps = g.nnz * terms * k / t / 1e9
+    return {"value": gteps if unit == "GTEPS" else k / t, "unit": unit, "cores": th,
+            "kind": "oracle",
+            "sample": f"FP64 oracle CPAA in C + OpenMP, {k} of the workload's sources, {terms} "
+                      f"terms each, on {th} threads (median of 3: {t:.2f} s)",
+            "cpu_model": cpu_model(), "gteps": gteps, "solves_per_s": k / t}
+
+
+class _Csr:
+    def __init__(self, n, rp, ci):
+        self.n, self.row_ptr, self.col_idx, self.nnz = n, rp, ci, int(rp[-1])
+
+
+def cpu_baseline_graphs(g, c, p, terms, sample=500):
+    """The C oracle's CPAA on the first `sample` graphs of the batch, one graph per
+    host thread at a time (each single-threaded: the graphs are small), with the
+    GPU solve's term count per graph; median of 3."""
+    from concurrent.futures import ThreadPoolExecutor
+    omp = _omp()
+    th = host_threads()
+    subs = []
+    for i in range(min(sample, g.num_graphs)):
+        a, b = int(g.graph_ptr[i]), int(g.graph_ptr[i + 1])
+        sg = _Csr(b - a, (g.row_ptr[a:b + 1] - g.row_ptr[a]).astype(np.int32),
+                  (g.col_idx[g.row_ptr[a]:g.row_ptr[b]] - a).astype(np.int32))
+        subs.append((sg, (1.0 - c) * np.asarray(p[a:b], dtype=np.float64), int(terms[i])))
+
+    def run():
+        with ThreadPoolExecutor(th) as ex:
+            list(ex.map(lambda t: omp.cpaa(t[0], t[1], c, t[2], threads=1), subs))
+    t = _median_time(run)
+    edges = sum(sg.nnz * m for sg, _, m in subs)
+    return {"value": edges / t / 1e9, "unit": "GTEPS", "cores": th, "kind": "oracle",
+            "sample": f"FP64 oracle CPAA in C on the first {len(subs)} graphs of the batch, "
+                      f"{th} graphs at a time, one thread each, each with its GPU term count "
+                      f"(median of 3: {t:.2f} s)",
+            "cpu_model": cpu_model(), "solves_per_s": len(subs) / t}
+
+
 def tile_term_bytes(n: int, nnz: int, tiles: int, cols: int, acc_frac: float = 1.0) -> float:
     """Algorithmic bytes of one batched term launch: each tile streams the pattern
     (4*nnz + 4*(n+1)); per vertex and column z_k gathered once, z_{k-1} read and
@@ -257,6 +326,10 @@ def bench_grid_batched(args):
                                                                        tiles * W),
                         "frac_every_term": tile_term_bytes(g.n, g.nnz, tiles, tiles * W)
                         / avg / 1e9 / HBM_PEAK_GBS}}
+    if not args.no_cpu_baseline:
+        log("cpu baseline ...")
+        out["cpu_baseline"] = cpu_baseline_sources(
+            g, c, src[:16], max(r["terms"] + r["refine_terms"] for r in allreps[-1]))
     print(json.dumps(out), flush=True)
 
 
@@ -335,6 +408,28 @@ def bench_table3(args):
            "paper_delaunay_n21": {"cpaa_rounds": 12, "power_rounds": 20, "cpaa_s": 1.111,
                                   "mpi_s": 1.854, "spi_s": 20.175,
                                   "hardware": "Xeon Silver 4210R, 38 threads, FP64"}}
+    # the term kernel of the certified CPAA solve (row order on the reverse
+    # Cuthill-McKee labels), timed by the HIP events around its series
+    mpt = cert["cpaa"]["ms_per_term"] / 1e3
+    alg = term_bytes(g.n, g.nnz)
+    out["roofline"] = {"bound": "hbm", "achieved": alg / mpt / 1e9, "peak": HBM_PEAK_GBS,
+                       "unit": "GB/s", "frac": alg / mpt / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                       "kernel": "term = k_term_w1 (row order, reverse Cuthill-McKee labels)",
+                       "bytes_per_launch": alg, "avg_launch_us": mpt * 1e6}
+    if not args.no_cpu_baseline:
+        log("cpu baseline ...")
+        omp = _omp()
+        th = host_threads()
+        pu = np.full(g.n, 1.0 / g.n)
+        t_c = _median_time(lambda: omp.cpaa(g, (1.0 - c) * pu, c, k_c, threads=th))
+        t_p = _median_time(lambda: omp.power(g, pu, c, 0.0, max_iter=k_p, threads=th))
+        out["cpu_baseline"] = {
+            "value": 1.0 / t_c, "unit": "solves/s", "cores": th, "kind": "oracle",
+            "sample": f"FP64 oracle in C + OpenMP on the same graph, {th} threads, median of 3: "
+                      f"CPAA {k_c} rounds (ERR < 1e-3) in {t_c:.3f} s, the power method "
+                      f"{k_p} rounds in {t_p:.3f} s",
+            "cpu_model": cpu_model(), "power_solves_per_s": 1.0 / t_p,
+            "speedup_at_err_1e-3": t_p / t_c}
     print(json.dumps(out), flush=True)
 
 
@@ -392,6 +487,20 @@ def bench_directed(args):
                                    if info["column_slices"] == 8 else "step = k_term_dir"),
                         "bytes_per_launch": alg,
                         "avg_launch_us": avg * 1e6}}
+    if not args.no_cpu_baseline:
+        # the numpy/scipy oracle's directed power method (one thread), P'' applied
+        # as written, for the GPU solve's step count; its setup (P from the
+        # pattern) is inside the timed call
+        log("cpu baseline ...")
+        import oracle
+        steps = r["terms"] + r["refine_terms"]
+        pu = np.full(g.n, 1.0 / g.n)
+        t = _median_time(lambda: oracle.power_method_directed(g, pu, c, steps), reps=1)
+        out["cpu_baseline"] = {
+            "value": g.nnz * steps / t / 1e9, "unit": "GTEPS", "cores": 1, "kind": "oracle",
+            "sample": f"FP64 numpy/scipy oracle, directed power method, {steps} steps on the "
+                      f"full graph, one thread, one run including its setup: {t:.2f} s",
+            "cpu_model": cpu_model(), "solves_per_s": 1.0 / t}
     print(json.dumps(out), flush=True)
 
 
@@ -444,6 +553,9 @@ def bench_graph_batch(args):
                         "bytes_per_launch": streamed, "avg_launch_us": kernel_s * 1e6,
                         "model": "pattern streamed once per term and residual pass + p, x, "
                                  "row_ptr; mostly served from L2/MALL"}}
+    if not args.no_cpu_baseline:
+        log("cpu baseline ...")
+        out["cpu_baseline"] = cpu_baseline_graphs(g, c, p, terms)
     print(json.dumps(out), flush=True)
 
 
@@ -494,6 +606,24 @@ def bench_config0(args):
                         "frac": alg / avg_launch_s / 1e9 / HBM_PEAK_GBS, "traffic": None,
                         "kernel": "term = k_term_w1 (row order; L2-resident, launch-bound)",
                         "bytes_per_launch": alg, "avg_launch_us": avg_launch_s * 1e6}}
+    if not args.no_cpu_baseline:
+        log("cpu baseline ...")
+        omp = _omp()
+        th = host_threads()
+        terms = reps[-1]["terms"] + reps[-1]["refine_terms"]
+        b = (1.0 - c) * np.full(g.n, 1.0 / g.n)
+        runs = 20   # a solve of this size takes milliseconds: time 20 in a row
+        t_all = _median_time(lambda: [omp.cpaa(g, b, c, terms, threads=th)
+                                      for _ in range(runs)]) / runs
+        t_one = _median_time(lambda: [omp.cpaa(g, b, c, terms, threads=1)
+                                      for _ in range(runs)]) / runs
+        out["cpu_baseline"] = {
+            "value": g.nnz * terms / t_all / 1e9, "unit": "GTEPS", "cores": th, "kind": "oracle",
+            "sample": f"FP64 oracle CPAA in C + OpenMP, the GPU solve's {terms} terms (main and "
+                      f"correction) on the same graph, {runs} solves in a row, median of 3: "
+                      f"{t_all * 1e3:.2f} ms per solve on {th} threads, {t_one * 1e3:.2f} ms on one",
+            "cpu_model": cpu_model(), "single_thread_gteps": g.nnz * terms / t_one / 1e9,
+            "solves_per_s": 1.0 / t_all}
     print(json.dumps(out), flush=True)
 
 
@@ -536,7 +666,13 @@ def bench_warmstart(args):
            "plain_solves_per_s": res["plain_solves_per_s"], "warm": res,
            "train": dict(stats, wall_s=train_s,
                          ms_per_source=1e3 * stats["train_s"] / max(len(tr_src), 1)),
+           # evaluate() raises unless every warm and plain solve is certified
            "certified": True}
+    if not args.no_cpu_baseline:
+        log("cpu baseline ...")
+        out["cpu_baseline"] = cpu_baseline_sources(
+            g_ev, c, ev_src[:8], int(round(res["plain_terms_mean"])), unit="solves/s")
+        out["cpu_baseline"]["sample"] += " (plain solves; the CPU has no network)"
     print(json.dumps(out), flush=True)
 
 

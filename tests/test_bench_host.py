@@ -74,3 +74,21 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode != 0
     assert "one GPU" in (r.stdout + r.stderr)
+
+
+def test_cpu_baselines_of_the_secondary_workloads():
+    """The per-workload CPU baselines run the C oracle on a sample of the same
+    workload: single sources with a given term count, and graphs cut out of a
+    block-diagonal batch (local labels, their own term counts)."""
+    import graphgen as gg
+    g = gg.chung_lu(3000, 8, 2.3, seed=3)
+    r = bench.cpu_baseline_sources(g, 0.85, [0, 5], 10)
+    assert r["kind"] == "oracle" and r["unit"] == "GTEPS" and r["value"] > 0
+    assert r["solves_per_s"] > 0 and r["cores"] >= 1
+    r = bench.cpu_baseline_sources(g, 0.85, [0], 10, unit="solves/s")
+    assert r["value"] == r["solves_per_s"]
+    batch = gg.uneven_batch(12, seed=5)
+    _, p = gg.batch_sources(batch, seed=5)
+    terms = [20] * batch.num_graphs
+    r = bench.cpu_baseline_graphs(batch, 0.85, p, terms, sample=5)
+    assert r["value"] > 0 and "first 5 graphs" in r["sample"]
