@@ -215,7 +215,7 @@ def cpu_baseline_sources(g, c, sources, terms, unit="GTEPS"):
             b[s] = 1.0 - c
             omp.cpaa(g, b, c, terms, threads=th)
     t = _median_time(run)
-    gteps = g.nnz * terms * k / t / 1e9
+    gteps = float(g.nnz) * terms * k / t / 1e9
     return {"value": gteps if unit == "GTEPS" else k / t, "unit": unit, "cores": th,
             "kind": "oracle",
             "sample": f"FP64 oracle CPAA in C + OpenMP, {k} of the workload's sources, {terms} "
@@ -246,7 +246,7 @@ def cpu_baseline_graphs(g, c, p, terms, sample=500):
         with ThreadPoolExecutor(th) as ex:
             list(ex.map(lambda t: omp.cpaa(t[0], t[1], c, t[2], threads=1), subs))
     t = _median_time(run)
-    edges = sum(sg.nnz * m for sg, _, m in subs)
+    edges = sum(float(sg.nnz) * m for sg, _, m in subs)
     return {"value": edges / t / 1e9, "unit": "GTEPS", "cores": th, "kind": "oracle",
             "sample": f"FP64 oracle CPAA in C on the first {len(subs)} graphs of the batch, "
                       f"{th} graphs at a time, one thread each, each with its GPU term count "
@@ -497,7 +497,7 @@ def bench_directed(args):
         pu = np.full(g.n, 1.0 / g.n)
         t = _median_time(lambda: oracle.power_method_directed(g, pu, c, steps), reps=1)
         out["cpu_baseline"] = {
-            "value": g.nnz * steps / t / 1e9, "unit": "GTEPS", "cores": 1, "kind": "oracle",
+            "value": float(g.nnz) * steps / t / 1e9, "unit": "GTEPS", "cores": 1, "kind": "oracle",
             "sample": f"FP64 numpy/scipy oracle, directed power method, {steps} steps on the "
                       f"full graph, one thread, one run including its setup: {t:.2f} s",
             "cpu_model": cpu_model(), "solves_per_s": 1.0 / t}
@@ -618,11 +618,11 @@ def bench_config0(args):
         t_one = _median_time(lambda: [omp.cpaa(g, b, c, terms, threads=1)
                                       for _ in range(runs)]) / runs
         out["cpu_baseline"] = {
-            "value": g.nnz * terms / t_all / 1e9, "unit": "GTEPS", "cores": th, "kind": "oracle",
+            "value": float(g.nnz) * terms / t_all / 1e9, "unit": "GTEPS", "cores": th, "kind": "oracle",
             "sample": f"FP64 oracle CPAA in C + OpenMP, the GPU solve's {terms} terms (main and "
                       f"correction) on the same graph, {runs} solves in a row, median of 3: "
                       f"{t_all * 1e3:.2f} ms per solve on {th} threads, {t_one * 1e3:.2f} ms on one",
-            "cpu_model": cpu_model(), "single_thread_gteps": g.nnz * terms / t_one / 1e9,
+            "cpu_model": cpu_model(), "single_thread_gteps": float(g.nnz) * terms / t_one / 1e9,
             "solves_per_s": 1.0 / t_all}
     print(json.dumps(out), flush=True)
 
