@@ -45,6 +45,8 @@ DIR_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_directed_n4m_traffic.jso
 TILE_KERNEL_SRC = [os.path.join(CSRC, f)
                    for f in ("kernels_tile.hip", "internal.h", "device.h", "api.hip", "solve.hip")]
 GRAPH_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "graphs_batch_10k_traffic.json")
+TABLE3_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "term_table3_delaunay_n21_traffic.json")
+CONFIG0_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "term_config0_er10k_traffic.json")
 GRAPH_KERNEL_SRC = [os.path.join(CSRC, f) for f in ("graphs.hip", "internal.h", "device.h")]
 
 
@@ -413,7 +415,8 @@ def bench_table3(args):
     mpt = cert["cpaa"]["ms_per_term"] / 1e3
     alg = term_bytes(g.n, g.nnz)
     out["roofline"] = {"bound": "hbm", "achieved": alg / mpt / 1e9, "peak": HBM_PEAK_GBS,
-                       "unit": "GB/s", "frac": alg / mpt / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                       "unit": "GB/s", "frac": alg / mpt / 1e9 / HBM_PEAK_GBS,
+                       "traffic": load_traffic(g.n, g.nnz, TABLE3_TRAFFIC_FILE),
                        "kernel": "term = k_term_w1 (row order, reverse Cuthill-McKee labels)",
                        "bytes_per_launch": alg, "avg_launch_us": mpt * 1e6}
     if not args.no_cpu_baseline:
@@ -603,7 +606,8 @@ def bench_config0(args):
            "certified": certified,
            "roofline": {"bound": "hbm", "achieved": alg / avg_launch_s / 1e9,
                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": alg / avg_launch_s / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                        "frac": alg / avg_launch_s / 1e9 / HBM_PEAK_GBS,
+                        "traffic": load_traffic(g.n, g.nnz, CONFIG0_TRAFFIC_FILE),
                         "kernel": "term = k_term_w1 (row order; L2-resident, launch-bound)",
                         "bytes_per_launch": alg, "avg_launch_us": avg_launch_s * 1e6}}
     if not args.no_cpu_baseline:
