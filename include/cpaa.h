@@ -178,6 +178,13 @@ typedef struct {
                              solves the graph without them (relabelled internally) and writes
                              x_v = (1-c) p_v (scaled like the rest under normalize) for each
                              dropped v.  0 (default): such a vertex is CPAA_EISOLATED. */
+  int32_t rows_per_wave;  /* column-sliced term with compact partials (undirected plans): most
+                             rows one wavefront's work item may hold, 1-1024; 0 (default) =
+                             1024.  An item also holds at most 2,048 stored entries, so the cap
+                             only binds where rows have few entries in a slice; smaller caps
+                             give more, shorter items.  The row-order layout is sized by
+                             nnz_per_thread instead.  Results depend on it only through the
+                             summation order of a row's entries. */
 } cpaa_opts;
 
 /* Per-solve report (one per right-hand side in batched calls, one per graph in

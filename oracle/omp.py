@@ -21,7 +21,7 @@ _lib = None
 
 
 def build() -> str:
-    tmp = LIB_PATH + ".tmp"
+    tmp = f"{LIB_PATH}.{os.getpid()}.tmp"   # concurrent builds (test workers) do not collide
     subprocess.run(["gcc", "-O3", "-march=x86-64-v2", "-fopenmp", "-shared", "-fPIC", "-std=c11",
                     SRC, "-o", tmp, "-lm"], check=True, capture_output=True)
     os.replace(tmp, LIB_PATH)

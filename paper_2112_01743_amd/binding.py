@@ -40,7 +40,8 @@ class cpaa_opts(ctypes.Structure):
                 ("column_slices", ctypes.c_int32), ("locality_order", ctypes.c_int32),
                 ("spectral_interval", ctypes.c_int32), ("directed", ctypes.c_int32),
                 ("slice_shape", ctypes.c_int32), ("fp64_recurrence", ctypes.c_int32),
-                ("deterministic", ctypes.c_int32), ("drop_isolated", ctypes.c_int32)]
+                ("deterministic", ctypes.c_int32), ("drop_isolated", ctypes.c_int32),
+                ("rows_per_wave", ctypes.c_int32)]
 
 
 class cpaa_report(ctypes.Structure):

@@ -474,10 +474,11 @@ struct HubHost {
 
 // Packed entries, wave items, compact partial indices and long-row chunks of
 // the hub-sliced term (layout in internal.h), from the relabelled CSR
-// (columns sorted).  Returns false when the entry array (with its run
-// padding) or the partial array would outgrow int offsets; h is then unusable.
+// (columns sorted); a wave item holds at most row_cap (<= kHubRows) present
+// rows.  Returns false when the entry array (with its run padding) or the
+// partial array would outgrow int offsets; h is then unusable.
 bool build_hub_sliced(int32_t n, const std::vector<int32_t>& rp2, const std::vector<int32_t>& ci2,
-                      const int slice_off[kSlices + 1], HubHost& h) {
+                      const int slice_off[kSlices + 1], int row_cap, HubHost& h) {
   struct LocalItem {
     int64_t j0, e0;
     int len, rows;
@@ -539,7 +540,7 @@ bool build_hub_sliced(int32_t n, const std::vector<int32_t>& rp2, const std::vec
         continue;
       }
       if (cur_rows > 0 &&
-          (static_cast<int>(logical.size()) + len > kHubItemCap || cur_rows == kHubRows))
+          (static_cast<int>(logical.size()) + len > kHubItemCap || cur_rows == row_cap))
         flush();
       if (cur_rows == 0) cur_j0 = j;
       for (const int32_t* q = x; q < y; ++q)
@@ -716,6 +717,7 @@ void cpaa_default_opts(cpaa_opts* o) {
   o->spectral_interval = 0;
   o->directed = 0;
   o->slice_shape = 0;
+  o->rows_per_wave = 0;
   o->fp64_recurrence = 0;
   o->deterministic = 0;
   o->drop_isolated = 0;
@@ -792,6 +794,10 @@ cpaa_status cpaa_plan(const cpaa_csr* g, double c, const cpaa_opts* opts, cpaa_p
   }
   if (o.column_slices == kSlices && (g->num_graphs > 1 || g->n >= kSliceMaxN)) {
     set_error("column slices need one graph with n < 8 (2^21 - 16)");
+    return CPAA_EINVAL;
+  }
+  if (o.rows_per_wave < 0 || o.rows_per_wave > kHubRows) {
+    set_error("rows_per_wave must be 0 (auto) or 1-" + std::to_string(kHubRows));
     return CPAA_EINVAL;
   }
   if (o.slice_shape < 0 || o.slice_shape > kHubConfigs + 1) {
@@ -1128,7 +1134,8 @@ cpaa_status cpaa_plan(const cpaa_csr* g, double c, const cpaa_opts* opts, cpaa_p
     const bool per_item_layout = pl->directed || shape == kHubConfigs + 1;
     if (s == CPAA_OK && !per_item_layout) {
       hh.cfg = shape - 1;
-      fits = build_hub_sliced(n, rp2, ci2, pl->slc.slice_off, hh);
+      fits = build_hub_sliced(n, rp2, ci2, pl->slc.slice_off,
+                              o.rows_per_wave > 0 ? o.rows_per_wave : kHubRows, hh);
       std::string why;
       if (fits && !check_hub_map(n, pl->slc.slice_off, hh, why)) {
         set_error("internal error: hub-sliced map check failed (" + why + ")");

@@ -591,6 +591,23 @@ def test_launch_shapes_give_identical_bits_and_autotune_keeps_one(torch_cuda):
     assert np.array_equal(x1.cpu().numpy(), ref[0]) and np.array_equal(x2.cpu().numpy(), ref[0])
 
 
+@pytest.mark.parametrize("rows", [1, 5, 64])
+def test_rows_per_wave_caps_the_items(torch_cuda, rows):
+    """rows_per_wave caps the present rows of a wave item of the column-sliced
+    map (the default is 1,024): more, shorter items, the same solution to the
+    solve's bound, and deterministic solves stay bitwise repeatable."""
+    from paper_2112_01743_amd import Plan
+    torch = torch_cuda
+    g = gg.chung_lu(200000, 12, 2.1, seed=49, dmax=30000)
+    p = gg.source_personalization(g.n, [11])[0]
+    plan = Plan.from_graph(g, C, column_slices=8, rows_per_wave=rows, deterministic=1)
+    x1, r1 = plan.solve(_dev(torch, p), 1e-9)
+    x2, _ = plan.solve(_dev(torch, p), 1e-9)
+    a = x1.cpu().numpy()
+    assert np.array_equal(a, x2.cpu().numpy())
+    _assert_parity(g, p, a, r1, 1e-9)
+
+
 def _host_residual_l1(g, p, x):
     """||(1-c) p - (I - cP) x||_1 in FP64 on the host, P x = A D^-1 x."""
     deg = np.diff(g.row_ptr).astype(np.float64)

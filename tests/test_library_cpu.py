@@ -233,6 +233,7 @@ def test_drop_isolated_plan_options():
                 {"deterministic": 1, "column_slices": 1},
                 {"deterministic": 1, "slice_shape": 5},
                 {"slice_shape": 6}, {"slice_shape": -1},
-                {"time_kernels": 3}, {"time_kernels": -1}):
+                {"time_kernels": 3}, {"time_kernels": -1},
+                {"rows_per_wave": -1}, {"rows_per_wave": 1025}):
         g = gg.cycle(6)
         assert _plan_status(g.row_ptr, g.col_idx, **bad) == B.CPAA_EINVAL, bad
