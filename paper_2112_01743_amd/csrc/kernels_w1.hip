@@ -475,7 +475,8 @@ __global__ __launch_bounds__(kWG) void k_combine_w1(CombineArgs a) {
 // by a segmented scan over the lanes (Hillis-Steele, keyed by row), so every
 // present row is written once, in LDS, and then copied out coalesced.
 // Pass 2 (k_combine_hub) adds a row's partials in slice order and runs the
-// term epilogue.
+// term epilogue.  With V = double the same pass sums acc for the FP64
+// residual (pass 2 is then k_resid_hub).
 template <typename V>
 struct HubArgsT {
   const uint32_t* entries;
@@ -494,7 +495,6 @@ struct HubArgsT {
   int pofs[kSlices + 1];
 };
 using HubArgs = HubArgsT<float>;
-
 
 // ordering of LDS accesses between the lanes of one wavefront
 __device__ __forceinline__ void wave_lds_sync() {
