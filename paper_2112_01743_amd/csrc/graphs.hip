@@ -82,9 +82,10 @@ __device__ __forceinline__ double block_allmax(double v, double* red) {
 // y[row] += src[col] over the graph's entries (LDS gathers, LDS atomics).
 // One pass y[row] += src[col] (or |src[col]|) over a graph's packed entries.
 // The entries of each chunk of 64*rl (row-ordered) entries are stored
-// transposed: lane l owns the contiguous run [l*rl, (l+1)*rl), element i at
-// i*64 + l, so the loads stay coalesced while a lane sums its rows in a
-// register.  A row that starts and ends inside a run has no other contributor
+// transposed: lane l owns the contiguous run [l*rl, (l+1)*rl) (rl a multiple
+// of 4), elements 4q..4q+3 of the run at q*256 + 4l, so each lane reads four
+// run elements with one 16-byte load and a wavefront's load covers 1 KB
+// contiguously, while a lane sums its rows in a register.  A row that starts and ends inside a run has no other contributor
 // (plain LDS store into the zeroed y); the first and last row of a run may be
 // shared with neighbouring runs (LDS atomic).  Per-entry LDS atomics, with
 // the lanes of a wavefront mostly hitting the same row, cost 4x more.
@@ -93,10 +94,17 @@ __device__ __forceinline__ void coo_pass(const uint32_t* __restrict__ coo, int n
                                          const T* src, T* y) {
   const int lane = threadIdx.x & 63;
   for (int c = threadIdx.x >> 6; c < nch; c += BLOCK / 64) {
-    const uint32_t* pc = coo + (size_t)c * 64 * rl + lane;
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    const u32x4* pc = reinterpret_cast<const u32x4*>(coo + (size_t)c * 64 * rl) + lane;
     uint32_t e[kGraphRunMax];
 #pragma unroll
-    for (int i = 0; i < kGraphRunMax; ++i) e[i] = i < rl ? pc[i * 64] : kGraphPad;
+    for (int q = 0; q < kGraphRunMax / 4; ++q) {
+      const u32x4 v = 4 * q < rl ? pc[q * 64] : u32x4{kGraphPad, kGraphPad, kGraphPad, kGraphPad};
+      e[4 * q] = v.x;
+      e[4 * q + 1] = v.y;
+      e[4 * q + 2] = v.z;
+      e[4 * q + 3] = v.w;
+    }
     T v[kGraphRunMax];
 #pragma unroll
     for (int i = 0; i < kGraphRunMax; ++i) {
@@ -466,13 +474,15 @@ cpaa_status build_graph_state(cpaa_plan_s* pl, const int32_t* rp, const int32_t*
   }
   pl->graph_state = gs;
   const int G = pl->num_graphs;
-  // per graph: runs of rl entries per lane, rl = clamp(nnz_g / 512, 2, 16),
-  // chunks of 64*rl entries, the last one padded
+  // per graph: runs of rl entries per lane, rl = nnz_g / 512 rounded up to a
+  // multiple of 4 within [4, 16], chunks of 64*rl entries (16-byte aligned),
+  // the last one padded
+  static_assert(kGraphRunMax % 4 == 0, "runs load four entries at a time");
   std::vector<int> off(G), meta(G);
   size_t total = 0;
   for (int gi = 0; gi < G; ++gi) {
     const int mg = rp[gp[gi + 1]] - rp[gp[gi]];
-    const int rl = std::min(kGraphRunMax, std::max(2, (mg + 511) / 512));
+    const int rl = std::min(kGraphRunMax, std::max(4, ((mg + 511) / 512 + 3) & ~3));
     const int nch = (mg + 64 * rl - 1) / (64 * rl);
     off[gi] = static_cast<int>(total);
     meta[gi] = (nch << 6) | rl;
@@ -489,8 +499,8 @@ cpaa_status build_graph_state(cpaa_plan_s* pl, const int32_t* rp, const int32_t*
     int q = 0;
     for (int u = gp[gi]; u < gp[gi + 1]; ++u)
       for (int j = rp[u]; j < rp[u + 1]; ++j, ++q) {
-        const int c = q / ch, w = q % ch;
-        coo[off[gi] + static_cast<size_t>(c) * ch + (w % rl) * 64 + w / rl] =
+        const int c = q / ch, w = q % ch, l = w / rl, i = w % rl;
+        coo[off[gi] + static_cast<size_t>(c) * ch + (i >> 2) * 256 + l * 4 + (i & 3)] =
             (static_cast<uint32_t>(u - v0) << 16) | static_cast<uint32_t>(ci[j] - v0);
       }
   }
