@@ -226,6 +226,8 @@ def cpu_baseline_sources(g, c, sources, terms, unit="GTEPS"):
 
 
 class _Csr:
+    """A plain CSR (n, row_ptr, col_idx, nnz): one graph cut out of a batch."""
+
     def __init__(self, n, rp, ci):
         self.n, self.row_ptr, self.col_idx, self.nnz = n, rp, ci, int(rp[-1])
 
