@@ -121,8 +121,10 @@ constexpr int64_t kSliceEntryLimit = INT32_MAX;   // int32 entry offsets of the 
 // 160 KB).  Measured on the 4M-vertex power-law graph (gather pass per term):
 // 16 / 22,528 175 us, 16 / 16,384 185 us, 8 / 8,192 189 us, 4 / 2,048 228 us;
 // 12 wavefronts with a larger hub (24,576 or 27,648) 187 us: below 16
-// wavefronts per CU the gathers in flight drop more than the hub gains.  A
-// persistent variant (workgroups looping over items claimed from a counter)
+// wavefronts per CU the gathers in flight drop more than the hub gains; two
+// workgroups per CU of 12 / 7,808 tie the best (175 us, 24 wavefronts per CU,
+// half the hub), 10 / 9,920 183 us, and 512-row items with 12 / 14,144 179 us.
+// A persistent variant (workgroups looping over items claimed from a counter)
 // took 420-540 us, and the per-item layout's pass 219 us.
 struct HubShape {
   int waves, hub;   // one workgroup per `waves` consecutive wave items of a slice
