@@ -125,7 +125,9 @@ constexpr int64_t kSliceEntryLimit = INT32_MAX;   // int32 entry offsets of the 
 // workgroups per CU of 12 / 7,808 tie the best (175 us, 24 wavefronts per CU,
 // half the hub), 10 / 9,920 183 us, and 512-row items with 12 / 14,144 179 us.
 // A persistent variant (workgroups looping over items claimed from a counter)
-// took 420-540 us, and the per-item layout's pass 219 us.
+// took 420-540 us; one with a workgroup per CU taking a fixed contiguous share
+// of its slice's items (no counter, the hub copied once) about 187 us (the
+// term 218 against 206 us); the per-item layout's pass 219 us.
 struct HubShape {
   int waves, hub;   // one workgroup per `waves` consecutive wave items of a slice
 };
