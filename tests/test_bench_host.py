@@ -92,3 +92,22 @@ def test_cpu_baselines_of_the_secondary_workloads():
     terms = [20] * batch.num_graphs
     r = bench.cpu_baseline_graphs(batch, 0.85, p, terms, sample=5)
     assert r["value"] > 0 and "first 5 graphs" in r["sample"]
+
+
+def test_emit_prints_the_line_when_the_copy_cannot_run(capsys, monkeypatch):
+    """The copy bandwidth is context added after the timed region: when it
+    cannot be measured the line is printed as it was, and when it can the
+    fraction is achieved over the copy's rate."""
+    def no_gpu():
+        raise RuntimeError("no device")
+    monkeypatch.setattr(bench, "copy_bandwidth", no_gpu)
+    line = {"value": 1.0, "roofline": {"unit": "GB/s", "achieved": 10.0}}
+    bench.emit(dict(line, roofline=dict(line["roofline"])))
+    assert json.loads(capsys.readouterr().out) == line
+    monkeypatch.setattr(bench, "copy_bandwidth", lambda: 40.0)
+    bench.emit(dict(line, roofline=dict(line["roofline"])))
+    rf = json.loads(capsys.readouterr().out)["roofline"]
+    assert rf["copy_gbs"] == 40.0 and rf["frac_of_copy"] == 0.25
+    # a roofline in other units (TFLOP/s) gets no copy figure
+    bench.emit({"value": 1.0, "roofline": {"unit": "TFLOP/s", "achieved": 1.0}})
+    assert "copy_gbs" not in json.loads(capsys.readouterr().out)["roofline"]
