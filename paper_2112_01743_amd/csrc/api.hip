@@ -1251,11 +1251,15 @@ cpaa_status cpaa_plan(const cpaa_csr* g, double c, const cpaa_opts* opts, cpaa_p
       pl->max_graph_nnz = std::max(pl->max_graph_nnz, gnnz[gi]);
     }
     // size classes: class 0 holds graphs with more than max_n/2 vertices, class 1
-    // more than max_n/4, class 2 the rest; each class is launched with the LDS
-    // its own largest graph needs, so small graphs get more workgroups per CU
+    // more than max_n/4, class 2 more than max_n/8, class 3 the rest; each class
+    // is launched with the LDS its own largest graph needs (and its own
+    // workgroup size), so small graphs get more workgroups per CU
     auto cls = [&](int gi) {
       const int ng = gp[gi + 1] - gp[gi];
-      return ng * 2 > pl->max_graph_n ? 0 : (ng * 4 > pl->max_graph_n ? 1 : 2);
+      return ng * 2 > pl->max_graph_n ? 0
+             : ng * 4 > pl->max_graph_n ? 1
+             : ng * 8 > pl->max_graph_n ? 2
+                                        : 3;
     };
     std::vector<int32_t> order(num_graphs);
     for (int gi = 0; gi < num_graphs; ++gi) order[gi] = gi;

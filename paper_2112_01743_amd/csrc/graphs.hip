@@ -390,7 +390,7 @@ struct GraphRun {
   const double* p = nullptr;
   double* x = nullptr;
   double tol = 0.0;
-  int block = 0;
+  int block[kGraphClasses] = {};
 };
 
 // launch shape: workgroup size and rows per thread
@@ -412,6 +412,10 @@ static hipError_t launch_graphs(int block, int rpt, dim3 grid, size_t lds, hipSt
     hipLaunchKernelGGL((k_graphs<B, R>), grid, dim3(B), lds, st, a);              \
     return hipGetLastError();                                                     \
   }
+  CPAA_G(64, 1) CPAA_G(64, 2) CPAA_G(64, 4) CPAA_G(64, 8) CPAA_G(64, 10) CPAA_G(64, 16)
+  CPAA_G(64, 20)
+  CPAA_G(128, 1) CPAA_G(128, 2) CPAA_G(128, 4) CPAA_G(128, 8) CPAA_G(128, 10) CPAA_G(128, 16)
+  CPAA_G(128, 20)
   CPAA_G(256, 1) CPAA_G(256, 2) CPAA_G(256, 4) CPAA_G(256, 8) CPAA_G(256, 10) CPAA_G(256, 16)
   CPAA_G(256, 20)
   CPAA_G(512, 1) CPAA_G(512, 2) CPAA_G(512, 4) CPAA_G(512, 8) CPAA_G(512, 10) CPAA_G(512, 16)
@@ -426,6 +430,10 @@ static hipError_t set_lds_limit(int block, int rpt, size_t lds) {
   if (block == B && rpt == R)                                                              \
     return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_graphs<B, R>),              \
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  CPAA_A(64, 1) CPAA_A(64, 2) CPAA_A(64, 4) CPAA_A(64, 8) CPAA_A(64, 10) CPAA_A(64, 16)
+  CPAA_A(64, 20)
+  CPAA_A(128, 1) CPAA_A(128, 2) CPAA_A(128, 4) CPAA_A(128, 8) CPAA_A(128, 10) CPAA_A(128, 16)
+  CPAA_A(128, 20)
   CPAA_A(256, 1) CPAA_A(256, 2) CPAA_A(256, 4) CPAA_A(256, 8) CPAA_A(256, 10) CPAA_A(256, 16)
   CPAA_A(256, 20)
   CPAA_A(512, 1) CPAA_A(512, 2) CPAA_A(512, 4) CPAA_A(512, 8) CPAA_A(512, 10) CPAA_A(512, 16)
@@ -444,7 +452,7 @@ struct GraphState {
   int* d_abort = nullptr;
   double* h_rec = nullptr;
   int num_cus = 0;
-  int block = 0;          // chosen workgroup size (0 = not chosen yet)
+  int block[kGraphClasses] = {};   // chosen workgroup size per size class (0 = not chosen yet)
   GraphRun run;
 };
 
@@ -524,8 +532,17 @@ cpaa_status build_graph_state(cpaa_plan_s* pl, const int32_t* rp, const int32_t*
   return CPAA_OK;
 }
 
-static cpaa_status capture_run(cpaa_plan_s* pl, GraphState* gs, const double* p, double tol,
-                               double* x, int block, hipStream_t st) {
+// One persistent launch per size class, each with the LDS of its largest
+// graph and its own workgroup size (blocks[k]).
+struct ClassLaunch {
+  GraphArgs a;
+  int cls, block, rpt;
+  size_t lds;
+  dim3 grid;
+};
+
+static cpaa_status class_launches(cpaa_plan_s* pl, GraphState* gs, const double* p, double tol,
+                                  double* x, const int* blocks, std::vector<ClassLaunch>& out) {
   GraphArgs a;
   a.rp = pl->d_row_ptr;
   a.coo = gs->d_coo;
@@ -547,42 +564,61 @@ static cpaa_status capture_run(cpaa_plan_s* pl, GraphState* gs, const double* p,
   a.max_refine = pl->opts.max_refine;
   a.normalize = pl->opts.normalize;
   a.rec = gs->d_rec;
-  // one persistent launch per size class, each with the LDS of its largest graph
-  struct ClassLaunch {
-    GraphArgs a;
-    int rpt;
-    size_t lds;
-    dim3 grid;
-  };
-  std::vector<ClassLaunch> launches;
+  out.clear();
   for (int k = 0; k < kGraphClasses; ++k) {
     const int count = pl->graph_cls_off[k + 1] - pl->graph_cls_off[k];
-    if (count == 0) continue;
+    if (count == 0 || blocks[k] == 0) continue;   // 0: left out (tuning runs only)
     ClassLaunch L;
     L.a = a;
     L.a.order = pl->d_graph_order + pl->graph_cls_off[k];
     L.a.num_graphs = count;
     L.a.max_ng = pl->graph_cls_n[k];
     L.a.queue = pl->d_queue + k;
-    if (!pick_shape(L.a.max_ng, block, &L.rpt)) {
+    L.cls = k;
+    L.block = blocks[k];
+    if (!pick_shape(L.a.max_ng, L.block, &L.rpt)) {
       set_error("graphs too large for the batched kernel");
       return CPAA_EINVAL;
     }
     L.lds = 16 * (size_t)L.a.max_ng;
     // resident workgroups per CU: 2048 threads and 160 KB of LDS per CU
     const int per_cu = std::max(
-        1, std::min(2048 / block, (int)((160 * 1024) / (L.lds + (size_t)block / 8 + 64))));
+        1, std::min(2048 / L.block, (int)((160 * 1024) / (L.lds + (size_t)L.block / 8 + 64))));
     L.grid = dim3(std::min(count, gs->num_cus * per_cu));
-    launches.push_back(L);
+    out.push_back(L);
   }
   // classes can share a (block, rpt) instantiation: raise its LDS limit to the largest use
-  for (const ClassLaunch& L : launches) {
+  for (const ClassLaunch& L : out) {
     size_t lds = L.lds;
-    for (const ClassLaunch& M : launches)
-      if (M.rpt == L.rpt) lds = std::max(lds, M.lds);
-    CPAA_HIP(set_lds_limit(block, L.rpt, lds));
+    for (const ClassLaunch& M : out)
+      if (M.block == L.block && M.rpt == L.rpt) lds = std::max(lds, M.lds);
+    CPAA_HIP(set_lds_limit(L.block, L.rpt, lds));
   }
+  return CPAA_OK;
+}
 
+// reset the queues -> validate p -> one launch per class, in turn; with
+// `ev` (kGraphClasses + 1 events) class k's launch runs between ev[k] and ev[k+1]
+static hipError_t enqueue_run(cpaa_plan_s* pl, GraphState* gs, const double* p,
+                              const std::vector<ClassLaunch>& launches, hipStream_t st,
+                              hipEvent_t* ev = nullptr) {
+  hipLaunchKernelGGL(k_reset_graph_run, dim3(1), dim3(64), 0, st, gs->d_abort, pl->d_queue);
+  hipLaunchKernelGGL(k_validate_graphs, dim3(pl->num_graphs), dim3(kWG), 0, st,
+                     pl->d_graph_ptr, p, gs->d_rec, gs->d_abort);
+  hipError_t e = hipGetLastError();
+  for (const ClassLaunch& L : launches) {
+    if (e == hipSuccess && ev) e = hipEventRecord(ev[L.cls], st);
+    if (e == hipSuccess) e = launch_graphs(L.block, L.rpt, L.grid, L.lds, st, L.a);
+    if (e == hipSuccess && ev) e = hipEventRecord(ev[L.cls + 1], st);
+  }
+  return e;
+}
+
+static cpaa_status capture_run(cpaa_plan_s* pl, GraphState* gs, const double* p, double tol,
+                               double* x, const int* blocks, hipStream_t st) {
+  std::vector<ClassLaunch> launches;
+  cpaa_status s = class_launches(pl, gs, p, tol, x, blocks, launches);
+  if (s != CPAA_OK) return s;
   GraphRun& run = gs->run;
   if (run.exec) (void)hipGraphExecDestroy(run.exec);
   if (run.graph) (void)hipGraphDestroy(run.graph);
@@ -591,12 +627,7 @@ static cpaa_status capture_run(cpaa_plan_s* pl, GraphState* gs, const double* p,
   CPAA_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
   hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_reset_graph_run, dim3(1), dim3(64), 0, cs, gs->d_abort, pl->d_queue);
-    hipLaunchKernelGGL(k_validate_graphs, dim3(pl->num_graphs), dim3(kWG), 0, cs,
-                       pl->d_graph_ptr, p, gs->d_rec, gs->d_abort);
-    hipError_t el = hipSuccess;
-    for (const ClassLaunch& L : launches)
-      if (el == hipSuccess) el = launch_graphs(block, L.rpt, L.grid, L.lds, cs, L.a);
+    const hipError_t el = enqueue_run(pl, gs, p, launches, cs);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(cs, &graph);
     if (el != hipSuccess) e = el;
@@ -612,9 +643,54 @@ static cpaa_status capture_run(cpaa_plan_s* pl, GraphState* gs, const double* p,
   run.p = p;
   run.x = x;
   run.tol = tol;
-  run.block = block;
+  for (int k = 0; k < kGraphClasses; ++k) run.block[k] = blocks[k];
   (void)st;
   return CPAA_OK;
+}
+
+// Workgroup size per size class: each candidate runs the whole batch eagerly
+// twice (the second timed, class by class); every class keeps its fastest.
+// Any workgroup size gives a certified result for every graph.
+static cpaa_status tune_blocks(cpaa_plan_s* pl, GraphState* gs, const double* p, double tol,
+                               double* x, hipStream_t st) {
+  hipEvent_t ev[kGraphClasses + 1] = {};
+  hipError_t e = hipSuccess;
+  for (int k = 0; k <= kGraphClasses && e == hipSuccess; ++k) e = hipEventCreate(&ev[k]);
+  float best[kGraphClasses];
+  for (int k = 0; k < kGraphClasses; ++k) {
+    best[k] = 1e30f;
+    gs->block[k] = 512;
+  }
+  cpaa_status s = CPAA_OK;
+  for (int b : {64, 128, 256, 512, 1024}) {
+    if (e != hipSuccess || s != CPAA_OK) break;
+    // a class whose largest graph does not fit b threads is left out for b
+    int blocks[kGraphClasses];
+    bool any = false;
+    for (int k = 0; k < kGraphClasses; ++k) {
+      int rpt;
+      blocks[k] = pick_shape(pl->graph_cls_n[k], b, &rpt) ? b : 0;
+      any = any || blocks[k] != 0;
+    }
+    if (!any) continue;
+    std::vector<ClassLaunch> launches;
+    if ((s = class_launches(pl, gs, p, tol, x, blocks, launches)) != CPAA_OK) break;
+    for (int rep = 0; rep < 2 && e == hipSuccess; ++rep)
+      e = enqueue_run(pl, gs, p, launches, st, rep == 1 ? ev : nullptr);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    for (const ClassLaunch& L : launches) {
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[L.cls], ev[L.cls + 1]);
+      if (e == hipSuccess && ms < best[L.cls]) {
+        best[L.cls] = ms;
+        gs->block[L.cls] = b;
+      }
+    }
+  }
+  for (int k = 0; k <= kGraphClasses; ++k)
+    if (ev[k]) (void)hipEventDestroy(ev[k]);
+  CPAA_HIP(e);
+  return s;
 }
 
 cpaa_status solve_graphs_impl(cpaa_plan_s* pl, const double* p, double tol, double* x,
@@ -626,35 +702,19 @@ cpaa_status solve_graphs_impl(cpaa_plan_s* pl, const double* p, double tol, doub
   }
   const int G = pl->num_graphs;
   cpaa_status s;
-  // Workgroup size: fixed by the autotuner on the first call (both candidates
-  // produce the same result), 512 threads otherwise.
-  if (gs->block == 0) {
+  // Workgroup size per size class: fixed by the autotuner on the first call,
+  // 512 threads otherwise.
+  if (gs->block[0] == 0) {
     if (pl->opts.autotune) {
-      float best = 1e30f;
-      int best_b = 512;
-      for (int b : {256, 512, 1024}) {
-        int rpt;
-        if (!pick_shape(pl->max_graph_n, b, &rpt)) continue;
-        if ((s = capture_run(pl, gs, p, tol, x, b, st)) != CPAA_OK) return s;
-        CPAA_HIP(hipGraphLaunch(gs->run.exec, st));   // warm
-        CPAA_HIP(hipEventRecord(pl->ev_begin, st));
-        CPAA_HIP(hipGraphLaunch(gs->run.exec, st));
-        CPAA_HIP(hipEventRecord(pl->ev_end, st));
-        CPAA_HIP(hipStreamSynchronize(st));
-        float ms = 0.f;
-        CPAA_HIP(hipEventElapsedTime(&ms, pl->ev_begin, pl->ev_end));
-        if (ms < best) {
-          best = ms;
-          best_b = b;
-        }
-      }
-      gs->block = best_b;
+      if ((s = tune_blocks(pl, gs, p, tol, x, st)) != CPAA_OK) return s;
     } else {
-      gs->block = 512;
+      for (int k = 0; k < kGraphClasses; ++k) gs->block[k] = 512;
     }
   }
   GraphRun& run = gs->run;
-  if (!run.exec || run.p != p || run.x != x || run.tol != tol || run.block != gs->block) {
+  bool same = run.exec && run.p == p && run.x == x && run.tol == tol;
+  for (int k = 0; k < kGraphClasses; ++k) same = same && run.block[k] == gs->block[k];
+  if (!same) {
     if ((s = capture_run(pl, gs, p, tol, x, gs->block, st)) != CPAA_OK) return s;
   }
   CPAA_HIP(hipEventRecord(pl->ev_begin, st));

@@ -28,7 +28,7 @@ constexpr int kLongRow = 128;      // W = 1: rows longer than this never share a
 constexpr int kTileLongDeg = 512;  // tiled: rows above this degree are split across wavefronts
 constexpr int kTileChunkNnz = 256; // tiled: nnz per wavefront chunk of a split row
 constexpr int kTileShortNnz = 128; // tiled: nnz budget of a wavefront's group of short rows
-constexpr int kGraphClasses = 3;   // multi-graph: size classes (LDS per workgroup) launched in turn
+constexpr int kGraphClasses = 4;   // multi-graph: size classes (LDS per workgroup) launched in turn
 
 void set_error(const std::string& msg);
 
@@ -318,8 +318,8 @@ struct cpaa_plan_s {
   int32_t* d_graph_ptr = nullptr;
   int32_t* d_graph_order = nullptr;  // graphs by size class, then by nnz, largest first
   int* d_queue = nullptr;            // [kGraphClasses] work counters
-  int graph_cls_off[4] = {};         // graphs of class k: order[graph_cls_off[k] .. [k+1])
-  int graph_cls_n[3] = {};           // largest vertex count in class k (LDS sizing)
+  int graph_cls_off[cpaa::kGraphClasses + 1] = {};   // graphs of class k: order[graph_cls_off[k] .. [k+1])
+  int graph_cls_n[cpaa::kGraphClasses] = {};         // largest vertex count in class k (LDS sizing)
   int max_graph_n = 0;
   int64_t max_graph_nnz = 0;
   std::vector<int32_t> h_graph_ptr;
