@@ -396,14 +396,28 @@ struct GraphRun {
 // launch shape: workgroup size and rows per thread
 static bool pick_shape(int max_ng, int block, int* rpt) {
   const int need = (max_ng + block - 1) / block;
-  static const int opts[] = {1, 2, 4, 8, 10, 16, 20};
+  static const int opts[] = {1, 2, 3, 4, 5, 6, 8, 10, 16, 20};
   for (int r : opts)
-    if (r >= need) {
+    if (r >= need && !(block == 1024 && r > 10)) {   // as instantiated below
       *rpt = r;
       return true;
     }
   return false;
 }
+
+// Instantiated shapes: every workgroup size with every rows-per-thread count
+// of pick_shape (1024 threads stop at 10: LDS caps a graph near 10,240 vertices).
+#define CPAA_GRAPH_SHAPES(X)                                                              \
+  X(64, 1) X(64, 2) X(64, 3) X(64, 4) X(64, 5) X(64, 6) X(64, 8) X(64, 10) X(64, 16)        \
+  X(64, 20)                                                                               \
+  X(128, 1) X(128, 2) X(128, 3) X(128, 4) X(128, 5) X(128, 6) X(128, 8) X(128, 10)         \
+  X(128, 16) X(128, 20)                                                                   \
+  X(256, 1) X(256, 2) X(256, 3) X(256, 4) X(256, 5) X(256, 6) X(256, 8) X(256, 10)         \
+  X(256, 16) X(256, 20)                                                                   \
+  X(512, 1) X(512, 2) X(512, 3) X(512, 4) X(512, 5) X(512, 6) X(512, 8) X(512, 10)         \
+  X(512, 16) X(512, 20)                                                                   \
+  X(1024, 1) X(1024, 2) X(1024, 3) X(1024, 4) X(1024, 5) X(1024, 6) X(1024, 8)             \
+  X(1024, 10)
 
 static hipError_t launch_graphs(int block, int rpt, dim3 grid, size_t lds, hipStream_t st,
                                 const GraphArgs& a) {
@@ -412,15 +426,7 @@ static hipError_t launch_graphs(int block, int rpt, dim3 grid, size_t lds, hipSt
     hipLaunchKernelGGL((k_graphs<B, R>), grid, dim3(B), lds, st, a);              \
     return hipGetLastError();                                                     \
   }
-  CPAA_G(64, 1) CPAA_G(64, 2) CPAA_G(64, 4) CPAA_G(64, 8) CPAA_G(64, 10) CPAA_G(64, 16)
-  CPAA_G(64, 20)
-  CPAA_G(128, 1) CPAA_G(128, 2) CPAA_G(128, 4) CPAA_G(128, 8) CPAA_G(128, 10) CPAA_G(128, 16)
-  CPAA_G(128, 20)
-  CPAA_G(256, 1) CPAA_G(256, 2) CPAA_G(256, 4) CPAA_G(256, 8) CPAA_G(256, 10) CPAA_G(256, 16)
-  CPAA_G(256, 20)
-  CPAA_G(512, 1) CPAA_G(512, 2) CPAA_G(512, 4) CPAA_G(512, 8) CPAA_G(512, 10) CPAA_G(512, 16)
-  CPAA_G(512, 20)
-  CPAA_G(1024, 1) CPAA_G(1024, 2) CPAA_G(1024, 4) CPAA_G(1024, 8) CPAA_G(1024, 10)
+  CPAA_GRAPH_SHAPES(CPAA_G)
 #undef CPAA_G
   return hipErrorInvalidValue;
 }
@@ -430,15 +436,7 @@ static hipError_t set_lds_limit(int block, int rpt, size_t lds) {
   if (block == B && rpt == R)                                                              \
     return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_graphs<B, R>),              \
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  CPAA_A(64, 1) CPAA_A(64, 2) CPAA_A(64, 4) CPAA_A(64, 8) CPAA_A(64, 10) CPAA_A(64, 16)
-  CPAA_A(64, 20)
-  CPAA_A(128, 1) CPAA_A(128, 2) CPAA_A(128, 4) CPAA_A(128, 8) CPAA_A(128, 10) CPAA_A(128, 16)
-  CPAA_A(128, 20)
-  CPAA_A(256, 1) CPAA_A(256, 2) CPAA_A(256, 4) CPAA_A(256, 8) CPAA_A(256, 10) CPAA_A(256, 16)
-  CPAA_A(256, 20)
-  CPAA_A(512, 1) CPAA_A(512, 2) CPAA_A(512, 4) CPAA_A(512, 8) CPAA_A(512, 10) CPAA_A(512, 16)
-  CPAA_A(512, 20)
-  CPAA_A(1024, 1) CPAA_A(1024, 2) CPAA_A(1024, 4) CPAA_A(1024, 8) CPAA_A(1024, 10)
+  CPAA_GRAPH_SHAPES(CPAA_A)
 #undef CPAA_A
   return hipErrorInvalidValue;
 }
