@@ -55,16 +55,17 @@ struct GraphArgs {
   double* rec;              // [num_graphs][kRec]
 };
 
+// Sum / max over the workgroup, returned to every thread: wavefront partials
+// through LDS, then each wavefront reduces the partials across its lanes (the
+// same butterfly in every wavefront, so every thread gets the same bits).
 template <int BLOCK>
 __device__ __forceinline__ double block_allsum(double v, double* red) {
   v = wave_sum(v);
   __syncthreads();
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
-  double s = 0.0;
-#pragma unroll
-  for (int w = 0; w < BLOCK / 64; ++w) s += red[w];
-  return s;
+  const int lane = threadIdx.x & 63;
+  return wave_sum(lane < BLOCK / 64 ? red[lane] : 0.0);
 }
 
 template <int BLOCK>
@@ -73,10 +74,8 @@ __device__ __forceinline__ double block_allmax(double v, double* red) {
   __syncthreads();
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
-  double s = 0.0;
-#pragma unroll
-  for (int w = 0; w < BLOCK / 64; ++w) s = fmax(s, red[w]);
-  return s;
+  const int lane = threadIdx.x & 63;
+  return wave_max(lane < BLOCK / 64 ? red[lane] : 0.0);
 }
 
 // y[row] += src[col] over the graph's entries (LDS gathers, LDS atomics).
@@ -105,17 +104,13 @@ __device__ __forceinline__ void coo_pass(const uint32_t* __restrict__ coo, int n
       e[4 * q + 2] = v.z;
       e[4 * q + 3] = v.w;
     }
-    T v[kGraphRunMax];
-#pragma unroll
-    for (int i = 0; i < kGraphRunMax; ++i) {
-      v[i] = e[i] != kGraphPad ? src[e[i] & 0xffffu] : T(0);
-      if (ABS) v[i] = fabs(v[i]);
-    }
     int row = -1;
     T sum = T(0);
     bool first = true;
 #pragma unroll
     for (int i = 0; i < kGraphRunMax; ++i) {
+      T vi = e[i] != kGraphPad ? src[e[i] & 0xffffu] : T(0);
+      if (ABS) vi = fabs(vi);
       if (e[i] != kGraphPad) {
         const int r = static_cast<int>(e[i] >> 16);
         if (r != row) {
@@ -127,9 +122,9 @@ __device__ __forceinline__ void coo_pass(const uint32_t* __restrict__ coo, int n
             first = false;
           }
           row = r;
-          sum = v[i];
+          sum = vi;
         } else {
-          sum += v[i];
+          sum += vi;
         }
       }
     }
