@@ -58,12 +58,19 @@ def _solve(torch, g, p, tol, **opts):
 
 
 @pytest.mark.parametrize("tol", [1e-6, 1e-10])
-def test_small_uneven_batch(torch_cuda, tol):
+@pytest.mark.parametrize("autotune", [0, 1])
+def test_small_uneven_batch(torch_cuda, tol, autotune):
+    """Four size classes of graphs with 5-400 vertices; with autotune every
+    class is timed with 64- to 1024-thread workgroups and keeps its fastest
+    (the tuning runs and the kept launches both leave certified results)."""
     g = gg.uneven_batch(40, seed=17, n_lo=5, n_hi=400)
     src, p = gg.batch_sources(g, seed=3)
-    _note(f"batch of {g.num_graphs} graphs n={g.n} nnz={g.nnz} tol={tol}")
-    x, reps, _ = _solve(torch_cuda, g, p, tol)
+    _note(f"batch of {g.num_graphs} graphs n={g.n} nnz={g.nnz} tol={tol} autotune={autotune}")
+    x, reps, plan = _solve(torch_cuda, g, p, tol, autotune=autotune)
     _check(g, p, x, reps, tol, range(g.num_graphs))
+    # a second call replays the captured launches with the kept shapes
+    x2, reps2 = plan.solve_graphs(_dev(torch_cuda, p), tol)
+    _check(g, p, x2.cpu().numpy(), reps2, tol, range(g.num_graphs))
 
 
 def test_mixed_personalizations(torch_cuda):
