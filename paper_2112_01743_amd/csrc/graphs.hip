@@ -591,7 +591,7 @@ static cpaa_status class_launches(cpaa_plan_s* pl, GraphState* gs, const double*
 }
 
 // reset the queues -> validate p -> one launch per class, in turn; with
-// `ev` (kGraphClasses + 1 events) class k's launch runs between ev[k] and ev[k+1]
+// `ev` (2 kGraphClasses events) class k's launch runs between ev[2k] and ev[2k+1]
 static hipError_t enqueue_run(cpaa_plan_s* pl, GraphState* gs, const double* p,
                               const std::vector<ClassLaunch>& launches, hipStream_t st,
                               hipEvent_t* ev = nullptr) {
@@ -600,9 +600,9 @@ static hipError_t enqueue_run(cpaa_plan_s* pl, GraphState* gs, const double* p,
                      pl->d_graph_ptr, p, gs->d_rec, gs->d_abort);
   hipError_t e = hipGetLastError();
   for (const ClassLaunch& L : launches) {
-    if (e == hipSuccess && ev) e = hipEventRecord(ev[L.cls], st);
+    if (e == hipSuccess && ev) e = hipEventRecord(ev[2 * L.cls], st);
     if (e == hipSuccess) e = launch_graphs(L.block, L.rpt, L.grid, L.lds, st, L.a);
-    if (e == hipSuccess && ev) e = hipEventRecord(ev[L.cls + 1], st);
+    if (e == hipSuccess && ev) e = hipEventRecord(ev[2 * L.cls + 1], st);
   }
   return e;
 }
@@ -646,9 +646,9 @@ static cpaa_status capture_run(cpaa_plan_s* pl, GraphState* gs, const double* p,
 // Any workgroup size gives a certified result for every graph.
 static cpaa_status tune_blocks(cpaa_plan_s* pl, GraphState* gs, const double* p, double tol,
                                double* x, hipStream_t st) {
-  hipEvent_t ev[kGraphClasses + 1] = {};
+  hipEvent_t ev[2 * kGraphClasses] = {};
   hipError_t e = hipSuccess;
-  for (int k = 0; k <= kGraphClasses && e == hipSuccess; ++k) e = hipEventCreate(&ev[k]);
+  for (int k = 0; k < 2 * kGraphClasses && e == hipSuccess; ++k) e = hipEventCreate(&ev[k]);
   float best[kGraphClasses];
   for (int k = 0; k < kGraphClasses; ++k) {
     best[k] = 1e30f;
@@ -673,14 +673,14 @@ static cpaa_status tune_blocks(cpaa_plan_s* pl, GraphState* gs, const double* p,
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     for (const ClassLaunch& L : launches) {
       float ms = 0.f;
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[L.cls], ev[L.cls + 1]);
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[2 * L.cls], ev[2 * L.cls + 1]);
       if (e == hipSuccess && ms < best[L.cls]) {
         best[L.cls] = ms;
         gs->block[L.cls] = b;
       }
     }
   }
-  for (int k = 0; k <= kGraphClasses; ++k)
+  for (int k = 0; k < 2 * kGraphClasses; ++k)
     if (ev[k]) (void)hipEventDestroy(ev[k]);
   CPAA_HIP(e);
   return s;
