@@ -16,8 +16,11 @@
 //     evaluates the in-loop certificate and stops that graph on its own;
 //   * the FP64 residual (with its rounding allowance) and, if needed,
 //     correction series run in the same workgroup, then D acc is written out.
-// The host captures "reset queues -> validate p -> persistent solves" once in
-// a HIP graph per (p, x, tol) and replays it.
+// Graphs are split into size classes by vertex count; each class is one
+// persistent launch with the LDS of its largest graph and its own workgroup
+// size (timed per class on the first call when autotuning).  The host captures
+// "reset queues -> validate p -> one launch per class" once in a HIP graph per
+// (p, x, tol) and replays it.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
