@@ -549,7 +549,8 @@ def bench_directed(args):
 def bench_graph_batch(args):
     """10,000 independent Chung-Lu graphs (n log-uniform in [100, 5000], average
     degree 4-32, exponent 2.1-3.0, seed 2112003), one random source each, solved
-    by one persistent HIP-graph launch per step (autotuned workgroup size)."""
+    by one HIP-graph replay per step: one persistent launch per size class, each
+    with the workgroup size the first call's autotuner kept for it."""
     import torch
     import graphgen as gg
     from paper_2112_01743_amd import Plan
